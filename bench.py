@@ -1,0 +1,233 @@
+#!/usr/bin/env python3
+"""Throughput of the fused relax-and-transport step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-variants] [--no-cpu]
+
+Workload (the headline line): 2D vectorial D2Q5, 4096 x 4096 periodic grid on
+[0, 2pi)^2, nu = 1e-3, mu = dx^2/dt = 8, seeded divergence-free random field
+(|k|^-3 amplitudes, 1 <= |k| <= 16) scaled to Mach dx*max|u| = 0.05, FP32
+storage and arithmetic, 2000 steps.  Inputs are resident in HBM before the
+timed region; one step is one launch of the fused kernel over the grid.
+
+Printed: one JSON line on stdout with MLUPS, the HBM roofline of the step
+kernel (algorithmic bytes / measured average launch time, against the 8 TB/s
+published peak and against the measured copy-probe bandwidth), and the FP64
+CPU oracle timed on a bounded sample of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0                 # MI355X published HBM3E bandwidth
+METRIC = "MLUPS & % HBM peak; fp16-store / learned closure vs plain fp32 at fixed error"
+BYTES_PER_LUP = {("f32", 2): 120, ("f16_dev", 2): 60, ("bf16_dev", 2): 60, ("f16_dev_r32", 2): 72,
+                 ("bf16_dev_r32", 2): 72, ("f32_raw", 2): 120, ("f32", 3): 224, ("f16_dev", 3): 112, ("bf16_dev", 3): 112,
+                 ("f16_dev_r32", 3): 128, ("bf16_dev_r32", 3): 128}
+KERNEL_SOURCES = ("paper_2607_24059_amd/csrc/lbm_kernels.hip", "paper_2607_24059_amd/csrc/lbm_device.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step2d_f32_4096_traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def make_workload(n: int, dim: int, nu: float, seed: int = 0, mach: float = 0.05):
+    import inputs
+    from paper_2607_24059_amd import lbm
+    dx = 2 * math.pi / n
+    dt = dx * dx / 8.0
+    if dim == 2:
+        u0 = inputs.random_field_2d(n, seed, umax=mach / dx)
+    else:
+        u0 = inputs.random_field_3d(n, seed, umax=mach / dx)
+    return u0, dx, dt, lbm
+
+
+def time_engine(n, dim, storage, steps, warmup, nu=1e-3, u0=None):
+    """Run `warmup` untimed steps then `steps` timed steps; returns (ms per step, engine)."""
+    import torch
+    from paper_2607_24059_amd import lbm
+    dx = 2 * math.pi / n
+    dt = dx * dx / 8.0
+    if u0 is None:
+        u0, *_ = make_workload(n, dim, nu)
+    grid = (n,) * dim
+    prm = lbm.make_params(dim, grid, dx, dt, nu, storage=storage)
+    eng = lbm.Engine.create(prm, u0)
+    eng.step(warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(eng.stream)
+    eng.step(steps)
+    ev1.record(eng.stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / max(steps, 1)
+    return ms, eng
+
+
+def copy_probe_gbs(nbytes: int = 1 << 30, reps: int = 20) -> float:
+    """Read + write bandwidth of the library's copy kernel on a 1 GiB buffer."""
+    import torch
+    from paper_2607_24059_amd import lbm
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    s = torch.cuda.current_stream()
+    for _ in range(3):
+        lbm.lbm_copy_probe(dst.data_ptr(), src.data_ptr(), nbytes, s.cuda_stream)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(s)
+    for _ in range(reps):
+        lbm.lbm_copy_probe(dst.data_ptr(), src.data_ptr(), nbytes, s.cuda_stream)
+    ev1.record(s)
+    torch.cuda.synchronize()
+    sec = ev0.elapsed_time(ev1) / 1e3 / reps
+    del src, dst
+    return 2 * nbytes / sec / 1e9
+
+
+def cpu_baseline(n: int = 4096, steps: int = 3, nu: float = 1e-3) -> dict:
+    """The FP64 numpy oracle on `steps` steps of the same 4096^2 workload."""
+    from oracle import scheme
+    u0, dx, dt, _ = make_workload(n, 2, nu)
+    p = scheme.Params(dim=2, dx=dx, dt=dt, nu=nu)
+    f = scheme.init(np.ones((n, n)), u0, p)
+    f = scheme.step(f, p)  # warm-up
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        f = scheme.step(f, p)
+    sec = time.perf_counter() - t0
+    return {"value": n * n * steps / sec / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"numpy FP64 oracle, {n}x{n} k^-3 field, {steps} steps after 1 warm-up step "
+                      f"({sec:.1f} s); numpy element-wise kernels run on one thread"}
+
+
+def traffic_entry(per_launch_algo_bytes: float):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was
+    taken on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--variant-steps", type=int, default=200)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU slab decomposition is a design, not a build).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+
+    n = args.n
+    log(f"[bench] generating {n}^2 workload")
+    u0, dx, dt, lbm = make_workload(n, 2, 1e-3)
+    log("[bench] copy probe")
+    probe = copy_probe_gbs()
+    log(f"[bench] probe {probe:.0f} GB/s; timing {args.steps} steps after {args.warmup} warm-up")
+    ms, eng = time_engine(n, 2, "f32", args.steps, args.warmup, u0=u0)
+    d = eng.diagnostics()
+    eng.close()
+    del eng
+    cells = n * n
+    mlups = cells / (ms * 1e-3) / 1e6
+    algo = BYTES_PER_LUP[("f32", 2)] * cells
+    achieved = algo / (ms * 1e-3) / 1e9
+    result = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"vectorial D2Q5, {n}x{n} periodic, nu=1e-3, mu=8, k^-3 random "
+                               "field at Mach 0.05, FP32 storage+math, fused step",
+                   "grid": [n, n], "storage": "f32", "nu": 1e-3, "mu": 8.0,
+                   "omega_rho": 1.2, "omega_q": 1.15, "alpha_rho": 0.075},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": traffic_entry(algo), "bytes_per_launch_algorithmic": algo,
+                     "kernel": "k_step<2,float,float>",
+                     "probe_gbs": round(probe, 1), "frac_of_probe": round(achieved / probe, 4)},
+        "health": {"nonfinite": d["nonfinite"], "mass": d["mass"], "kinetic": d["kinetic"]},
+    }
+
+    if not args.no_variants:
+        variants = {}
+        vs = args.variant_steps
+        for storage in ("f16_dev", "bf16_dev", "f16_dev_r32"):
+            log(f"[bench] variant 2D {storage}")
+            ms_v, e = time_engine(n, 2, storage, vs, 10, u0=u0)
+            e.close()
+            variants[f"2d_{n}_{storage}"] = _variant(cells, ms_v, BYTES_PER_LUP[(storage, 2)], probe)
+        del u0
+        n3 = 256
+        u3, *_ = make_workload(n3, 3, 1e-3)
+        for storage in ("f32", "f16_dev", "f16_dev_r32"):
+            log(f"[bench] variant 3D {storage}")
+            ms_v, e = time_engine(n3, 3, storage, vs, 10, u0=u3)
+            e.close()
+            variants[f"3d_{n3}_{storage}"] = _variant(n3 ** 3, ms_v, BYTES_PER_LUP[(storage, 3)], probe)
+        result["variants"] = variants
+
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline")
+        result["cpu_baseline"] = cpu_baseline(n)
+    print(json.dumps(result), flush=True)
+
+
+def _variant(cells, ms, bytes_per_lup, probe):
+    gbs = bytes_per_lup * cells / (ms * 1e-3) / 1e9
+    return {"MLUPS": round(cells / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 5),
+            "GBs": round(gbs, 1), "frac_peak": round(gbs / PEAK_HBM_GBS, 4),
+            "frac_probe": round(gbs / probe, 4)}
+
+
+if __name__ == "__main__":
+    main()

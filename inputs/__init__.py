@@ -14,6 +14,7 @@ from .fields import (  # noqa: F401
     abc_pressure,
     random_field_2d,
     random_field_3d,
+    random_field_box,
     well_prepared_density,
     batch_run_specs,
 )

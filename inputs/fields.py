@@ -202,6 +202,52 @@ def random_field_3d(n: int, seed: int, umax: float = 1.0, kmax: int = 16,
     return u * scale
 
 
+def random_field_box(shape, dx: float, seed: int, umax: float = 1.0, mmax: int = 3) -> np.ndarray:
+    """Smooth divergence-free field on a periodic box of any shape.
+
+    shape = (ny, nx) or (nz, ny, nx) cells of spacing dx, so the box sides are
+    L_a = n_a dx.  Modes exp(i k . x) with k_a = 2 pi m_a / L_a for integer
+    m in [-mmax, mmax]^d, 1 <= |m| <= mmax, coefficients (a + ib)/|m|^3 from
+    default_rng(seed); 2D: u = (d_y psi, -d_x psi); 3D: u = curl A.  Scaled so
+    that max |u| over the grid equals umax.  Returns (d, *shape).
+    """
+    dim = len(shape)
+    ncomp = 1 if dim == 2 else 3
+    coef, m1 = _coeffs(seed, mmax, dim, ncomp)
+    sizes = list(reversed(shape))                        # (nx, ny[, nz])
+    # e[a][m, i] = exp(i k_a(m) x_i), axis a = 0 is x
+    e = []
+    kv = []
+    for a in range(dim):
+        L = sizes[a] * dx
+        k = 2 * math.pi * m1 / L
+        x = (np.arange(sizes[a]) + 0.5) * dx
+        e.append(np.exp(1j * np.outer(k, x)))
+        kv.append(k)
+
+    def synth(c):                                        # c indexed [.., ky, kx] -> real field
+        if dim == 2:
+            return np.real(e[1].T @ c @ e[0])
+        g = np.tensordot(c, e[0], axes=([2], [0]))       # [kz, ky, x]
+        g = np.tensordot(g, e[1], axes=([1], [0]))       # [kz, x, y]
+        g = np.transpose(g, (0, 2, 1))                   # [kz, y, x]
+        return np.real(np.tensordot(e[2], g, axes=([0], [0])))
+
+    if dim == 2:
+        ky = kv[1][:, None]
+        kx = kv[0][None, :]
+        psi = coef[0]
+        u = np.stack([synth(1j * ky * psi), synth(-1j * kx * psi)])
+    else:
+        kz = kv[2][:, None, None]
+        ky = kv[1][None, :, None]
+        kx = kv[0][None, None, :]
+        ax, ay, az = coef
+        u = np.stack([synth(1j * (ky * az - kz * ay)), synth(1j * (kz * ax - kx * az)),
+                      synth(1j * (kx * ay - ky * ax))])
+    return u * (umax / float(np.sqrt(np.max(np.sum(u * u, axis=0)))))
+
+
 # --------------------------------------------------------------------------- #
 # The batch workload: many independent runs of uneven size and viscosity      #
 # --------------------------------------------------------------------------- #

@@ -1,0 +1,9 @@
+"""MI355X-native engine for the vectorial lattice Boltzmann scheme.
+
+The compute path is the HIP library liblbm.so (csrc/, C ABI in include/lbm.h);
+`lbm` is its ctypes binding.  torch supplies device memory and streams only.
+"""
+
+from . import lbm  # noqa: F401
+
+__all__ = ["lbm"]

@@ -1,0 +1,275 @@
+// C ABI of the single-run engine (see include/lbm.h for the contract).
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "lbm.h"
+#include "lbm_internal.hpp"
+
+using lbm::Geometry;
+using lbm::Ops;
+using lbm::RunCoef;
+
+struct lbm_ctx {
+  lbm_params p;
+  double mu;
+  double alpha_q;
+  uint32_t flags;
+  Geometry g;
+  const Ops* ops;
+  RunCoef coef;
+  char* ws;
+  size_t ws_bytes;
+  char* cur;        // buffer holding the state at step `steps`
+  char* nxt;        // the other buffer (also used as staging between steps)
+  double* partials; // diagnostics per-block partials
+  double* result;   // diagnostics final slots
+  int64_t diag_blocks;
+  hipStream_t stream;
+  int64_t steps;
+  int bx, by;       // step kernel block shape
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kDiagSlots = 16;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+lbm_status check(const lbm_params* p, double* mu, double* alpha_q, uint32_t* flags) {
+  if (!p) return LBM_EINVAL;
+  if (p->dim != 2 && p->dim != 3) return LBM_EINVAL;
+  size_t re, me;
+  if (!lbm::storage_elems(p->storage, &re, &me)) return LBM_EINVAL;
+  for (int a = 0; a < 3; ++a) {
+    if (p->n[a] < 1 || p->n[a] > (int64_t(1) << 30)) return LBM_EINVAL;
+  }
+  if (p->dim == 2 && p->n[2] != 1) return LBM_EINVAL;
+  const int64_t cells = p->n[0] * p->n[1] * p->n[2];
+  if (cells > (int64_t(1) << 31) - 1) return LBM_EINVAL;
+  if (p->dim == 3 && p->n[2] > 65535) return LBM_EINVAL;
+  if (!(p->dx > 0.0) || !(p->dt > 0.0) || !isfinite(p->dx) || !isfinite(p->dt)) return LBM_EINVAL;
+  if (!(p->nu >= 0.0) || !isfinite(p->nu)) return LBM_EINVAL;
+  if (p->gamma != 1.0) return LBM_EINVAL;
+  if (!(p->rho_ref > 0.0) || !isfinite(p->rho_ref)) return LBM_EINVAL;
+  // omega in (0, 2): omega = 2 is inviscid (Section 3); Lemma 1 gives stability
+  // of the checkerboard mode only for omega in [0, 2] and alpha in [0, 1/(2 dim)].
+  if (!(p->omega_rho > 0.0 && p->omega_rho < 2.0)) return LBM_EUNSTABLE;
+  if (!(p->omega_q > 0.0 && p->omega_q < 2.0)) return LBM_EUNSTABLE;
+  const double m = p->dx * p->dx / p->dt;
+  const double aq = p->nu / (2.0 * m * (1.0 / p->omega_q - 0.5));
+  const double amax = 1.0 / (2.0 * p->dim);
+  if (!(p->alpha_rho >= 0.0 && p->alpha_rho <= amax)) return LBM_EUNSTABLE;
+  if (!(aq >= 0.0 && aq <= amax)) return LBM_EUNSTABLE;
+  uint32_t fl = 0;
+  if (m * m * (p->alpha_rho + aq) < 1.0) fl |= LBM_WARN_LOWFREQ;
+  if (mu) *mu = m;
+  if (alpha_q) *alpha_q = aq;
+  if (flags) *flags = fl;
+  return LBM_OK;
+}
+
+Geometry geometry(const lbm_params* p) {
+  Geometry g;
+  g.dim = p->dim;
+  g.nx = static_cast<int32_t>(p->n[0]);
+  g.ny = static_cast<int32_t>(p->n[1]);
+  g.nz = static_cast<int32_t>(p->n[2]);
+  g.cells = p->n[0] * p->n[1] * p->n[2];
+  g.stride = (g.cells + 255) / 256 * 256;
+  lbm::storage_elems(p->storage, &g.rest_elem, &g.move_elem);
+  const int ns = p->dim + 1;
+  g.rest_bytes = align_up(static_cast<size_t>(ns) * g.stride * g.rest_elem);
+  g.buf_bytes = align_up(g.rest_bytes + static_cast<size_t>(ns) * 2 * p->dim * g.stride * g.move_elem);
+  return g;
+}
+
+// staging (FP64 moments or initial fields) lives in the idle buffer
+size_t staging_bytes(const Geometry& g) { return static_cast<size_t>(g.dim + 1) * g.cells * sizeof(double); }
+
+lbm_status dev(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EDEVICE; }
+
+void default_block(const Geometry& g, int* bx, int* by) {
+  int x = 256;
+  while (x > 64 && x / 2 >= g.nx) x /= 2;
+  *bx = x;
+  *by = 256 / x;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_check_params(const lbm_params* p, double* mu, double* alpha_q, uint32_t* flags) {
+  return check(p, mu, alpha_q, flags);
+}
+
+size_t lbm_workspace_bytes(const lbm_params* p) {
+  if (check(p, nullptr, nullptr, nullptr) != LBM_OK) return 0;
+  const Geometry g = geometry(p);
+  const Ops* o = lbm::ops_for(p->dim, p->storage);
+  if (!o) return 0;
+  const size_t scratch = align_up(static_cast<size_t>(o->diag_blocks(g) + 1) * kDiagSlots * sizeof(double));
+  return 2 * g.buf_bytes + scratch;
+}
+
+lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const double* rho0,
+                    void* workspace, size_t ws_bytes, void* hip_stream) {
+  if (!out || !p || !u0 || !workspace) return LBM_EINVAL;
+  *out = nullptr;
+  double mu = 0, aq = 0;
+  uint32_t flags = 0;
+  lbm_status st = check(p, &mu, &aq, &flags);
+  if (st != LBM_OK) return st;
+  const size_t need = lbm_workspace_bytes(p);
+  if (ws_bytes < need) return LBM_ENOMEM;
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0) return LBM_EINVAL;
+  const Geometry g = geometry(p);
+  if (staging_bytes(g) > g.buf_bytes) return LBM_ENOMEM;
+
+  lbm_ctx* c = new (std::nothrow) lbm_ctx;
+  if (!c) return LBM_ENOMEM;
+  c->p = *p;
+  c->mu = mu;
+  c->alpha_q = aq;
+  c->flags = flags;
+  c->g = g;
+  c->ops = lbm::ops_for(p->dim, p->storage);
+  c->coef = RunCoef{p->dx, mu, p->alpha_rho, aq, p->omega_rho, p->omega_q, p->rho_ref};
+  c->ws = static_cast<char*>(workspace);
+  c->ws_bytes = ws_bytes;
+  c->cur = c->ws;
+  c->nxt = c->ws + g.buf_bytes;
+  c->partials = reinterpret_cast<double*>(c->ws + 2 * g.buf_bytes);
+  c->diag_blocks = c->ops->diag_blocks(g);
+  c->result = c->partials + c->diag_blocks * kDiagSlots;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->steps = 0;
+  default_block(g, &c->bx, &c->by);
+
+  // stage u0 (and rho0) as FP64 in the idle buffer, then build the equilibrium
+  double* su = reinterpret_cast<double*>(c->nxt);
+  double* sr = rho0 ? su + static_cast<size_t>(g.dim) * g.cells : nullptr;
+  hipError_t e = hipMemcpyAsync(su, u0, static_cast<size_t>(g.dim) * g.cells * sizeof(double),
+                                hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess && rho0)
+    e = hipMemcpyAsync(sr, rho0, static_cast<size_t>(g.cells) * sizeof(double), hipMemcpyHostToDevice,
+                       c->stream);
+  if (e == hipSuccess) e = c->ops->init(g, c->coef, su, sr, c->cur, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    delete c;
+    return LBM_EDEVICE;
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
+  if (!c || nsteps < 0) return LBM_EINVAL;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    hipError_t e = c->ops->step(c->g, c->coef, c->cur, c->nxt, c->bx, c->by, c->stream);
+    if (e != hipSuccess) return LBM_EDEVICE;
+    char* t = c->cur;
+    c->cur = c->nxt;
+    c->nxt = t;
+    c->steps += 1;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_moments(lbm_ctx* c, double* rho, double* q) {
+  if (!c || !rho) return LBM_EINVAL;
+  double* st = reinterpret_cast<double*>(c->nxt);
+  const size_t plane = static_cast<size_t>(c->g.cells) * sizeof(double);
+  hipError_t e = c->ops->moments(c->g, c->coef, c->cur, st, nullptr, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(rho, st, plane, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess && q)
+    e = hipMemcpyAsync(q, st + c->g.cells, plane * c->g.dim, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  return dev(e);
+}
+
+lbm_status lbm_moments_device(lbm_ctx* c, float* out) {
+  if (!c || !out) return LBM_EINVAL;
+  return dev(c->ops->moments(c->g, c->coef, c->cur, nullptr, out, c->stream));
+}
+
+lbm_status lbm_diagnostics(lbm_ctx* c, lbm_diag* out) {
+  if (!c || !out) return LBM_EINVAL;
+  double r[kDiagSlots];
+  hipError_t e = c->ops->diag(c->g, c->coef, c->cur, c->partials, c->result, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(r, c->result, sizeof(r), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return LBM_EDEVICE;
+  const double dv = pow(c->p.dx, c->p.dim);
+  memset(out, 0, sizeof(*out));
+  out->step = c->steps;
+  out->time = static_cast<double>(c->steps) * c->p.dt;
+  out->mass = dv * r[0];
+  for (int j = 0; j < c->p.dim; ++j) out->mom[j] = dv * r[1 + j];
+  out->kinetic = 0.5 * dv * r[4];
+  out->enstrophy = 0.5 * dv * r[5];
+  out->div_l2 = sqrt(dv * r[6]);
+  out->max_u = sqrt(r[7]);
+  out->rho_min = r[8];
+  out->rho_max = r[9];
+  out->nonfinite = static_cast<int64_t>(r[10]);
+  out->flags = c->flags;
+  return out->nonfinite > 0 ? LBM_ENONFINITE : LBM_OK;
+}
+
+size_t lbm_state_bytes(const lbm_ctx* c) {
+  if (!c) return 0;
+  return c->g.buf_bytes + sizeof(int64_t);
+}
+
+lbm_status lbm_save_state(lbm_ctx* c, void* host, size_t bytes) {
+  if (!c || !host) return LBM_EINVAL;
+  if (bytes != lbm_state_bytes(c)) return LBM_ESTATE;
+  hipError_t e = hipMemcpyAsync(host, c->cur, c->g.buf_bytes, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return LBM_EDEVICE;
+  memcpy(static_cast<char*>(host) + c->g.buf_bytes, &c->steps, sizeof(int64_t));
+  return LBM_OK;
+}
+
+lbm_status lbm_load_state(lbm_ctx* c, const void* host, size_t bytes) {
+  if (!c || !host) return LBM_EINVAL;
+  if (bytes != lbm_state_bytes(c)) return LBM_ESTATE;
+  hipError_t e = hipMemcpyAsync(c->cur, host, c->g.buf_bytes, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return LBM_EDEVICE;
+  memcpy(&c->steps, static_cast<const char*>(host) + c->g.buf_bytes, sizeof(int64_t));
+  return LBM_OK;
+}
+
+int64_t lbm_step_count(const lbm_ctx* c) { return c ? c->steps : -1; }
+
+void lbm_destroy(lbm_ctx* c) { delete c; }
+
+const char* lbm_strerror(lbm_status s) {
+  switch (s) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_EUNSTABLE: return "parameters outside the stability region (omega in (0,2), alpha in [0,1/(2d)])";
+    case LBM_ENOMEM: return "workspace too small";
+    case LBM_EDEVICE: return "HIP runtime error";
+    case LBM_ENONFINITE: return "non-finite populations";
+    case LBM_ESTATE: return "state blob size or layout mismatch";
+  }
+  return "unknown status";
+}
+
+lbm_status lbm_copy_probe(void* dst, const void* src, size_t bytes, void* hip_stream) {
+  if (!dst || !src || bytes % 16 != 0) return LBM_EINVAL;
+  if (reinterpret_cast<uintptr_t>(dst) % 16 || reinterpret_cast<uintptr_t>(src) % 16) return LBM_EINVAL;
+  return dev(lbm::launch_copy(dst, src, bytes, static_cast<hipStream_t>(hip_stream)));
+}
+
+}  // extern "C"

@@ -1,0 +1,150 @@
+// Device-side building blocks of the vectorial lattice Boltzmann engine (gfx950).
+//
+// Units.  Every stored population is in the scaled units of the paper's moment
+// definition (Section 2): the moments are W = sum_l f_l = (rho, dx q_x, dx q_y
+// [, dx q_z]).  Dividing the equilibria of Section 2 through by the powers of dx
+// they carry leaves a form that depends on W, mu = dx^2/dt and the alphas only:
+//
+//   F_{rho j} = W_j,      F_{i j} = W_i W_j / W_rho + delta_ij P(W_rho)
+//   f^eq_{i,rest} = (1 - 2 D alpha_i) W_i
+//   f^eq_{i,+-j}  = alpha_i W_i +- F_{ij} / (2 mu)
+//
+// (for example dx alpha q_x = alpha W_x and dx^2/(2 mu) q_x^2/rho = W_x^2/(2 mu W_rho)).
+// The rest component of each momentum set carries the factor dx that makes
+// the equilibria sum to W, the reading under which Lemma 1 holds.
+//
+// Deviation storage.  With a reference density rho_ref, the populations can be
+// stored as g = f - fbar where fbar = f^eq(rho_ref, 0):
+//   density set  fbar_rest = (1 - 2D alpha_rho) rho_ref, fbar_{+-j} = alpha_rho rho_ref
+//   set q_i      fbar_{+-i} = +- rho_ref / (2 mu), every other entry 0.
+// Since sum_l fbar_{rho,l} = rho_ref and sum_l fbar_{q_i,l} = 0, the sums of g
+// are (W_rho - rho_ref, W_q), and for P(rho) = rho the deviation of the
+// equilibrium, f^eq(W) - fbar, is the same formula with W_rho replaced by its
+// deviation in every linear term and only 1/W_rho using rho_ref + deviation.
+// So one collision routine serves both forms: rho_ref = 0 is the plain scheme.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// ----------------------------------------------------------------------------
+// storage element types
+// ----------------------------------------------------------------------------
+struct bf16 {
+  uint16_t bits;
+};
+
+__device__ __forceinline__ float load_f32(const float* p) { return *p; }
+__device__ __forceinline__ float load_f32(const _Float16* p) { return static_cast<float>(*p); }
+__device__ __forceinline__ float load_f32(const bf16* p) {
+  return __uint_as_float(static_cast<uint32_t>(p->bits) << 16);
+}
+
+__device__ __forceinline__ void store_f32(float* p, float v) { *p = v; }
+__device__ __forceinline__ void store_f32(_Float16* p, float v) {
+  *p = static_cast<_Float16>(v);  // round to nearest even
+}
+__device__ __forceinline__ void store_f32(bf16* p, float v) {
+  uint32_t u = __float_as_uint(v);
+  uint16_t out;
+  if ((u & 0x7fffffffu) > 0x7f800000u) {
+    out = static_cast<uint16_t>((u >> 16) | 0x40u);  // keep NaN a (quiet) NaN
+  } else {
+    u += 0x7fffu + ((u >> 16) & 1u);                 // round to nearest even
+    out = static_cast<uint16_t>(u >> 16);
+  }
+  p->bits = out;
+}
+
+// ----------------------------------------------------------------------------
+// lattice description: D2Q5 / D3Q7 per set, D+1 sets
+//   velocity l: 0 = rest, 1 + 2j = +e_j, 2 + 2j = -e_j   (j = 0 is x)
+//   set i:      0 = rho, 1 + j = q_j
+// plane layout in HBM (SoA, x fastest):
+//   rest planes  [set][cells]           element type TR
+//   moving planes[set][2D][cells]       element type TM, velocity order 1..2D
+// ----------------------------------------------------------------------------
+template <int D>
+struct Lattice {
+  static constexpr int NS = D + 1;      // sets
+  static constexpr int NV = 2 * D + 1;  // velocities per set
+  static constexpr int NM = 2 * D;      // moving velocities per set
+};
+
+template <typename R>
+struct CoefT {
+  R c;         // 1 / (2 mu)
+  R a_rho;     // alpha_rho
+  R a_q;       // alpha_q
+  R d2a_rho;   // 2 D alpha_rho
+  R d2a_q;     // 2 D alpha_q
+  R w_rho;     // omega_rho
+  R w_q;       // omega_q
+  R ref;       // rho_ref for deviation storage, 0 for plain storage
+};
+using Coef = CoefT<float>;
+
+// Equilibrium (or its deviation from fbar) of one cell in scaled units.
+// W[0] is W_rho for plain storage or W_rho - rho_ref for deviations; W[1+j]
+// is W_{q_j}; inv = 1 / W_rho (always the full density).
+template <int D, typename R>
+__device__ __forceinline__ void equilibrium(const R (&W)[D + 1], R inv, const CoefT<R>& k,
+                                            R (&eq)[D + 1][2 * D + 1]) {
+  const R wl = W[0];
+  // density set: F_{rho j} = W_j.  The rest entry (1 - 2D alpha) W is formed
+  // as W - (2D alpha) W: rounding the coefficient 1 - 2D alpha itself would
+  // break the exact sum of the equilibria by up to half an ulp of W per step,
+  // a bias that accumulates; the product (2D alpha) W is small, so its
+  // rounding error is negligible.
+  eq[0][0] = wl - k.d2a_rho * wl;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    const R base = k.a_rho * wl;
+    const R flux = k.c * W[1 + j];
+    eq[0][1 + 2 * j] = base + flux;
+    eq[0][2 + 2 * j] = base - flux;
+  }
+  // momentum sets: F_{ij} = W_i W_j / W_rho + delta_ij P(W_rho), P(rho) = rho
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const R wi = W[1 + i];
+    eq[1 + i][0] = wi - k.d2a_q * wi;
+    const R base = k.a_q * wi;
+    const R wi_inv = wi * inv;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      R F = wi_inv * W[1 + j];
+      if (i == j) F = F + wl;
+      const R flux = k.c * F;
+      eq[1 + i][1 + 2 * j] = base + flux;
+      eq[1 + i][2 + 2 * j] = base - flux;
+    }
+  }
+}
+
+// Relax the populations of one cell in place: f* = f + omega (f^eq - f),
+// equation (LBM_scheme).  g[i][l] holds plain values (ref = 0) or deviations.
+template <int D>
+__device__ __forceinline__ void collide(float (&g)[D + 1][2 * D + 1], const Coef& k) {
+  float W[D + 1];
+#pragma unroll
+  for (int i = 0; i < D + 1; ++i) {
+    float s = g[i][0];
+#pragma unroll
+    for (int l = 1; l < 2 * D + 1; ++l) s = s + g[i][l];
+    W[i] = s;
+  }
+  const float inv = 1.0f / (W[0] + k.ref);
+  float eq[D + 1][2 * D + 1];
+  equilibrium<D, float>(W, inv, k, eq);
+#pragma unroll
+  for (int i = 0; i < D + 1; ++i) {
+    const float w = (i == 0) ? k.w_rho : k.w_q;
+#pragma unroll
+    for (int l = 0; l < 2 * D + 1; ++l) g[i][l] = __builtin_fmaf(w, eq[i][l] - g[i][l], g[i][l]);
+  }
+}
+
+}  // namespace lbm

@@ -1,0 +1,436 @@
+// Kernels of the single-run engine: initialisation, the fused
+// relax-and-transport step, moments, FP64 diagnostics and the copy probe.
+//
+// Every kernel is templated on the dimension D and on the element types of
+// the rest (TR) and moving (TM) planes; plain FP32 storage and the deviation
+// storages run the same code (see lbm_device.hpp).
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+
+#include "lbm_device.hpp"
+#include "lbm_internal.hpp"
+
+namespace lbm {
+namespace {
+
+template <typename R>
+CoefT<R> make_coef(const RunCoef& r, int D, bool deviation) {
+  CoefT<R> k;
+  k.c = static_cast<R>(1.0 / (2.0 * r.mu));
+  k.a_rho = static_cast<R>(r.alpha_rho);
+  k.a_q = static_cast<R>(r.alpha_q);
+  k.d2a_rho = static_cast<R>(2.0 * D * r.alpha_rho);
+  k.d2a_q = static_cast<R>(2.0 * D * r.alpha_q);
+  k.w_rho = static_cast<R>(r.omega_rho);
+  k.w_q = static_cast<R>(r.omega_q);
+  k.ref = static_cast<R>(deviation ? r.ref : 0.0);
+  return k;
+}
+
+template <typename TR, typename TM>
+struct PlaneSet {
+  TR* rest;  // [D+1][stride]
+  TM* move;  // [D+1][2D][stride]
+};
+
+template <typename TR, typename TM>
+__host__ __device__ inline PlaneSet<TR, TM> planes_of(void* base, size_t rest_bytes) {
+  PlaneSet<TR, TM> p;
+  p.rest = reinterpret_cast<TR*>(base);
+  p.move = reinterpret_cast<TM*>(reinterpret_cast<char*>(base) + rest_bytes);
+  return p;
+}
+
+// ----------------------------------------------------------------------------
+// init: every population at the equilibrium of W0 = (rho0, dx rho0 u0)
+// ----------------------------------------------------------------------------
+template <int D, typename TR, typename TM>
+__global__ __launch_bounds__(256) void k_init(const double* __restrict__ u0,
+                                              const double* __restrict__ rho0, double rho_ref,
+                                              double dx, TR* __restrict__ rest,
+                                              TM* __restrict__ move, int64_t cells,
+                                              int64_t stride, CoefT<double> k) {
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= cells) return;
+  const double rho = rho0 ? rho0[c] : rho_ref;
+  double W[D + 1];
+  W[0] = rho - k.ref;  // deviation when k.ref = rho_ref, plain when 0
+#pragma unroll
+  for (int j = 0; j < D; ++j) W[1 + j] = dx * rho * u0[j * cells + c];
+  double eq[D + 1][2 * D + 1];
+  equilibrium<D, double>(W, 1.0 / rho, k, eq);
+#pragma unroll
+  for (int i = 0; i < D + 1; ++i) {
+    store_f32(rest + i * stride + c, static_cast<float>(eq[i][0]));
+#pragma unroll
+    for (int m = 0; m < 2 * D; ++m)
+      store_f32(move + (i * 2 * D + m) * stride + c, static_cast<float>(eq[i][1 + m]));
+  }
+}
+
+// ----------------------------------------------------------------------------
+// step: pull transport fused with relaxation.
+//   f_{+e_j}(t+dt, x) = f*_{+e_j}(t, x - dx e_j): the post-relaxation state is
+//   what is stored, so a cell gathers the stored values of its upwind
+//   neighbours, sums the moments, relaxes and writes its own cell.  Each
+//   stored value is read exactly once per step and written exactly once.
+// ----------------------------------------------------------------------------
+template <int D, typename TR, typename TM>
+__global__ __launch_bounds__(256) void k_step(const TR* __restrict__ sr,
+                                              const TM* __restrict__ sm, TR* __restrict__ dr,
+                                              TM* __restrict__ dm, int nx, int ny, int nz,
+                                              int64_t stride, Coef k) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= nx || y >= ny) return;
+  const int64_t plane = static_cast<int64_t>(nx) * ny;
+  const int64_t c = static_cast<int64_t>(z) * plane + static_cast<int64_t>(y) * nx + x;
+  int64_t src[2 * D];
+  src[0] = (x == 0) ? c + (nx - 1) : c - 1;                                   // +x from x-1
+  src[1] = (x == nx - 1) ? c - (nx - 1) : c + 1;                              // -x from x+1
+  src[2] = (y == 0) ? c + static_cast<int64_t>(ny - 1) * nx : c - nx;         // +y from y-1
+  src[3] = (y == ny - 1) ? c - static_cast<int64_t>(ny - 1) * nx : c + nx;    // -y from y+1
+  if constexpr (D == 3) {
+    src[4] = (z == 0) ? c + static_cast<int64_t>(nz - 1) * plane : c - plane;      // +z
+    src[5] = (z == nz - 1) ? c - static_cast<int64_t>(nz - 1) * plane : c + plane; // -z
+  }
+  float g[D + 1][2 * D + 1];
+#pragma unroll
+  for (int i = 0; i < D + 1; ++i) {
+    g[i][0] = load_f32(sr + i * stride + c);
+#pragma unroll
+    for (int m = 0; m < 2 * D; ++m) g[i][1 + m] = load_f32(sm + (i * 2 * D + m) * stride + src[m]);
+  }
+  collide<D>(g, k);
+#pragma unroll
+  for (int i = 0; i < D + 1; ++i) {
+    store_f32(dr + i * stride + c, g[i][0]);
+#pragma unroll
+    for (int m = 0; m < 2 * D; ++m) store_f32(dm + (i * 2 * D + m) * stride + c, g[i][1 + m]);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// moments: rho = ref + sum_l g_rho,l and q_j = (sum_l g_qj,l) / dx, in FP64
+// ----------------------------------------------------------------------------
+template <int D, typename TR, typename TM>
+__device__ __forceinline__ void cell_sums(const TR* __restrict__ r, const TM* __restrict__ m,
+                                          int64_t c, int64_t stride, double (&s)[D + 1]) {
+#pragma unroll
+  for (int i = 0; i < D + 1; ++i) {
+    double a = static_cast<double>(load_f32(r + i * stride + c));
+#pragma unroll
+    for (int v = 0; v < 2 * D; ++v) a += static_cast<double>(load_f32(m + (i * 2 * D + v) * stride + c));
+    s[i] = a;
+  }
+}
+
+template <int D, typename TR, typename TM>
+__global__ __launch_bounds__(256) void k_moments(const TR* __restrict__ r, const TM* __restrict__ m,
+                                                 int64_t cells, int64_t stride, double ref, double dx,
+                                                 double* __restrict__ out64,
+                                                 float* __restrict__ out32) {
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= cells) return;
+  double s[D + 1];
+  cell_sums<D>(r, m, c, stride, s);
+  double v[D + 1];
+  v[0] = ref + s[0];
+#pragma unroll
+  for (int j = 0; j < D; ++j) v[1 + j] = s[1 + j] / dx;
+#pragma unroll
+  for (int i = 0; i < D + 1; ++i) {
+    if (out64) out64[i * cells + c] = v[i];
+    if (out32) out32[i * cells + c] = static_cast<float>(v[i]);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// diagnostics: per-block FP64 partials over a tile, then one fixed-order pass
+//   partial slots: 0 sum rho, 1..3 sum q_j, 4 sum |q|^2/rho, 5 sum |curl u|^2,
+//   6 sum (div u)^2, 7 max |u|^2, 8 min rho, 9 max rho, 10 non-finite cells
+// ----------------------------------------------------------------------------
+constexpr int kDiagSlots = 16;
+constexpr int kDiagThreads = 256;
+
+template <int D>
+struct DiagTile;
+template <>
+struct DiagTile<2> {
+  static constexpr int TX = 32, TY = 8, TZ = 1;
+};
+template <>
+struct DiagTile<3> {
+  static constexpr int TX = 8, TY = 8, TZ = 4;
+};
+
+__device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+__device__ __forceinline__ void combine(double (&a)[kDiagSlots], const double (&b)[kDiagSlots]) {
+#pragma unroll
+  for (int s = 0; s < 7; ++s) a[s] += b[s];
+  a[7] = fmax(a[7], b[7]);
+  a[8] = fmin(a[8], b[8]);
+  a[9] = fmax(a[9], b[9]);
+  a[10] += b[10];
+}
+
+__device__ __forceinline__ void identity(double (&a)[kDiagSlots]) {
+#pragma unroll
+  for (int s = 0; s < kDiagSlots; ++s) a[s] = 0.0;
+  a[8] = INFINITY;
+  a[9] = -INFINITY;
+}
+
+// Reduce a[] over the 256 threads of the block in a fixed order; thread 0 ends
+// with the result.
+__device__ void block_reduce(double (&a)[kDiagSlots]) {
+  __shared__ double red[kDiagThreads / 64][kDiagSlots];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    double b[kDiagSlots];
+#pragma unroll
+    for (int s = 0; s < kDiagSlots; ++s) b[s] = __shfl_xor(a[s], off, 64);
+    combine(a, b);
+  }
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int s = 0; s < kDiagSlots; ++s) red[wave][s] = a[s];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int s = 0; s < kDiagSlots; ++s) a[s] = red[0][s];
+    for (int w = 1; w < kDiagThreads / 64; ++w) {
+      double b[kDiagSlots];
+#pragma unroll
+      for (int s = 0; s < kDiagSlots; ++s) b[s] = red[w][s];
+      combine(a, b);
+    }
+  }
+}
+
+template <int D, typename TR, typename TM>
+__global__ __launch_bounds__(kDiagThreads) void k_diag(const TR* __restrict__ r,
+                                                      const TM* __restrict__ m, int nx, int ny,
+                                                      int nz, int64_t stride, double ref, double dx,
+                                                      double* __restrict__ partials) {
+  using T = DiagTile<D>;
+  constexpr int HX = T::TX + 2, HY = T::TY + 2, HZ = (D == 3) ? T::TZ + 2 : 1;
+  constexpr int HN = HX * HY * HZ;
+  __shared__ double sw[D + 1][HN];  // rho, q_j on the tile plus a one-cell halo
+  const int x0 = blockIdx.x * T::TX, y0 = blockIdx.y * T::TY, z0 = blockIdx.z * T::TZ;
+  const int64_t plane = static_cast<int64_t>(nx) * ny;
+  for (int t = threadIdx.x; t < HN; t += kDiagThreads) {
+    const int hx = t % HX, hy = (t / HX) % HY, hz = t / (HX * HY);
+    const int gx = wrap(x0 + hx - 1, nx), gy = wrap(y0 + hy - 1, ny);
+    const int gz = (D == 3) ? wrap(z0 + hz - 1, nz) : 0;
+    const int64_t c = static_cast<int64_t>(gz) * plane + static_cast<int64_t>(gy) * nx + gx;
+    double s[D + 1];
+    cell_sums<D>(r, m, c, stride, s);
+    sw[0][t] = ref + s[0];
+#pragma unroll
+    for (int j = 0; j < D; ++j) sw[1 + j][t] = s[1 + j] / dx;
+  }
+  __syncthreads();
+
+  double a[kDiagSlots];
+  identity(a);
+  const int tx = threadIdx.x % T::TX, ty = (threadIdx.x / T::TX) % T::TY, tz = threadIdx.x / (T::TX * T::TY);
+  const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
+  if (x < nx && y < ny && (D == 2 || z < nz)) {
+    const int h = ((tz + (D == 3 ? 1 : 0)) * HY + (ty + 1)) * HX + (tx + 1);
+    const int sx = 1, sy = HX, sz = HX * HY;
+    const double rho = sw[0][h];
+    double q[D], u2 = 0.0, q2 = 0.0;
+    bool finite = isfinite(rho);
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      q[j] = sw[1 + j][h];
+      finite = finite && isfinite(q[j]);
+      q2 += q[j] * q[j];
+    }
+    u2 = q2 / (rho * rho);
+    // u_j at the neighbour at offset o
+    auto U = [&](int j, int o) { return sw[1 + j][h + o] / sw[0][h + o]; };
+    const double inv2dx = 1.0 / (2.0 * dx);
+    const int st[3] = {sx, sy, sz};
+    double div = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) div += (U(j, st[j]) - U(j, -st[j])) * inv2dx;
+    double curl2 = 0.0;
+    if constexpr (D == 2) {
+      const double w = (U(1, sx) - U(1, -sx)) * inv2dx - (U(0, sy) - U(0, -sy)) * inv2dx;
+      curl2 = w * w;
+    } else {
+      const double wx = (U(2, sy) - U(2, -sy)) * inv2dx - (U(1, sz) - U(1, -sz)) * inv2dx;
+      const double wy = (U(0, sz) - U(0, -sz)) * inv2dx - (U(2, sx) - U(2, -sx)) * inv2dx;
+      const double wz = (U(1, sx) - U(1, -sx)) * inv2dx - (U(0, sy) - U(0, -sy)) * inv2dx;
+      curl2 = wx * wx + wy * wy + wz * wz;
+    }
+    a[0] = rho;
+#pragma unroll
+    for (int j = 0; j < D; ++j) a[1 + j] = q[j];
+    a[4] = q2 / rho;
+    a[5] = curl2;
+    a[6] = div * div;
+    a[7] = u2;
+    a[8] = rho;
+    a[9] = rho;
+    a[10] = finite ? 0.0 : 1.0;
+  }
+  block_reduce(a);
+  if (threadIdx.x == 0) {
+    const int64_t b = (static_cast<int64_t>(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+#pragma unroll
+    for (int s = 0; s < kDiagSlots; ++s) partials[b * kDiagSlots + s] = a[s];
+  }
+}
+
+__global__ __launch_bounds__(kDiagThreads) void k_diag_final(const double* __restrict__ partials,
+                                                            int64_t nblocks,
+                                                            double* __restrict__ result) {
+  double a[kDiagSlots];
+  identity(a);
+  for (int64_t b = threadIdx.x; b < nblocks; b += kDiagThreads) {
+    double v[kDiagSlots];
+#pragma unroll
+    for (int s = 0; s < kDiagSlots; ++s) v[s] = partials[b * kDiagSlots + s];
+    combine(a, v);
+  }
+  block_reduce(a);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int s = 0; s < kDiagSlots; ++s) result[s] = a[s];
+  }
+}
+
+// ----------------------------------------------------------------------------
+// copy probe: 16-byte loads and stores, grid-stride
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_copy(const float4* __restrict__ src, float4* __restrict__ dst,
+                                              int64_t n) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+    dst[i] = src[i];
+}
+
+// ----------------------------------------------------------------------------
+// launchers
+// ----------------------------------------------------------------------------
+template <int D, typename TR, typename TM, bool DEV>
+struct Impl {
+  static hipError_t init(const Geometry& g, const RunCoef& r, const double* u0, const double* rho0,
+                         void* dst, hipStream_t s) {
+    auto p = planes_of<TR, TM>(dst, g.rest_bytes);
+    const CoefT<double> k = make_coef<double>(r, D, DEV);
+    const int64_t blocks = (g.cells + 255) / 256;
+    hipLaunchKernelGGL((k_init<D, TR, TM>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, u0,
+                       rho0, r.ref, r.dx, p.rest, p.move, g.cells, g.stride, k);
+    return hipGetLastError();
+  }
+
+  static hipError_t step(const Geometry& g, const RunCoef& r, const void* src, void* dst, int bx,
+                         int by, hipStream_t s) {
+    auto a = planes_of<TR, TM>(const_cast<void*>(src), g.rest_bytes);
+    auto b = planes_of<TR, TM>(dst, g.rest_bytes);
+    const Coef k = make_coef<float>(r, D, DEV);
+    dim3 block(bx, by, 1);
+    dim3 grid((g.nx + bx - 1) / bx, (g.ny + by - 1) / by, g.nz);
+    hipLaunchKernelGGL((k_step<D, TR, TM>), grid, block, 0, s, a.rest, a.move, b.rest, b.move, g.nx,
+                       g.ny, g.nz, g.stride, k);
+    return hipGetLastError();
+  }
+
+  static hipError_t moments(const Geometry& g, const RunCoef& r, const void* src, double* out64,
+                            float* out32, hipStream_t s) {
+    auto a = planes_of<TR, TM>(const_cast<void*>(src), g.rest_bytes);
+    const int64_t blocks = (g.cells + 255) / 256;
+    hipLaunchKernelGGL((k_moments<D, TR, TM>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
+                       a.rest, a.move, g.cells, g.stride, DEV ? r.ref : 0.0, r.dx, out64, out32);
+    return hipGetLastError();
+  }
+
+  static dim3 diag_grid(const Geometry& g) {
+    using T = DiagTile<D>;
+    return dim3((g.nx + T::TX - 1) / T::TX, (g.ny + T::TY - 1) / T::TY,
+                D == 3 ? (g.nz + T::TZ - 1) / T::TZ : 1);
+  }
+
+  static int64_t diag_blocks(const Geometry& g) {
+    const dim3 gr = diag_grid(g);
+    return static_cast<int64_t>(gr.x) * gr.y * gr.z;
+  }
+
+  static hipError_t diag(const Geometry& g, const RunCoef& r, const void* src, double* partials,
+                         double* result, hipStream_t s) {
+    auto a = planes_of<TR, TM>(const_cast<void*>(src), g.rest_bytes);
+    hipLaunchKernelGGL((k_diag<D, TR, TM>), diag_grid(g), dim3(kDiagThreads), 0, s, a.rest, a.move,
+                       g.nx, g.ny, g.nz, g.stride, DEV ? r.ref : 0.0, r.dx, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kDiagThreads), 0, s, partials, diag_blocks(g),
+                       result);
+    return hipGetLastError();
+  }
+
+  static const Ops* ops() {
+    static const Ops o = {&init, &step, &moments, &diag, &diag_blocks};
+    return &o;
+  }
+};
+
+}  // namespace
+
+const Ops* ops_for(int dim, int storage) {
+  if (dim == 2) {
+    switch (storage) {
+      case LBM_F32: return Impl<2, float, float, true>::ops();
+      case LBM_F32_RAW: return Impl<2, float, float, false>::ops();
+      case LBM_F16_DEV: return Impl<2, _Float16, _Float16, true>::ops();
+      case LBM_BF16_DEV: return Impl<2, bf16, bf16, true>::ops();
+      case LBM_F16_DEV_R32: return Impl<2, float, _Float16, true>::ops();
+      case LBM_BF16_DEV_R32: return Impl<2, float, bf16, true>::ops();
+    }
+  } else if (dim == 3) {
+    switch (storage) {
+      case LBM_F32: return Impl<3, float, float, true>::ops();
+      case LBM_F32_RAW: return Impl<3, float, float, false>::ops();
+      case LBM_F16_DEV: return Impl<3, _Float16, _Float16, true>::ops();
+      case LBM_BF16_DEV: return Impl<3, bf16, bf16, true>::ops();
+      case LBM_F16_DEV_R32: return Impl<3, float, _Float16, true>::ops();
+      case LBM_BF16_DEV_R32: return Impl<3, float, bf16, true>::ops();
+    }
+  }
+  return nullptr;
+}
+
+bool storage_elems(int storage, size_t* rest_elem, size_t* move_elem) {
+  switch (storage) {
+    case LBM_F32:
+    case LBM_F32_RAW: *rest_elem = 4; *move_elem = 4; return true;
+    case LBM_F16_DEV:
+    case LBM_BF16_DEV: *rest_elem = 2; *move_elem = 2; return true;
+    case LBM_F16_DEV_R32:
+    case LBM_BF16_DEV_R32: *rest_elem = 4; *move_elem = 2; return true;
+  }
+  return false;
+}
+
+bool storage_is_deviation(int storage) { return storage != LBM_F32_RAW; }
+
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  const int64_t n = static_cast<int64_t>(bytes / 16);
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 256 * 64) blocks = 256 * 64;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_copy, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
+                     reinterpret_cast<const float4*>(src), reinterpret_cast<float4*>(dst), n);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

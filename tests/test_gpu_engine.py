@@ -1,0 +1,258 @@
+"""Parity of the HIP engine (through the C ABI) with the FP64 oracle.
+
+Bar: plain FP32 storage must stay within relative L2 1e-5 of the oracle on
+the velocity after up to 1000 steps; the FP64 diagnostics must agree with the
+oracle's definitions evaluated on the same moments to ~1e-12.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import inputs
+from oracle import diagnostics as odiag
+from oracle import scheme
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2607_24059_amd import lbm  # noqa: E402
+
+FP32_TOL = 1e-5
+
+
+def _engine(p: scheme.Params, u0, rho0=None, storage="f32"):
+    shape = u0.shape[1:]
+    n = tuple(reversed(shape))
+    prm = lbm.make_params(p.dim, n, p.dx, p.dt, p.nu, p.omega_rho, p.omega_q, p.alpha_rho,
+                          storage=storage)
+    return lbm.Engine.create(prm, u0, rho0)
+
+
+def _rel_l2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def _compare(p, u0, steps, rho0=None, tol=FP32_TOL):
+    print(f"[gpu parity] dim={p.dim} shape={u0.shape[1:]} steps={steps}", flush=True)
+    eng = _engine(p, u0, rho0)
+    eng.step(steps)
+    rho, q = eng.moments()
+    eng.close()
+    r_ref, q_ref, _ = scheme.simulate(u0, p, steps, rho0)
+    u, u_ref = q / rho, q_ref / r_ref
+    err = _rel_l2(u, u_ref)
+    print(f"[gpu parity] rel-L2(u) = {err:.3e}", flush=True)
+    assert err <= tol, err
+    assert np.max(np.abs(rho - r_ref)) <= 1e-5
+    return err
+
+
+def test_taylor_green_64_1000_steps():
+    """64^2 Taylor-Green, nu = 0.01, mu = 8, 1000 steps (the oracle-sized case)."""
+    n = 64
+    p = scheme.params_for_grid(2, n, 0.01)
+    _compare(p, inputs.taylor_green(n), 1000)
+
+
+def test_random_field_256_1000_steps():
+    """The benchmark field (k^-3, Mach 0.05, nu = 1e-3) at 256^2 for 1000 steps."""
+    n = 256
+    p = scheme.params_for_grid(2, n, 1e-3)
+    _compare(p, inputs.random_field_2d(n, 0, umax=0.05 / p.dx), 1000)
+
+
+def test_raw_fp32_storage_runs_close():
+    """LBM_F32_RAW (populations themselves in FP32) on the same case: correct to
+    FP32 precision, but its large constant parts make it the less accurate mode."""
+    n = 64
+    p = scheme.params_for_grid(2, n, 0.01)
+    u0 = inputs.taylor_green(n)
+    eng = _engine(p, u0, storage="f32_raw")
+    eng.step(1000)
+    rho, q = eng.moments()
+    eng.close()
+    r_ref, q_ref, _ = scheme.simulate(u0, p, 1000)
+    err = _rel_l2(q / rho, q_ref / r_ref)
+    print(f"[gpu parity] f32_raw rel-L2(u) = {err:.3e}", flush=True)
+    assert err <= 5e-5
+
+
+@pytest.mark.parametrize("shape", [(8, 8), (75, 75), (40, 96), (3, 130), (129, 1)])
+def test_random_field_2d_ragged(shape):
+    """Non power-of-two and ragged grids: wrap-around and partial blocks."""
+    ny, nx = shape
+    dx = 2 * math.pi / max(nx, ny)
+    p = scheme.Params(dim=2, dx=dx, dt=dx * dx / 8, nu=0.02)
+    u = inputs.random_field_box(shape, dx, seed=3, umax=0.05 / dx)
+    rho0 = 1 + 1e-3 * inputs.random_field_box(shape, dx, seed=4)[0]  # smooth density bump
+    _compare(p, u, 300, rho0)
+
+
+def test_zero_steps_is_the_equilibrium():
+    n = 32
+    p = scheme.params_for_grid(2, n, 0.01)
+    u0 = inputs.random_field_2d(n, 0, umax=0.05 / p.dx)
+    eng = _engine(p, u0)
+    rho, q = eng.moments()
+    eng.close()
+    assert np.max(np.abs(rho - 1)) <= 1e-6
+    assert _rel_l2(q, u0) <= 1e-6
+
+
+@pytest.mark.parametrize("shape,steps", [((16, 16, 16), 200), ((10, 12, 14), 100), ((32, 32, 32), 100)])
+def test_random_field_3d(shape, steps):
+    dx = 2 * math.pi / max(shape)
+    p = scheme.Params(dim=3, dx=dx, dt=dx * dx / 8, nu=0.02)
+    if len(set(shape)) == 1:
+        u = inputs.random_field_3d(shape[0], seed=5, umax=0.05 / dx)
+    else:
+        u = inputs.random_field_box(shape, dx, seed=5, umax=0.05 / dx)
+    _compare(p, u, steps)
+
+
+def test_abc_3d():
+    n = 24
+    p = scheme.params_for_grid(3, n, 0.05)
+    u0 = inputs.abc_flow(n, 0.25, 0.25, 0.25)
+    rho0 = inputs.well_prepared_density(inputs.abc_pressure(u0), p.dx)
+    _compare(p, u0, 150, rho0)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_diagnostics_match_definitions(dim):
+    n = 48 if dim == 2 else 20
+    p = scheme.params_for_grid(dim, n, 0.02)
+    if dim == 2:
+        u0 = inputs.random_field_2d(n, 2, umax=0.05 / p.dx)
+    else:
+        u0 = inputs.random_field_3d(n, 2, umax=0.05 / p.dx)
+    eng = _engine(p, u0)
+    eng.step(50)
+    rho, q = eng.moments()
+    d = eng.diagnostics()
+    eng.close()
+    ref = odiag.from_moments(rho, q, p.dx)
+    for key in ("mass", "kinetic", "enstrophy", "div_l2", "max_u", "rho_min", "rho_max"):
+        assert d[key] == pytest.approx(ref[key], rel=1e-12, abs=1e-300), key
+    for j in range(dim):
+        assert d["mom"][j] == pytest.approx(ref["mom"][j], abs=1e-12 * ref["kinetic"])
+    assert d["nonfinite"] == 0 and d["status"] == lbm.LBM_OK
+    assert d["step"] == 50 and d["time"] == pytest.approx(50 * p.dt)
+
+
+def test_mass_momentum_conserved_and_deterministic():
+    n = 96
+    p = scheme.params_for_grid(2, n, 0.01)
+    u0 = inputs.random_field_2d(n, 4, umax=0.05 / p.dx)
+    blobs = []
+    for _ in range(2):
+        eng = _engine(p, u0)
+        d0 = eng.diagnostics()
+        eng.step(500)
+        d1 = eng.diagnostics()
+        blobs.append(eng.save_state())
+        eng.close()
+        assert d1["mass"] == pytest.approx(d0["mass"], rel=1e-6)
+    assert np.array_equal(blobs[0], blobs[1])
+
+
+def test_save_load_continuation_is_bitwise():
+    n = 40
+    p = scheme.params_for_grid(2, n, 0.01)
+    u0 = inputs.random_field_2d(n, 6, umax=0.05 / p.dx)
+    a = _engine(p, u0)
+    a.step(60)
+    blob_full = None
+    mid = a.save_state()
+    a.step(60)
+    blob_full = a.save_state()
+    a.close()
+    b = _engine(p, inputs.taylor_green(n))  # different initial state, then overwritten
+    b.load_state(mid)
+    assert b.steps == 60
+    b.step(60)
+    assert np.array_equal(b.save_state(), blob_full)
+    b.close()
+
+
+def test_nonfinite_reported():
+    n = 16
+    p = scheme.params_for_grid(2, n, 0.01)
+    u0 = inputs.taylor_green(n)
+    eng = _engine(p, u0)
+    blob = eng.save_state()
+    f = blob[:-8].view(np.float32)
+    f[5] = np.nan          # rho rest plane, cell 5
+    f[n * n + 7] = np.inf  # q_x rest plane (plane stride is n*n rounded to 256 = 256), cell 7
+    eng.load_state(blob)
+    d = eng.diagnostics()
+    eng.close()
+    assert d["status"] == lbm.LBM_ENONFINITE and d["nonfinite"] == 2
+
+
+def test_invalid_workspace_rejected():
+    n = 16
+    p = scheme.params_for_grid(2, n, 0.01)
+    prm = lbm.make_params(2, (n, n), p.dx, p.dt, p.nu)
+    nb = lbm.lbm_workspace_bytes(prm)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_init(prm, inputs.taylor_green(n), None, ws.data_ptr(), nb - 256,
+                     torch.cuda.current_stream().cuda_stream)
+    assert e.value.status == lbm.LBM_ENOMEM
+
+
+# --------------------------------------------------------------------------- #
+# full-size cases, in the launch configuration the benchmark times            #
+# --------------------------------------------------------------------------- #
+
+def _patch_reference(u0_full, p, centre, steps):
+    """Oracle value at `centre` after `steps` steps, from a periodic patch of
+    side 2*steps + 2 around it: information moves at most one cell per step,
+    so the wrapped patch edges cannot reach the centre in time."""
+    dim = p.dim
+    half = steps + 1
+    idx = [np.arange(c - half, c + half) % s for c, s in zip(centre, u0_full.shape[1:])]
+    patch = u0_full[(slice(None),) + np.ix_(*idx)]
+    rho, q, _ = scheme.simulate(np.ascontiguousarray(patch), p, steps)
+    mid = (half,) * dim
+    return rho[mid], q[(slice(None),) + mid]
+
+
+def test_full_size_2d_4096_sampled():
+    """4096^2, nu = 1e-3, k^-3 field at Mach 0.05, 64 steps: sampled cells
+    against the oracle on domain-of-dependence patches."""
+    n, steps = 4096, 64
+    p = scheme.params_for_grid(2, n, 1e-3)
+    u0 = inputs.random_field_2d(n, 0, umax=0.05 / p.dx)
+    eng = _engine(p, u0)
+    eng.step(steps)
+    rho, q = eng.moments()
+    d = eng.diagnostics()
+    eng.close()
+    assert d["nonfinite"] == 0
+    rng = np.random.default_rng(0)
+    for centre in [(0, 0), (n - 1, 17), (2048, 4095)] + [tuple(rng.integers(0, n, 2)) for _ in range(3)]:
+        r_ref, q_ref = _patch_reference(u0, p, centre, steps)
+        assert abs(rho[centre] - r_ref) <= 1e-6
+        assert np.max(np.abs(q[(slice(None),) + centre] - q_ref)) <= 1e-5 * 0.05 / p.dx
+
+
+def test_full_size_3d_256_sampled():
+    n, steps = 256, 16
+    p = scheme.params_for_grid(3, n, 1e-3)
+    u0 = inputs.random_field_3d(n, 0, umax=0.05 / p.dx)
+    eng = _engine(p, u0)
+    eng.step(steps)
+    rho, q = eng.moments()
+    eng.close()
+    rng = np.random.default_rng(1)
+    for centre in [(0, 0, 0), (255, 3, 128)] + [tuple(rng.integers(0, n, 3)) for _ in range(2)]:
+        r_ref, q_ref = _patch_reference(u0, p, centre, steps)
+        assert abs(rho[centre] - r_ref) <= 1e-6
+        assert np.max(np.abs(q[(slice(None),) + centre] - q_ref)) <= 1e-5 * 0.05 / p.dx
