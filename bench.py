@@ -108,7 +108,7 @@ def copy_probe_gbs(nbytes: int = 1 << 30, reps: int = 20) -> float:
     return 2 * nbytes / sec / 1e9
 
 
-def cpu_baseline(n: int = 4096, steps: int = 3, nu: float = 1e-3) -> dict:
+def cpu_baseline(n: int = 4096, steps: int = 10, nu: float = 1e-3) -> dict:
     """The FP64 numpy oracle on `steps` steps of the same 4096^2 workload."""
     from oracle import scheme
     u0, dx, dt, _ = make_workload(n, 2, nu)
@@ -214,12 +214,50 @@ def main():
             ms_v, e = time_engine(n3, 3, storage, vs, 10, u0=u3)
             e.close()
             variants[f"3d_{n3}_{storage}"] = _variant(n3 ** 3, ms_v, BYTES_PER_LUP[(storage, 3)], probe)
+        for storage in ("f32", "f16_dev_r32"):
+            log(f"[bench] batch 512 runs {storage}")
+            variants[f"batch512_{storage}"] = batch_variant(storage, 1000, probe)
         result["variants"] = variants
 
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")
         result["cpu_baseline"] = cpu_baseline(n)
     print(json.dumps(result), flush=True)
+
+
+def batch_variant(storage: str, steps: int, probe: float, n_runs: int = 512) -> dict:
+    """The batch workload: n_runs independent 2D runs, sizes 64^2..1024^2,
+    nu log-uniform in [1e-4, 1e-2], k^-3 fields at Mach 0.05, all advanced
+    `steps` steps by one persistent launch per step (graph replays)."""
+    import torch
+    import inputs
+    from paper_2607_24059_amd import batch as B
+    specs = inputs.batch_run_specs(n_runs)
+    runs, u0s = [], []
+    for s in specs:
+        n = s["n"]
+        dx = 2 * math.pi / n
+        runs.append(B.make_run((n, n), dx, dx * dx / 8, s["nu"]))
+        u0s.append(inputs.random_field_2d(n, s["seed"], umax=0.05 / dx))
+    b = B.Batch.create(2, storage, runs, u0s)
+    del u0s
+    b.autotune(None)
+    b.step(4)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(b.stream)
+    b.step(steps)
+    ev1.record(b.stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    cells, tiles, _ = b.info()
+    widths = sorted({(int(r.n[0]), b.tile_width(i)) for i, r in enumerate(runs)})
+    b.close()
+    out = _variant(cells, ms, BYTES_PER_LUP[(storage, 2)], probe)
+    out.update({"runs": n_runs, "cells": cells, "tiles": tiles, "steps": steps,
+                "tile_width_by_n": {str(n): w for n, w in widths}})
+    return out
 
 
 def _variant(cells, ms, bytes_per_lup, probe):

@@ -1,0 +1,79 @@
+/*
+ * lbm_batch.h - many independent runs of the vectorial lattice Boltzmann
+ * scheme (paper, Section 2) advanced together on one GPU.
+ *
+ * Every run is an independent periodic problem with its own grid and its own
+ * scheme parameters (dx, dt, nu, omega, alpha); all runs share the dimension
+ * and the storage mode (lbm_storage of lbm.h).  One time step of the whole
+ * batch is ONE launch of a persistent kernel whose blocks walk a list of
+ * 256-cell tiles covering every run; the tile shape of each size class
+ * (64x4, 128x2 or 256x1 cells in 2D) is chosen by lbm_batch_autotune.  Steps
+ * are replayed from a HIP graph.  The per-cell update is the same device code
+ * as lbm_step, so a run advanced in a batch is bit-identical to the same run
+ * advanced alone.
+ *
+ * Conventions are those of lbm.h: status codes only, caller-owned device
+ * workspace (never allocated by the library), caller's stream, FP64 host
+ * arrays copied during the call.
+ */
+#ifndef LBM_BATCH_H
+#define LBM_BATCH_H
+
+#include "lbm.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_batch lbm_batch;
+
+/* One run.  Same meaning and validity rules as the fields of lbm_params. */
+typedef struct lbm_run_spec {
+  int64_t n[3];       /* cells along x, y, z (n[2] = 1 in 2D) */
+  double dx, dt, nu;  /* mu = dx^2/dt; nu sets alpha_q */
+  double omega_rho, omega_q, alpha_rho;
+  double rho_ref;
+} lbm_run_spec;
+
+/* Device workspace bytes for the batch (0 if any run is invalid). */
+size_t lbm_batch_workspace_bytes(int32_t dim, int32_t storage, int32_t nruns,
+                                 const lbm_run_spec* runs);
+
+/* Create the batch and set every run to the equilibrium of its initial moments.
+ *   u0[r]    host FP64 [dim][cells_r] velocity of run r (required)
+ *   rho0     NULL, or an array whose entries are NULL (rho_ref) or FP64 [cells_r]
+ * Returns LBM_EINVAL / LBM_EUNSTABLE for the first invalid run (its index in
+ * *bad_run if bad_run != NULL).  Synchronises once. */
+lbm_status lbm_batch_init(lbm_batch** out, int32_t dim, int32_t storage, int32_t nruns,
+                          const lbm_run_spec* runs, const double* const* u0,
+                          const double* const* rho0, void* workspace, size_t ws_bytes,
+                          void* hip_stream, int32_t* bad_run);
+
+/* Choose the tile shape of every size class (runs grouped by nx rounded up to
+ * a power of two) by timing each candidate on the batch's own buffers; the
+ * state is not changed.  If cache_path is non-NULL (else the environment
+ * variable LBM_AUTOTUNE_CACHE, if set) previously tuned shapes for this
+ * device, dimension and storage are read from that text file and new ones are
+ * appended.  Rebuilds the step graph.  Synchronises. */
+lbm_status lbm_batch_autotune(lbm_batch* b, const char* cache_path);
+
+/* Advance every run by nsteps >= 0 steps.  Asynchronous (graph replays). */
+lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps);
+
+/* Moments of run r, as lbm_moments.  Synchronises. */
+lbm_status lbm_batch_moments(lbm_batch* b, int32_t run, double* rho, double* q);
+
+/* Total cells over all runs, and number of 256-cell tiles per step. */
+lbm_status lbm_batch_info(const lbm_batch* b, int64_t* total_cells, int64_t* tiles,
+                          int64_t* steps);
+
+/* Tile width (cells along x) chosen for run r's size class. */
+int32_t lbm_batch_tile_width(const lbm_batch* b, int32_t run);
+
+void lbm_batch_destroy(lbm_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_BATCH_H */

@@ -74,20 +74,7 @@ lbm_status check(const lbm_params* p, double* mu, double* alpha_q, uint32_t* fla
   return LBM_OK;
 }
 
-Geometry geometry(const lbm_params* p) {
-  Geometry g;
-  g.dim = p->dim;
-  g.nx = static_cast<int32_t>(p->n[0]);
-  g.ny = static_cast<int32_t>(p->n[1]);
-  g.nz = static_cast<int32_t>(p->n[2]);
-  g.cells = p->n[0] * p->n[1] * p->n[2];
-  g.stride = (g.cells + 255) / 256 * 256;
-  lbm::storage_elems(p->storage, &g.rest_elem, &g.move_elem);
-  const int ns = p->dim + 1;
-  g.rest_bytes = align_up(static_cast<size_t>(ns) * g.stride * g.rest_elem);
-  g.buf_bytes = align_up(g.rest_bytes + static_cast<size_t>(ns) * 2 * p->dim * g.stride * g.move_elem);
-  return g;
-}
+Geometry geometry(const lbm_params* p) { return lbm::make_geometry(p->dim, p->storage, p->n); }
 
 // staging (FP64 moments or initial fields) lives in the idle buffer
 size_t staging_bytes(const Geometry& g) { return static_cast<size_t>(g.dim + 1) * g.cells * sizeof(double); }

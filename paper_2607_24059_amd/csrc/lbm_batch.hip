@@ -1,0 +1,525 @@
+// Batched engine: many independent runs, one persistent launch per step,
+// replayed from a HIP graph (contract in include/lbm_batch.h).
+//
+// Work decomposition.  Every run is cut into tiles of exactly 256 cells:
+// bx x (256 / bx) cells of one z-plane, with bx in {64, 128, 256} chosen per
+// size class.  The tile list of the whole batch (runs in order, tiles of a run
+// row-major) lives in device memory; a step is one launch of k_batch_step
+// whose blocks walk the list with a static stride, so at any moment the
+// resident blocks work on one contiguous stretch of it.  Each tile reads its
+// run's descriptor (geometry, buffer offsets, coefficients) with scalar loads
+// and updates its cells with the same step_cell as the single-run kernel.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_batch.h"
+#include "lbm_device.hpp"
+#include "lbm_internal.hpp"
+
+namespace lbm {
+namespace {
+
+constexpr int kTileCells = 256;
+constexpr int kGraphSteps = 50;  // steps per replay of the main graph (even)
+
+struct BatchRun {
+  int32_t nx, ny, nz, pad;
+  int64_t stride;
+  int64_t rest_bytes;
+  int64_t off[2];  // byte offsets of the two state buffers from the workspace base
+  Coef k;
+};
+
+struct BatchTile {
+  int32_t run;
+  int32_t x0, y0;
+  int16_t z;
+  int16_t bx_log2;
+};
+static_assert(sizeof(BatchTile) == 16, "tile descriptor is 16 bytes");
+
+template <int D, typename TR, typename TM>
+__global__ __launch_bounds__(kTileCells) void k_batch_step(const BatchRun* __restrict__ runs,
+                                                           const BatchTile* __restrict__ tiles,
+                                                           int64_t ntiles, char* __restrict__ base,
+                                                           int parity) {
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const BatchTile tl = tiles[t];
+    const BatchRun& r = runs[tl.run];
+    const int bxl = tl.bx_log2;
+    const int x = tl.x0 + (threadIdx.x & ((1 << bxl) - 1));
+    const int y = tl.y0 + (threadIdx.x >> bxl);
+    if (x < r.nx && y < r.ny) {
+      char* src = base + r.off[parity];
+      char* dst = base + r.off[parity ^ 1];
+      const auto a = planes_of<TR, TM>(src, static_cast<size_t>(r.rest_bytes));
+      const auto b = planes_of<TR, TM>(dst, static_cast<size_t>(r.rest_bytes));
+      step_cell<D, TR, TM>(a.rest, a.move, b.rest, b.move, x, y, tl.z, r.nx, r.ny, r.nz, r.stride, r.k);
+    }
+  }
+}
+
+using BatchKernel = void (*)(const BatchRun*, const BatchTile*, int64_t, char*, int);
+
+BatchKernel batch_kernel(int dim, int storage) {
+  if (dim == 2) {
+    switch (storage) {
+      case LBM_F32: case LBM_F32_RAW: return &k_batch_step<2, float, float>;
+      case LBM_F16_DEV: return &k_batch_step<2, _Float16, _Float16>;
+      case LBM_BF16_DEV: return &k_batch_step<2, bf16, bf16>;
+      case LBM_F16_DEV_R32: return &k_batch_step<2, float, _Float16>;
+      case LBM_BF16_DEV_R32: return &k_batch_step<2, float, bf16>;
+    }
+  } else if (dim == 3) {
+    switch (storage) {
+      case LBM_F32: case LBM_F32_RAW: return &k_batch_step<3, float, float>;
+      case LBM_F16_DEV: return &k_batch_step<3, _Float16, _Float16>;
+      case LBM_BF16_DEV: return &k_batch_step<3, bf16, bf16>;
+      case LBM_F16_DEV_R32: return &k_batch_step<3, float, _Float16>;
+      case LBM_BF16_DEV_R32: return &k_batch_step<3, float, bf16>;
+    }
+  }
+  return nullptr;
+}
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+int pow2_class(int64_t nx) {
+  int64_t c = 1;
+  while (c < nx) c <<= 1;
+  return static_cast<int>(c);
+}
+
+// tiles of one run for tile width bx
+int64_t tiles_of(const Geometry& g, int bx) {
+  const int by = kTileCells / bx;
+  return static_cast<int64_t>((g.nx + bx - 1) / bx) * ((g.ny + by - 1) / by) * g.nz;
+}
+
+int log2i(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+}  // namespace
+}  // namespace lbm
+
+using namespace lbm;
+
+struct lbm_batch {
+  int dim = 0, storage = 0, nruns = 0;
+  std::vector<lbm_run_spec> specs;
+  std::vector<Geometry> geo;
+  std::vector<RunCoef> coef;
+  std::vector<int64_t> off0, off1;
+  std::vector<int> cls;           // size class (pow2 of nx) of each run
+  std::map<int, int> bx_of_class; // tile width per class
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  BatchRun* d_runs = nullptr;
+  BatchTile* d_tiles = nullptr;
+  int64_t max_tiles = 0;
+  int64_t ntiles = 0;
+  int64_t total_cells = 0;
+  int parity = 0;  // state buffer index holding the current step
+  int grid = 0;    // persistent grid size
+  hipStream_t stream = nullptr;
+  BatchKernel kernel = nullptr;
+  hipGraphExec_t exec_main = nullptr;  // kGraphSteps steps starting at parity 0
+  hipGraphExec_t exec_one[2] = {nullptr, nullptr};
+  int64_t steps = 0;
+};
+
+namespace {
+
+lbm_params params_of(int dim, int storage, const lbm_run_spec& r) {
+  lbm_params p;
+  p.dim = dim;
+  p.storage = storage;
+  for (int a = 0; a < 3; ++a) p.n[a] = r.n[a];
+  p.dx = r.dx;
+  p.dt = r.dt;
+  p.nu = r.nu;
+  p.omega_rho = r.omega_rho;
+  p.omega_q = r.omega_q;
+  p.alpha_rho = r.alpha_rho;
+  p.gamma = 1.0;
+  p.rho_ref = r.rho_ref;
+  return p;
+}
+
+int default_bx(const Geometry& g) {
+  int bx = 256;
+  while (bx > 64 && bx / 2 >= g.nx) bx /= 2;
+  return bx;
+}
+
+struct Layout {
+  size_t runs_off, tiles_off, bufs_off, total;
+  int64_t max_tiles;
+  std::vector<int64_t> off0, off1;
+};
+
+Layout layout(int dim, int storage, int nruns, const lbm_run_spec* runs) {
+  Layout L;
+  L.max_tiles = 0;
+  std::vector<Geometry> geo;
+  for (int r = 0; r < nruns; ++r) {
+    const Geometry g = make_geometry(dim, storage, runs[r].n);
+    int64_t mt = 0;
+    for (int bx = 64; bx <= 256; bx *= 2) mt = std::max(mt, tiles_of(g, bx));
+    L.max_tiles += mt;
+    geo.push_back(g);
+  }
+  L.runs_off = 0;
+  L.tiles_off = align256(sizeof(BatchRun) * nruns);
+  L.bufs_off = align256(L.tiles_off + sizeof(BatchTile) * L.max_tiles);
+  size_t off = L.bufs_off;
+  for (int r = 0; r < nruns; ++r) {
+    L.off0.push_back(static_cast<int64_t>(off));
+    off += geo[r].buf_bytes;
+    L.off1.push_back(static_cast<int64_t>(off));
+    off += geo[r].buf_bytes;
+  }
+  L.total = off;
+  return L;
+}
+
+lbm_status dev(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EDEVICE; }
+
+// Build the host tile list for the runs selected by `use` (all if empty).
+std::vector<BatchTile> build_tiles(const lbm_batch* b, const std::vector<char>& use) {
+  std::vector<BatchTile> t;
+  for (int r = 0; r < b->nruns; ++r) {
+    if (!use.empty() && !use[r]) continue;
+    const Geometry& g = b->geo[r];
+    const int bx = b->bx_of_class.at(b->cls[r]);
+    const int by = kTileCells / bx;
+    const int16_t bl = static_cast<int16_t>(log2i(bx));
+    for (int z = 0; z < g.nz; ++z)
+      for (int y0 = 0; y0 < g.ny; y0 += by)
+        for (int x0 = 0; x0 < g.nx; x0 += bx) t.push_back(BatchTile{r, x0, y0, static_cast<int16_t>(z), bl});
+  }
+  return t;
+}
+
+hipError_t upload_tiles(lbm_batch* b, const std::vector<BatchTile>& t) {
+  if (static_cast<int64_t>(t.size()) > b->max_tiles) return hipErrorInvalidValue;
+  b->ntiles = static_cast<int64_t>(t.size());
+  if (t.empty()) return hipSuccess;
+  hipError_t e = hipMemcpyAsync(b->d_tiles, t.data(), t.size() * sizeof(BatchTile), hipMemcpyHostToDevice,
+                                b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  return e;
+}
+
+hipError_t launch_step(lbm_batch* b, int parity, int64_t ntiles, hipStream_t s) {
+  if (ntiles == 0) return hipSuccess;
+  const unsigned grid = static_cast<unsigned>(std::min<int64_t>(ntiles, b->grid));
+  hipLaunchKernelGGL(b->kernel, dim3(grid), dim3(kTileCells), 0, s, b->d_runs, b->d_tiles, ntiles, b->ws,
+                     parity);
+  return hipGetLastError();
+}
+
+void destroy_graphs(lbm_batch* b) {
+  if (b->exec_main) hipGraphExecDestroy(b->exec_main);
+  for (auto& e : b->exec_one)
+    if (e) hipGraphExecDestroy(e);
+  b->exec_main = nullptr;
+  b->exec_one[0] = b->exec_one[1] = nullptr;
+}
+
+// A graph of `count` consecutive steps starting at `parity`: a chain of
+// kernel nodes (no memset or copy nodes).
+hipError_t make_graph(lbm_batch* b, int parity, int count, hipGraphExec_t* out) {
+  hipGraph_t g = nullptr;
+  hipError_t e = hipGraphCreate(&g, 0);
+  if (e != hipSuccess) return e;
+  hipGraphNode_t prev = nullptr;
+  const unsigned grid = static_cast<unsigned>(std::min<int64_t>(std::max<int64_t>(b->ntiles, 1), b->grid));
+  for (int s = 0; s < count && e == hipSuccess; ++s) {
+    int par = (parity + s) & 1;
+    const BatchRun* runs = b->d_runs;
+    const BatchTile* tiles = b->d_tiles;
+    int64_t nt = b->ntiles;
+    char* base = b->ws;
+    void* args[] = {&runs, &tiles, &nt, &base, &par};
+    hipKernelNodeParams kp;
+    memset(&kp, 0, sizeof(kp));
+    kp.func = reinterpret_cast<void*>(b->kernel);
+    kp.gridDim = dim3(grid);
+    kp.blockDim = dim3(kTileCells);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    hipGraphNode_t node;
+    e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+    prev = node;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  return e;
+}
+
+hipError_t rebuild(lbm_batch* b) {
+  destroy_graphs(b);
+  hipError_t e = upload_tiles(b, build_tiles(b, {}));
+  if (e == hipSuccess) e = make_graph(b, 0, kGraphSteps, &b->exec_main);
+  if (e == hipSuccess) e = make_graph(b, 0, 1, &b->exec_one[0]);
+  if (e == hipSuccess) e = make_graph(b, 1, 1, &b->exec_one[1]);
+  return e;
+}
+
+std::string device_key() {
+  int dev = 0;
+  hipGetDevice(&dev);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  std::string k = prop.gcnArchName;
+  for (auto& ch : k)
+    if (ch == ' ' || ch == ':') ch = '_';
+  return k;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_batch_workspace_bytes(int32_t dim, int32_t storage, int32_t nruns, const lbm_run_spec* runs) {
+  if (nruns <= 0 || !runs) return 0;
+  for (int r = 0; r < nruns; ++r) {
+    lbm_params p = params_of(dim, storage, runs[r]);
+    if (lbm_check_params(&p, nullptr, nullptr, nullptr) != LBM_OK) return 0;
+  }
+  return layout(dim, storage, nruns, runs).total;
+}
+
+lbm_status lbm_batch_init(lbm_batch** out, int32_t dim, int32_t storage, int32_t nruns,
+                          const lbm_run_spec* runs, const double* const* u0, const double* const* rho0,
+                          void* workspace, size_t ws_bytes, void* hip_stream, int32_t* bad_run) {
+  if (!out || !runs || !u0 || !workspace || nruns <= 0) return LBM_EINVAL;
+  *out = nullptr;
+  if (bad_run) *bad_run = -1;
+  std::vector<RunCoef> coefs;
+  for (int r = 0; r < nruns; ++r) {
+    lbm_params p = params_of(dim, storage, runs[r]);
+    double mu = 0, aq = 0;
+    lbm_status st = lbm_check_params(&p, &mu, &aq, nullptr);
+    if (st == LBM_OK && !u0[r]) st = LBM_EINVAL;
+    if (st != LBM_OK) {
+      if (bad_run) *bad_run = r;
+      return st;
+    }
+    coefs.push_back(RunCoef{runs[r].dx, mu, runs[r].alpha_rho, aq, runs[r].omega_rho, runs[r].omega_q,
+                            runs[r].rho_ref});
+  }
+  const Layout L = layout(dim, storage, nruns, runs);
+  if (ws_bytes < L.total) return LBM_ENOMEM;
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return LBM_EINVAL;
+
+  lbm_batch* b = new (std::nothrow) lbm_batch;
+  if (!b) return LBM_ENOMEM;
+  b->dim = dim;
+  b->storage = storage;
+  b->nruns = nruns;
+  b->specs.assign(runs, runs + nruns);
+  b->coef = coefs;
+  b->off0 = L.off0;
+  b->off1 = L.off1;
+  b->ws = static_cast<char*>(workspace);
+  b->ws_bytes = ws_bytes;
+  b->d_runs = reinterpret_cast<BatchRun*>(b->ws + L.runs_off);
+  b->d_tiles = reinterpret_cast<BatchTile*>(b->ws + L.tiles_off);
+  b->max_tiles = L.max_tiles;
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  b->kernel = batch_kernel(dim, storage);
+  const Ops* ops = ops_for(dim, storage);
+  const bool devn = storage_is_deviation(storage);
+
+  std::vector<BatchRun> host_runs(nruns);
+  hipError_t e = hipSuccess;
+  for (int r = 0; r < nruns && e == hipSuccess; ++r) {
+    const Geometry g = make_geometry(dim, storage, runs[r].n);
+    b->geo.push_back(g);
+    b->total_cells += g.cells;
+    b->cls.push_back(pow2_class(g.nx));
+    if (!b->bx_of_class.count(b->cls.back())) b->bx_of_class[b->cls.back()] = default_bx(g);
+    BatchRun& d = host_runs[r];
+    d.nx = g.nx;
+    d.ny = g.ny;
+    d.nz = g.nz;
+    d.pad = 0;
+    d.stride = g.stride;
+    d.rest_bytes = static_cast<int64_t>(g.rest_bytes);
+    d.off[0] = L.off0[r];
+    d.off[1] = L.off1[r];
+    d.k = make_coef<float>(coefs[r], dim, devn);
+    // stage the initial fields in buffer 1 of the run, build the equilibrium in buffer 0
+    double* su = reinterpret_cast<double*>(b->ws + L.off1[r]);
+    double* sr = (rho0 && rho0[r]) ? su + static_cast<size_t>(dim) * g.cells : nullptr;
+    e = hipMemcpyAsync(su, u0[r], static_cast<size_t>(dim) * g.cells * sizeof(double), hipMemcpyHostToDevice,
+                       b->stream);
+    if (e == hipSuccess && sr)
+      e = hipMemcpyAsync(sr, rho0[r], static_cast<size_t>(g.cells) * sizeof(double), hipMemcpyHostToDevice,
+                         b->stream);
+    if (e == hipSuccess) e = ops->init(g, coefs[r], su, sr, b->ws + L.off0[r], b->stream);
+    // pageable host copies: keep the staging buffer alive until it has been consumed
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->d_runs, host_runs.data(), sizeof(BatchRun) * nruns, hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e == hipSuccess) {
+    int dev = 0, cus = 0;
+    hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 256;
+    b->grid = 8 * cus;  // 8 resident 256-thread blocks per CU at the kernel's register use
+    e = rebuild(b);
+  }
+  if (e != hipSuccess) {
+    destroy_graphs(b);
+    delete b;
+    return LBM_EDEVICE;
+  }
+  *out = b;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_autotune(lbm_batch* b, const char* cache_path) {
+  if (!b) return LBM_EINVAL;
+  if (!cache_path) cache_path = getenv("LBM_AUTOTUNE_CACHE");
+  const std::string key = device_key();
+  std::map<int, int> cached;
+  if (cache_path) {
+    FILE* f = fopen(cache_path, "r");
+    if (f) {
+      char arch[128];
+      int d, st, cl, bx;
+      while (fscanf(f, "%127s %d %d %d %d", arch, &d, &st, &cl, &bx) == 5)
+        if (key == arch && d == b->dim && st == b->storage && (bx == 64 || bx == 128 || bx == 256))
+          cached[cl] = bx;
+      fclose(f);
+    }
+  }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return LBM_EDEVICE;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return LBM_EDEVICE;
+  }
+  hipError_t e = hipSuccess;
+  std::vector<std::pair<int, int>> fresh;
+  for (auto& kv : b->bx_of_class) {
+    const int cl = kv.first;
+    if (cached.count(cl)) {
+      kv.second = cached[cl];
+      continue;
+    }
+    std::vector<char> use(b->nruns, 0);
+    for (int r = 0; r < b->nruns; ++r) use[r] = (b->cls[r] == cl);
+    float best = 1e30f;
+    int best_bx = kv.second;
+    for (int bx = 64; bx <= 256 && e == hipSuccess; bx *= 2) {
+      if (bx > 64 && bx > cl) break;  // tiles wider than the class waste lanes
+      kv.second = bx;
+      const std::vector<BatchTile> t = build_tiles(b, use);
+      e = upload_tiles(b, t);
+      // a step only writes the idle buffer, so timing it leaves the state intact
+      for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch_step(b, b->parity, b->ntiles, b->stream);
+      if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+      for (int it = 0; it < 5 && e == hipSuccess; ++it) e = launch_step(b, b->parity, b->ntiles, b->stream);
+      if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess && ms < best) {
+        best = ms;
+        best_bx = bx;
+      }
+    }
+    kv.second = best_bx;
+    fresh.emplace_back(cl, best_bx);
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (e == hipSuccess) e = rebuild(b);
+  if (e != hipSuccess) return LBM_EDEVICE;
+  if (cache_path && !fresh.empty()) {
+    FILE* f = fopen(cache_path, "a");
+    if (f) {
+      for (auto& p : fresh) fprintf(f, "%s %d %d %d %d\n", key.c_str(), b->dim, b->storage, p.first, p.second);
+      fclose(f);
+    }
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
+  if (!b || nsteps < 0) return LBM_EINVAL;
+  hipError_t e = hipSuccess;
+  while (nsteps > 0 && e == hipSuccess) {
+    if (b->parity == 0 && nsteps >= kGraphSteps) {
+      e = hipGraphLaunch(b->exec_main, b->stream);
+      if (e == hipSuccess) {
+        nsteps -= kGraphSteps;
+        b->steps += kGraphSteps;  // even count: parity unchanged
+      }
+    } else {
+      e = hipGraphLaunch(b->exec_one[b->parity], b->stream);
+      if (e == hipSuccess) {
+        nsteps -= 1;
+        b->steps += 1;
+        b->parity ^= 1;
+      }
+    }
+  }
+  return dev(e);
+}
+
+lbm_status lbm_batch_moments(lbm_batch* b, int32_t run, double* rho, double* q) {
+  if (!b || !rho || run < 0 || run >= b->nruns) return LBM_EINVAL;
+  const Geometry& g = b->geo[run];
+  const Ops* ops = ops_for(b->dim, b->storage);
+  char* cur = b->ws + (b->parity ? b->off1[run] : b->off0[run]);
+  double* st = reinterpret_cast<double*>(b->ws + (b->parity ? b->off0[run] : b->off1[run]));
+  const size_t plane = static_cast<size_t>(g.cells) * sizeof(double);
+  hipError_t e = ops->moments(g, b->coef[run], cur, st, nullptr, b->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(rho, st, plane, hipMemcpyDeviceToHost, b->stream);
+  if (e == hipSuccess && q) e = hipMemcpyAsync(q, st + g.cells, plane * g.dim, hipMemcpyDeviceToHost, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  return dev(e);
+}
+
+lbm_status lbm_batch_info(const lbm_batch* b, int64_t* total_cells, int64_t* tiles, int64_t* steps) {
+  if (!b) return LBM_EINVAL;
+  if (total_cells) *total_cells = b->total_cells;
+  if (tiles) *tiles = b->ntiles;
+  if (steps) *steps = b->steps;
+  return LBM_OK;
+}
+
+int32_t lbm_batch_tile_width(const lbm_batch* b, int32_t run) {
+  if (!b || run < 0 || run >= b->nruns) return -1;
+  return b->bx_of_class.at(b->cls[run]);
+}
+
+void lbm_batch_destroy(lbm_batch* b) {
+  if (!b) return;
+  destroy_graphs(b);
+  delete b;
+}
+
+}  // extern "C"

@@ -46,16 +46,24 @@ __device__ __forceinline__ void store_f32(float* p, float v) { *p = v; }
 __device__ __forceinline__ void store_f32(_Float16* p, float v) {
   *p = static_cast<_Float16>(v);  // round to nearest even
 }
-__device__ __forceinline__ void store_f32(bf16* p, float v) {
+__device__ __forceinline__ uint16_t bf16_bits(float v) {
   uint32_t u = __float_as_uint(v);
-  uint16_t out;
-  if ((u & 0x7fffffffu) > 0x7f800000u) {
-    out = static_cast<uint16_t>((u >> 16) | 0x40u);  // keep NaN a (quiet) NaN
-  } else {
-    u += 0x7fffu + ((u >> 16) & 1u);                 // round to nearest even
-    out = static_cast<uint16_t>(u >> 16);
-  }
-  p->bits = out;
+  if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>((u >> 16) | 0x40u);  // quiet NaN
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+  return static_cast<uint16_t>(u >> 16);
+}
+__device__ __forceinline__ void store_f32(bf16* p, float v) { p->bits = bf16_bits(v); }
+
+// Streaming stores for the step kernel: the next step reads these values from
+// HBM anyway (the state is far larger than the caches), so they are written
+// with the non-temporal hint and do not displace the neighbour lines that the
+// shifted loads of adjacent tiles still need.
+__device__ __forceinline__ void store_stream(float* p, float v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void store_stream(_Float16* p, float v) {
+  __builtin_nontemporal_store(static_cast<_Float16>(v), p);
+}
+__device__ __forceinline__ void store_stream(bf16* p, float v) {
+  __builtin_nontemporal_store(bf16_bits(v), reinterpret_cast<uint16_t*>(p));
 }
 
 // ----------------------------------------------------------------------------
@@ -144,6 +152,45 @@ __device__ __forceinline__ void collide(float (&g)[D + 1][2 * D + 1], const Coef
     const float w = (i == 0) ? k.w_rho : k.w_q;
 #pragma unroll
     for (int l = 0; l < 2 * D + 1; ++l) g[i][l] = __builtin_fmaf(w, eq[i][l] - g[i][l], g[i][l]);
+  }
+}
+
+
+// One lattice update of cell (x, y, z): gather the post-relaxation values of
+// the upwind neighbours (pull form of the transport phase: f_{+e_j}(t+dt, x)
+// = f*_{+e_j}(t, x - dx e_j), periodic), sum the moments, relax, and write the
+// cell's own post-relaxation values.  Every stored value is read once and
+// written once per step.  Used by the single-run and the batched kernels, so
+// both produce bit-identical states.
+template <int D, typename TR, typename TM>
+__device__ __forceinline__ void step_cell(const TR* __restrict__ sr, const TM* __restrict__ sm,
+                                          TR* __restrict__ dr, TM* __restrict__ dm, int x, int y,
+                                          int z, int nx, int ny, int nz, int64_t stride,
+                                          const Coef& k) {
+  const int64_t plane = static_cast<int64_t>(nx) * ny;
+  const int64_t c = static_cast<int64_t>(z) * plane + static_cast<int64_t>(y) * nx + x;
+  int64_t src[2 * D];
+  src[0] = (x == 0) ? c + (nx - 1) : c - 1;                                   // +x from x-1
+  src[1] = (x == nx - 1) ? c - (nx - 1) : c + 1;                              // -x from x+1
+  src[2] = (y == 0) ? c + static_cast<int64_t>(ny - 1) * nx : c - nx;         // +y from y-1
+  src[3] = (y == ny - 1) ? c - static_cast<int64_t>(ny - 1) * nx : c + nx;    // -y from y+1
+  if constexpr (D == 3) {
+    src[4] = (z == 0) ? c + static_cast<int64_t>(nz - 1) * plane : c - plane;      // +z
+    src[5] = (z == nz - 1) ? c - static_cast<int64_t>(nz - 1) * plane : c + plane; // -z
+  }
+  float g[D + 1][2 * D + 1];
+#pragma unroll
+  for (int i = 0; i < D + 1; ++i) {
+    g[i][0] = load_f32(sr + i * stride + c);
+#pragma unroll
+    for (int m = 0; m < 2 * D; ++m) g[i][1 + m] = load_f32(sm + (i * 2 * D + m) * stride + src[m]);
+  }
+  collide<D>(g, k);
+#pragma unroll
+  for (int i = 0; i < D + 1; ++i) {
+    store_stream(dr + i * stride + c, g[i][0]);
+#pragma unroll
+    for (int m = 0; m < 2 * D; ++m) store_stream(dm + (i * 2 * D + m) * stride + c, g[i][1 + m]);
   }
 }
 

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "lbm.h"
+#include "lbm_device.hpp"
 
 namespace lbm {
 
@@ -46,9 +47,41 @@ const Ops* ops_for(int dim, int storage);
 // Element sizes of a storage mode (rest planes, moving planes); false if unknown.
 bool storage_elems(int storage, size_t* rest_elem, size_t* move_elem);
 
+// Buffer geometry of one run (plane stride, region sizes) for a storage mode.
+Geometry make_geometry(int dim, int storage, const int64_t n[3]);
+
 // Whether a storage mode stores deviations from the reference equilibrium.
 bool storage_is_deviation(int storage);
 
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+
+template <typename R>
+inline CoefT<R> make_coef(const RunCoef& r, int D, bool deviation) {
+  CoefT<R> k;
+  k.c = static_cast<R>(1.0 / (2.0 * r.mu));
+  k.a_rho = static_cast<R>(r.alpha_rho);
+  k.a_q = static_cast<R>(r.alpha_q);
+  k.d2a_rho = static_cast<R>(2.0 * D * r.alpha_rho);
+  k.d2a_q = static_cast<R>(2.0 * D * r.alpha_q);
+  k.w_rho = static_cast<R>(r.omega_rho);
+  k.w_q = static_cast<R>(r.omega_q);
+  k.ref = static_cast<R>(deviation ? r.ref : 0.0);
+  return k;
+}
+
+template <typename TR, typename TM>
+struct PlaneSet {
+  TR* rest;  // [D+1][stride]
+  TM* move;  // [D+1][2D][stride]
+};
+
+template <typename TR, typename TM>
+__host__ __device__ inline PlaneSet<TR, TM> planes_of(void* base, size_t rest_bytes) {
+  PlaneSet<TR, TM> p;
+  p.rest = reinterpret_cast<TR*>(base);
+  p.move = reinterpret_cast<TM*>(reinterpret_cast<char*>(base) + rest_bytes);
+  return p;
+}
+
 
 }  // namespace lbm

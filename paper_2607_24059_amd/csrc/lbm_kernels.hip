@@ -14,34 +14,6 @@
 namespace lbm {
 namespace {
 
-template <typename R>
-CoefT<R> make_coef(const RunCoef& r, int D, bool deviation) {
-  CoefT<R> k;
-  k.c = static_cast<R>(1.0 / (2.0 * r.mu));
-  k.a_rho = static_cast<R>(r.alpha_rho);
-  k.a_q = static_cast<R>(r.alpha_q);
-  k.d2a_rho = static_cast<R>(2.0 * D * r.alpha_rho);
-  k.d2a_q = static_cast<R>(2.0 * D * r.alpha_q);
-  k.w_rho = static_cast<R>(r.omega_rho);
-  k.w_q = static_cast<R>(r.omega_q);
-  k.ref = static_cast<R>(deviation ? r.ref : 0.0);
-  return k;
-}
-
-template <typename TR, typename TM>
-struct PlaneSet {
-  TR* rest;  // [D+1][stride]
-  TM* move;  // [D+1][2D][stride]
-};
-
-template <typename TR, typename TM>
-__host__ __device__ inline PlaneSet<TR, TM> planes_of(void* base, size_t rest_bytes) {
-  PlaneSet<TR, TM> p;
-  p.rest = reinterpret_cast<TR*>(base);
-  p.move = reinterpret_cast<TM*>(reinterpret_cast<char*>(base) + rest_bytes);
-  return p;
-}
-
 // ----------------------------------------------------------------------------
 // init: every population at the equilibrium of W0 = (rho0, dx rho0 u0)
 // ----------------------------------------------------------------------------
@@ -70,11 +42,7 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ u0,
 }
 
 // ----------------------------------------------------------------------------
-// step: pull transport fused with relaxation.
-//   f_{+e_j}(t+dt, x) = f*_{+e_j}(t, x - dx e_j): the post-relaxation state is
-//   what is stored, so a cell gathers the stored values of its upwind
-//   neighbours, sums the moments, relaxes and writes its own cell.  Each
-//   stored value is read exactly once per step and written exactly once.
+// step: one thread per cell, pull transport fused with relaxation (step_cell)
 // ----------------------------------------------------------------------------
 template <int D, typename TR, typename TM>
 __global__ __launch_bounds__(256) void k_step(const TR* __restrict__ sr,
@@ -85,31 +53,7 @@ __global__ __launch_bounds__(256) void k_step(const TR* __restrict__ sr,
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= nx || y >= ny) return;
-  const int64_t plane = static_cast<int64_t>(nx) * ny;
-  const int64_t c = static_cast<int64_t>(z) * plane + static_cast<int64_t>(y) * nx + x;
-  int64_t src[2 * D];
-  src[0] = (x == 0) ? c + (nx - 1) : c - 1;                                   // +x from x-1
-  src[1] = (x == nx - 1) ? c - (nx - 1) : c + 1;                              // -x from x+1
-  src[2] = (y == 0) ? c + static_cast<int64_t>(ny - 1) * nx : c - nx;         // +y from y-1
-  src[3] = (y == ny - 1) ? c - static_cast<int64_t>(ny - 1) * nx : c + nx;    // -y from y+1
-  if constexpr (D == 3) {
-    src[4] = (z == 0) ? c + static_cast<int64_t>(nz - 1) * plane : c - plane;      // +z
-    src[5] = (z == nz - 1) ? c - static_cast<int64_t>(nz - 1) * plane : c + plane; // -z
-  }
-  float g[D + 1][2 * D + 1];
-#pragma unroll
-  for (int i = 0; i < D + 1; ++i) {
-    g[i][0] = load_f32(sr + i * stride + c);
-#pragma unroll
-    for (int m = 0; m < 2 * D; ++m) g[i][1 + m] = load_f32(sm + (i * 2 * D + m) * stride + src[m]);
-  }
-  collide<D>(g, k);
-#pragma unroll
-  for (int i = 0; i < D + 1; ++i) {
-    store_f32(dr + i * stride + c, g[i][0]);
-#pragma unroll
-    for (int m = 0; m < 2 * D; ++m) store_f32(dm + (i * 2 * D + m) * stride + c, g[i][1 + m]);
-  }
+  step_cell<D, TR, TM>(sr, sm, dr, dm, x, y, z, nx, ny, nz, stride, k);
 }
 
 // ----------------------------------------------------------------------------
@@ -310,13 +254,14 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_final(const double* __res
 }
 
 // ----------------------------------------------------------------------------
-// copy probe: 16-byte loads and stores, grid-stride
+// copy probe: one 16-byte load and store per thread, one block per 4 KiB
+// (the fastest of the copy shapes measured on MI355X: grid-stride loops and
+// several vectors per thread were slower)
 // ----------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_copy(const float4* __restrict__ src, float4* __restrict__ dst,
                                               int64_t n) {
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
-    dst[i] = src[i];
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
 }
 
 // ----------------------------------------------------------------------------
@@ -421,13 +366,29 @@ bool storage_elems(int storage, size_t* rest_elem, size_t* move_elem) {
   return false;
 }
 
+Geometry make_geometry(int dim, int storage, const int64_t n[3]) {
+  Geometry g;
+  g.dim = dim;
+  g.nx = static_cast<int32_t>(n[0]);
+  g.ny = static_cast<int32_t>(n[1]);
+  g.nz = static_cast<int32_t>(n[2]);
+  g.cells = n[0] * n[1] * n[2];
+  g.stride = (g.cells + 255) / 256 * 256;
+  storage_elems(storage, &g.rest_elem, &g.move_elem);
+  const int ns = dim + 1;
+  auto align = [](size_t v) { return (v + 255) / 256 * 256; };
+  g.rest_bytes = align(static_cast<size_t>(ns) * g.stride * g.rest_elem);
+  g.buf_bytes = align(g.rest_bytes + static_cast<size_t>(ns) * 2 * dim * g.stride * g.move_elem);
+  return g;
+}
+
 bool storage_is_deviation(int storage) { return storage != LBM_F32_RAW; }
 
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
   const int64_t n = static_cast<int64_t>(bytes / 16);
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 256 * 64) blocks = 256 * 64;
-  if (blocks < 1) blocks = 1;
+  if (n == 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_copy, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
                      reinterpret_cast<const float4*>(src), reinterpret_cast<float4*>(dst), n);
   return hipGetLastError();
