@@ -1,0 +1,76 @@
+/*
+ * lbm_closure.h - device-side pieces of the learned coarse-grid correction.
+ *
+ * The paper has no closure; these entry points connect a coarse run of the
+ * scheme (an lbm_ctx) with the correction network of lbm_cnn.h:
+ *
+ *   restriction   fine moments -> coarse moments (block averages)
+ *   features      coarse moments -> normalised network input
+ *   reset         populations <- equilibrium of given device moments
+ *   correction    populations += f^eq(W + dW) - f^eq(W) behind a guard
+ *
+ * Moments are device FP32 planes [(1 + dim)][cells] holding rho, then the
+ * physical momentum q_j (as lbm_moments_device writes them).  Every call is
+ * enqueued on the context's stream (or the given one) and is asynchronous,
+ * except lbm_closure_report which synchronises.
+ */
+#ifndef LBM_CLOSURE_H
+#define LBM_CLOSURE_H
+
+#include "lbm.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* 2D restriction by r x r block averages (nfx, nfy multiples of r):
+ *   q_c = mean(q_f),  rho_c = rho_ref + r^2 (mean(rho_f) - rho_ref)
+ * The density deviation carries the pressure, rho - rho_ref ~ dx^2 Phi
+ * (Proposition 1), so the same pressure field has an r^2 larger density
+ * deviation on the r-times coarser grid. */
+lbm_status lbm_restrict(const float* fine, int64_t nfx, int64_t nfy, int32_t r, double rho_ref,
+                        float* coarse, void* stream);
+
+/* Network input x[(1 + dim)][cells]: x0 = (rho - rho_ref)/s_rho, x_{1+j} = (q_j/rho)/s_u. */
+lbm_status lbm_closure_features(const float* moments, int32_t dim, int64_t cells, double rho_ref,
+                                float s_rho, float s_u, float* x, void* stream);
+
+/* Training target of a window (2D): t0 = (rho_next - rho_now)/s_drho,
+ * t_{1+j} = (q_next_j - q_now_j)/s_dq, for [3][cells] moment planes. */
+lbm_status lbm_closure_target(const float* m_next, const float* m_now, int64_t cells, float s_drho,
+                              float s_dq, float* t, void* stream);
+
+/* Replace the state of ctx by the equilibrium of the device moments (end of
+ * Section 2: populations at equilibrium); the step count is kept. */
+lbm_status lbm_set_equilibrium_device(lbm_ctx* ctx, const float* moments);
+
+/* Guarded correction of a 2D context from the network output y[3][cells]:
+ *   dW = (y0 s_drho, y1 s_dq, y2 s_dq), each channel minus its grid mean (so
+ *   mass and momentum are unchanged);
+ *   accept iff every corrected value is finite and
+ *   ||div_h u'||_2 <= guard_factor ||div_h u||_2, u = q/rho, u' = (q+dq)/(rho+drho),
+ *   centred differences on the periodic grid, u from `moments`;
+ *   if accepted, every population gets f^eq(W + dW) - f^eq(W) added, W being
+ *   the moments of the current state (the non-equilibrium part is kept).
+ * The decision is taken on the device (no host round trip); read it with
+ * lbm_closure_report. */
+lbm_status lbm_closure_apply(lbm_ctx* ctx, const float* moments, const float* y, float s_drho, float s_dq,
+                             float guard_factor);
+
+typedef struct lbm_closure_report {
+  int64_t n_accepted; /* corrections applied since lbm_init */
+  int64_t n_rejected; /* corrections refused by the guard since lbm_init */
+  int32_t accepted;   /* 1 if the last correction was applied */
+  double div_before;  /* ||div_h u||_2 before */
+  double div_after;   /* ||div_h u'||_2 of the proposed correction */
+  double mean[3];     /* grid means removed from the three output channels (physical units) */
+} lbm_closure_report;
+
+/* Report of the last lbm_closure_apply on ctx.  Synchronises. */
+lbm_status lbm_closure_report_get(lbm_ctx* ctx, lbm_closure_report* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_CLOSURE_H */

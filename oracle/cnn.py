@@ -38,7 +38,20 @@ def init_params(seed: int = 0, layers=LAYERS) -> list:
     return params
 
 
-def conv(x: np.ndarray, w: np.ndarray, b: np.ndarray | None) -> np.ndarray:
+def _ident(a):
+    return a
+
+
+def bf16_round(a):
+    """Round to the nearest BF16 value (ties to even), as float64: the operand
+    precision of a BF16 matrix multiply with FP32 accumulation."""
+    u = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def conv(x: np.ndarray, w: np.ndarray, b: np.ndarray | None, rnd=_ident) -> np.ndarray:
+    x, w = rnd(x), rnd(w)
     bsz, cin, h, wd = x.shape
     cout = w.shape[0]
     y = np.zeros((bsz, cout, h, wd))
@@ -50,8 +63,11 @@ def conv(x: np.ndarray, w: np.ndarray, b: np.ndarray | None) -> np.ndarray:
     return y
 
 
-def conv_backward(x: np.ndarray, w: np.ndarray, dy_: np.ndarray):
-    """Gradients of Y = conv(X, W) + b given dL/dY: (dX, dW, db)."""
+def conv_backward(x: np.ndarray, w: np.ndarray, dy_: np.ndarray, rnd=_ident):
+    """Gradients of Y = conv(X, W) + b given dL/dY: (dX, dW, db).  `rnd` is
+    applied to the operands of the products (not to the bias sum)."""
+    db = dy_.sum(axis=(0, 2, 3))
+    x, w, dy_ = rnd(x), rnd(w), rnd(dy_)
     dw = np.zeros_like(w)
     dx_ = np.zeros_like(x)
     for (dy, dx) in TAPS:
@@ -59,22 +75,21 @@ def conv_backward(x: np.ndarray, w: np.ndarray, dy_: np.ndarray):
         dw[:, :, dy + 1, dx + 1] = np.einsum("bohw,bchw->oc", dy_, xs)
         # Y[y] gets W X[y + d]  =>  dX[z] += W^T dY[z - d]
         dx_ += np.einsum("oc,bohw->bchw", w[:, :, dy + 1, dx + 1], shifted(dy_, -dy, -dx))
-    db = dy_.sum(axis=(0, 2, 3))
     return dx_, dw, db
 
 
-def forward(params: list, x: np.ndarray):
+def forward(params: list, x: np.ndarray, rnd=_ident):
     """Returns (output, cache) with cache = list of (input, pre-activation) per layer."""
     cache = []
     a = x
     for li, (w, b) in enumerate(params):
-        z = conv(a, w, b)
+        z = conv(a, w, b, rnd)
         cache.append((a, z))
         a = np.maximum(z, 0.0) if li < len(params) - 1 else z
     return a, cache
 
 
-def backward(params: list, cache: list, dout: np.ndarray):
+def backward(params: list, cache: list, dout: np.ndarray, rnd=_ident):
     """dL/dparams (list of (dW, db)) and dL/dx from dL/doutput."""
     grads = [None] * len(params)
     d = dout
@@ -82,7 +97,7 @@ def backward(params: list, cache: list, dout: np.ndarray):
         a_in, z = cache[li]
         if li < len(params) - 1:
             d = d * (z > 0.0)
-        dx_, dw, db = conv_backward(a_in, params[li][0], d)
+        dx_, dw, db = conv_backward(a_in, params[li][0], d, rnd)
         grads[li] = (dw, db)
         d = dx_
     return grads, d

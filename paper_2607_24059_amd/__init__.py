@@ -4,6 +4,6 @@ The compute path is the HIP library liblbm.so (csrc/, C ABI in include/lbm.h);
 `lbm` is its ctypes binding.  torch supplies device memory and streams only.
 """
 
-from . import batch, lbm  # noqa: F401
+from . import batch, closure, cnn, lbm  # noqa: F401
 
-__all__ = ["lbm", "batch"]
+__all__ = ["lbm", "batch", "cnn", "closure"]

@@ -1,0 +1,430 @@
+"""Learned coarse-grid correction: bindings of include/lbm_closure.h and the
+driver that generates data, trains the network and evaluates it.
+
+Workload (defaults): coarse 256^2 runs of the D2Q5 scheme corrected every 4
+coarse steps by the four-layer 3x3 network of `cnn`; training data from 2048^2
+fine runs of the same scheme (nu = 5e-4, k^-3 random fields at coarse Mach
+0.05, mu = 8 on both grids so one coarse step is 64 fine steps), restricted
+8x to the coarse grid; judged against held-out fine runs; the guard falls back
+to the plain coarse step when the correction would more than double the
+discrete divergence norm.
+
+Every numerical step runs in liblbm.so; this module sequences calls and keeps
+device buffers (torch tensors) and a few host scalars (normalisation scales,
+errors).
+
+    python -m paper_2607_24059_amd.closure --train-seeds 200 --test-seeds 20 --out model.npz
+"""
+
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import math
+import sys
+import time
+from dataclasses import asdict, dataclass, field
+
+import numpy as np
+
+from . import cnn
+from .lbm import Engine, _ok, lib, make_params
+
+
+class lbm_closure_report(C.Structure):
+    _fields_ = [("n_accepted", C.c_int64), ("n_rejected", C.c_int64), ("accepted", C.c_int32), ("div_before", C.c_double), ("div_after", C.c_double),
+                ("mean", C.c_double * 3)]
+
+
+SIGNATURES = {
+    "lbm_restrict": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_int32, C.c_double, C.c_void_p, C.c_void_p]),
+    "lbm_closure_features": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_float, C.c_float,
+                                       C.c_void_p, C.c_void_p]),
+    "lbm_closure_target": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_float, C.c_float, C.c_void_p,
+                                     C.c_void_p]),
+    "lbm_set_equilibrium_device": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lbm_closure_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_float, C.c_float, C.c_float]),
+    "lbm_closure_report_get": (C.c_int, [C.c_void_p, C.POINTER(lbm_closure_report)]),
+}
+
+_bound = False
+
+
+def xlib():
+    global _bound
+    L = lib()
+    if not _bound:
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _bound = True
+    return L
+
+
+def _p(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def lbm_restrict(fine, nfx, nfy, r, rho_ref, coarse, stream):
+    _ok(xlib().lbm_restrict(_p(fine), nfx, nfy, r, rho_ref, _p(coarse), C.c_void_p(stream.cuda_stream)),
+        "lbm_restrict")
+
+
+def lbm_closure_features(moments, dim, cells, rho_ref, s_rho, s_u, x, stream):
+    _ok(xlib().lbm_closure_features(_p(moments), dim, cells, rho_ref, s_rho, s_u, _p(x),
+                                    C.c_void_p(stream.cuda_stream)), "lbm_closure_features")
+
+
+def lbm_closure_target(m_next, m_now, cells, s_drho, s_dq, t, stream):
+    _ok(xlib().lbm_closure_target(_p(m_next), _p(m_now), cells, s_drho, s_dq, _p(t),
+                                  C.c_void_p(stream.cuda_stream)), "lbm_closure_target")
+
+
+def lbm_set_equilibrium_device(ctx, moments):
+    _ok(xlib().lbm_set_equilibrium_device(C.c_void_p(ctx), _p(moments)), "lbm_set_equilibrium_device")
+
+
+def lbm_closure_apply(ctx, moments, y, s_drho, s_dq, guard_factor):
+    _ok(xlib().lbm_closure_apply(C.c_void_p(ctx), _p(moments), _p(y), s_drho, s_dq, guard_factor),
+        "lbm_closure_apply")
+
+
+def lbm_closure_report_get(ctx):
+    r = lbm_closure_report()
+    _ok(xlib().lbm_closure_report_get(C.c_void_p(ctx), C.byref(r)), "lbm_closure_report_get")
+    return {"n_accepted": r.n_accepted, "n_rejected": r.n_rejected, "accepted": bool(r.accepted), "div_before": r.div_before, "div_after": r.div_after,
+            "mean": list(r.mean)}
+
+
+# --------------------------------------------------------------------------- #
+# driver                                                                      #
+# --------------------------------------------------------------------------- #
+
+@dataclass
+class Config:
+    coarse_n: int = 256
+    factor: int = 8
+    nu: float = 5e-4
+    mach: float = 0.05
+    mu: float = 8.0
+    every: int = 4                 # coarse steps between corrections
+    pairs_per_seed: int = 16       # training pairs (4-coarse-step windows) per fine run
+    train_seeds: list = field(default_factory=lambda: list(range(200)))
+    test_seeds: list = field(default_factory=lambda: list(range(1000, 1020)))
+    horizon: int = 256             # coarse steps of each evaluation run (and training span)
+    batch: int = 8
+    epochs: int = 20
+    lr: float = 1e-3
+    guard: float = 2.0
+    eval_levels: tuple = (256, 512, 1024)
+
+    @property
+    def fine_n(self):
+        return self.coarse_n * self.factor
+
+    def dx(self, n):
+        return 2 * math.pi / n
+
+    def umax(self):
+        """Physical speed bound: Mach 0.05 on the coarse grid (dx_c max|u| = 0.05)."""
+        return self.mach / self.dx(self.coarse_n)
+
+
+def _engine(cfg: Config, n: int, u0=None, storage="f32"):
+    dx = cfg.dx(n)
+    prm = make_params(2, (n, n), dx, dx * dx / cfg.mu, cfg.nu, storage=storage)
+    if u0 is None:
+        u0 = np.zeros((2, n, n))
+    return Engine.create(prm, u0)
+
+
+def _field(cfg: Config, n: int, seed: int):
+    import inputs
+    return inputs.random_field_2d(n, seed, umax=cfg.umax())
+
+
+class FineRun:
+    """One fine run of the scheme; its moments restricted to coarser grids on request."""
+
+    def __init__(self, cfg: Config, seed: int, stream):
+        import torch
+        self.cfg = cfg
+        self.nf = cfg.fine_n
+        self.stream = stream
+        self.eng = _engine(cfg, self.nf, _field(cfg, self.nf, seed))
+        self.m = torch.empty((3, self.nf, self.nf), dtype=torch.float32, device="cuda")
+
+    def advance(self, coarse_steps: int) -> None:
+        # mu fixed on both grids: one coarse step is factor^2 fine steps
+        self.eng.step(coarse_steps * self.cfg.factor ** 2)
+
+    def restricted(self, n: int, out) -> None:
+        self.eng.moments_device(self.m)
+        lbm_restrict(self.m, self.nf, self.nf, self.nf // n, 1.0, out, self.stream)
+
+    def close(self):
+        self.eng.close()
+
+
+def coarse_after(cfg: Config, eng: Engine, m0, out):
+    """Coarse moments after `every` plain steps from the equilibrium of m0."""
+    lbm_set_equilibrium_device(eng.ctx, m0)
+    eng.step(cfg.every)
+    eng.moments_device(out)
+
+
+def build_dataset(cfg: Config, log=print):
+    """Pairs (coarse state after `every` steps from a restricted fine snapshot,
+    restricted fine snapshot `every` coarse steps later), windows spread over
+    the evaluation horizon; returns the network inputs, targets and scales."""
+    import torch
+    s = torch.cuda.current_stream()
+    nc = cfg.coarse_n
+    cells = nc * nc
+    stride = max(cfg.every, cfg.horizon // cfg.pairs_per_seed)
+    P = len(cfg.train_seeds) * cfg.pairs_per_seed
+    mc = torch.empty((P, 3, nc, nc), dtype=torch.float32, device="cuda")
+    mn = torch.empty_like(mc)
+    m_start = torch.empty((3, nc, nc), dtype=torch.float32, device="cuda")
+    rng = np.random.default_rng(12345)
+    perm = rng.permutation(P)  # shuffled storage order: minibatches are contiguous slices
+    ceng = _engine(cfg, nc)
+    t0 = time.time()
+    for si, seed in enumerate(cfg.train_seeds):
+        fine = FineRun(cfg, seed, s)
+        for k in range(cfg.pairs_per_seed):
+            j = int(perm[si * cfg.pairs_per_seed + k])
+            fine.restricted(nc, m_start)
+            coarse_after(cfg, ceng, m_start, mc[j])
+            fine.advance(cfg.every)
+            fine.restricted(nc, mn[j])
+            fine.advance(stride - cfg.every)
+        fine.close()
+        if si % 20 == 0:
+            torch.cuda.synchronize()
+            log(f"[closure] data seed {seed} ({si + 1}/{len(cfg.train_seeds)}) {time.time() - t0:.1f}s")
+    ceng.close()
+    # scales: rms of the raw features and of the raw moment differences
+    x = torch.empty_like(mc)
+    t = torch.empty_like(mc)
+    for i in range(P):
+        lbm_closure_features(mc[i], 2, cells, 1.0, 1.0, 1.0, x[i], s)
+        lbm_closure_target(mn[i], mc[i], cells, 1.0, 1.0, t[i], s)
+    picks = range(0, P, max(1, P // 64))
+    raw = np.zeros(3)
+    rawd = np.zeros(3)
+    for i in picks:
+        raw += cnn.channel_rms(x[i], 3, s).cpu().numpy() ** 2
+        rawd += cnn.channel_rms(t[i], 3, s).cpu().numpy() ** 2
+    raw = np.sqrt(raw / len(picks))
+    rawd = np.sqrt(rawd / len(picks))
+    scales = {"s_rho": float(raw[0]), "s_u": float(math.sqrt((raw[1] ** 2 + raw[2] ** 2) / 2)),
+              "s_drho": float(rawd[0]), "s_dq": float(math.sqrt((rawd[1] ** 2 + rawd[2] ** 2) / 2))}
+    for i in range(P):
+        lbm_closure_features(mc[i], 2, cells, 1.0, scales["s_rho"], scales["s_u"], x[i], s)
+        lbm_closure_target(mn[i], mc[i], cells, scales["s_drho"], scales["s_dq"], t[i], s)
+    torch.cuda.synchronize()
+    log(f"[closure] dataset: {P} pairs, scales {scales}, {time.time() - t0:.1f}s")
+    return x, t, scales
+
+
+def train(cfg: Config, x, t, log=print, seed: int = 0):
+    import torch
+    net = cnn.Net(seed=seed)
+    P = x.shape[0]
+    B = cfg.batch
+    nb = P // B
+    grad = torch.empty((B,) + tuple(x.shape[1:]), dtype=torch.float32, device="cuda")
+    scratch = torch.empty(cnn.lbm_reduce_scratch_bytes(grad.numel()) // 4, dtype=torch.float32, device="cuda")
+    losses = torch.zeros(nb, dtype=torch.float64, device="cuda")
+    rng = np.random.default_rng(seed)
+    history = []
+    t0 = time.time()
+    step = 0
+    total = cfg.epochs * nb
+    for ep in range(cfg.epochs):
+        order = rng.permutation(nb)
+        for bi in order:
+            lr = cfg.lr * 0.5 * (1 + math.cos(math.pi * step / total))  # cosine schedule
+            xb = x[bi * B:(bi + 1) * B]
+            tb = t[bi * B:(bi + 1) * B]
+            out = net.forward(xb)
+            cnn.mse(out, tb, grad, net.stream, scratch, losses[bi:bi + 1])
+            net.backward(grad)
+            net.adam_step(lr=lr)
+            step += 1
+        mean_loss = float(losses.mean().item())
+        history.append(mean_loss)
+        log(f"[closure] epoch {ep + 1}/{cfg.epochs} mean batch loss {mean_loss:.4e} ({time.time() - t0:.1f}s)")
+    return net, history
+
+
+def _host(m):
+    return m.double().cpu().numpy()
+
+
+def rel_u(m, ref):
+    """Relative L2 error of u = q/rho on the coarse grid (host arrays [3][n][n])."""
+    u = m[1:] / m[0:1]
+    ur = ref[1:] / ref[0:1]
+    return float(np.linalg.norm((u - ur).ravel()) / np.linalg.norm(ur.ravel()))
+
+
+def evaluate(cfg: Config, net, scales, log=print, seeds=None, storage="f32", levels=None):
+    """Errors against the restricted fine judge after `horizon` coarse steps for
+    the plain scheme at each level and for the corrected coarse run, plus the
+    wall time of each run (HIP events)."""
+    import torch
+    s = torch.cuda.current_stream()
+    nc = cfg.coarse_n
+    cells = nc * nc
+    seeds = cfg.test_seeds if seeds is None else seeds
+    levels = cfg.eval_levels if levels is None else levels
+    chunks = cfg.horizon // cfg.every
+    res = {"plain": {n: [] for n in levels}, "closure": [], "time_plain": {n: 0.0 for n in levels},
+           "time_closure": 0.0, "accepted": 0, "rejected": 0}
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    mbuf = torch.empty((3, nc, nc), dtype=torch.float32, device="cuda")
+    xbuf = torch.empty((1, 3, nc, nc), dtype=torch.float32, device="cuda")
+    for seed in seeds:
+        fine = FineRun(cfg, seed, s)
+        starts = {}
+        for n in levels:
+            starts[n] = torch.empty((3, n, n), dtype=torch.float32, device="cuda")
+            fine.restricted(n, starts[n])
+        fine.advance(cfg.horizon)
+        judge = torch.empty((3, nc, nc), dtype=torch.float32, device="cuda")
+        fine.restricted(nc, judge)
+        fine.close()
+        judge_h = _host(judge)
+        for n in levels:
+            eng = _engine(cfg, n, storage=storage)
+            lbm_set_equilibrium_device(eng.ctx, starts[n])
+            torch.cuda.synchronize()
+            ev0.record(s)
+            eng.step(cfg.horizon * (n // nc) ** 2)
+            ev1.record(s)
+            mm = torch.empty((3, n, n), dtype=torch.float32, device="cuda")
+            eng.moments_device(mm)
+            lbm_restrict(mm, n, n, n // nc, 1.0, mbuf, s)
+            torch.cuda.synchronize()
+            res["time_plain"][n] += ev0.elapsed_time(ev1)
+            res["plain"][n].append(rel_u(_host(mbuf), judge_h))
+            eng.close()
+        eng = _engine(cfg, nc, storage=storage)
+        lbm_set_equilibrium_device(eng.ctx, starts[nc])
+        torch.cuda.synchronize()
+        ev0.record(s)
+        for _ in range(chunks):
+            eng.step(cfg.every)
+            eng.moments_device(mbuf)
+            lbm_closure_features(mbuf, 2, cells, 1.0, scales["s_rho"], scales["s_u"], xbuf, s)
+            y = net.forward(xbuf)
+            lbm_closure_apply(eng.ctx, mbuf, y, scales["s_drho"], scales["s_dq"], cfg.guard)
+        ev1.record(s)
+        torch.cuda.synchronize()
+        res["time_closure"] += ev0.elapsed_time(ev1)
+        rep = lbm_closure_report_get(eng.ctx)
+        res["accepted"] += rep["n_accepted"]
+        res["rejected"] += rep["n_rejected"]
+        eng.moments_device(mbuf)
+        res["closure"].append(rel_u(_host(mbuf), judge_h))
+        eng.close()
+        log(f"[closure] seed {seed}: plain " + ", ".join(f"{n}: {res['plain'][n][-1]:.3e}" for n in levels)
+            + f"; corrected {nc}: {res['closure'][-1]:.3e} (accepted {rep['n_accepted']}, "
+              f"rejected {rep['n_rejected']})")
+    out = {"plain": {str(n): float(np.mean(v)) for n, v in res["plain"].items()},
+           "closure": float(np.mean(res["closure"])),
+           "per_seed_plain_coarse": res["plain"][nc], "per_seed_closure": res["closure"],
+           "time_plain_ms": {str(n): res["time_plain"][n] / len(seeds) for n in levels},
+           "time_closure_ms": res["time_closure"] / len(seeds),
+           "accepted": res["accepted"], "rejected": res["rejected"], "seeds": list(seeds),
+           "horizon": cfg.horizon, "storage": storage}
+    out["speedup_equal_error"] = equal_error_speedup(out)
+    return out
+
+
+def equal_error_speedup(ev: dict):
+    """Resolution N* at which the plain scheme's error equals the corrected
+    run's, by log-log interpolation over the evaluated levels; speedup =
+    T_plain(N*) / T_closure with T_plain interpolated log-log as well."""
+    levels = sorted(int(n) for n in ev["plain"])
+    e = np.array([ev["plain"][str(n)] for n in levels])
+    tp = np.array([ev["time_plain_ms"][str(n)] for n in levels])
+    ec = ev["closure"]
+    if len(levels) < 2 or not ec < e[0]:
+        return {"N_star": float(levels[0]), "speedup": float(tp[0] / ev["time_closure_ms"]), "note": "no gain"}
+    ln, le, lt = np.log(levels), np.log(e), np.log(tp)
+    for i in range(len(levels) - 1):
+        if le[i + 1] <= math.log(ec) <= le[i]:
+            f = (math.log(ec) - le[i]) / (le[i + 1] - le[i])
+            nstar = math.exp(ln[i] + f * (ln[i + 1] - ln[i]))
+            tstar = math.exp(lt[i] + f * (lt[i + 1] - lt[i]))
+            return {"N_star": nstar, "speedup": tstar / ev["time_closure_ms"], "note": "interpolated"}
+    i = len(levels) - 2
+    slope_e = (le[i + 1] - le[i]) / (ln[i + 1] - ln[i])
+    slope_t = (lt[i + 1] - lt[i]) / (ln[i + 1] - ln[i])
+    if slope_e >= 0:
+        return {"N_star": float("nan"), "speedup": float("nan"), "note": "plain error not decreasing"}
+    lnstar = ln[i + 1] + (math.log(ec) - le[i + 1]) / slope_e
+    tstar = math.exp(lt[i + 1] + slope_t * (lnstar - ln[i + 1]))
+    return {"N_star": math.exp(lnstar), "speedup": tstar / ev["time_closure_ms"], "note": "extrapolated"}
+
+
+def save_model(path, net, scales, cfg, history, evaluation=None):
+    flat = net.p.double().cpu().numpy()
+    meta = {"scales": scales, "config": {k: (list(v) if isinstance(v, tuple) else v)
+                                         for k, v in asdict(cfg).items()},
+            "history": history, "evaluation": evaluation}
+    np.savez(path, params=flat, meta=json.dumps(meta))
+
+
+def load_model(path):
+    z = np.load(path, allow_pickle=False)
+    meta = json.loads(str(z["meta"]))
+    flat = z["params"]
+    params, off = [], 0
+    for cin, cout in cnn.LAYERS:
+        nw = cout * cin * 9
+        params.append((flat[off:off + nw].reshape(cout, cin, 3, 3), flat[off + nw:off + nw + cout]))
+        off += nw + cout
+    return params, meta
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train-seeds", type=int, default=200)
+    ap.add_argument("--test-seeds", type=int, default=20)
+    ap.add_argument("--pairs", type=int, default=16)
+    ap.add_argument("--horizon", type=int, default=256)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--out", default="closure_model.npz")
+    ap.add_argument("--json", default=None)
+    args = ap.parse_args(argv)
+    import torch
+    torch.cuda.set_device(0)
+    cfg = Config(train_seeds=list(range(args.train_seeds)),
+                 test_seeds=list(range(1000, 1000 + args.test_seeds)),
+                 pairs_per_seed=args.pairs, horizon=args.horizon, epochs=args.epochs, lr=args.lr)
+
+    def log(*a):
+        print(*a, file=sys.stderr, flush=True)
+
+    x, t, scales = build_dataset(cfg, log)
+    net, hist = train(cfg, x, t, log)
+    del x, t
+    ev = evaluate(cfg, net, scales, log)
+    save_model(args.out, net, scales, cfg, hist, ev)
+    out = {"scales": scales, "loss_history": hist, "evaluation": ev}
+    if args.json:
+        with open(args.json, "w") as fh:
+            json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -14,25 +14,7 @@ using lbm::Geometry;
 using lbm::Ops;
 using lbm::RunCoef;
 
-struct lbm_ctx {
-  lbm_params p;
-  double mu;
-  double alpha_q;
-  uint32_t flags;
-  Geometry g;
-  const Ops* ops;
-  RunCoef coef;
-  char* ws;
-  size_t ws_bytes;
-  char* cur;        // buffer holding the state at step `steps`
-  char* nxt;        // the other buffer (also used as staging between steps)
-  double* partials; // diagnostics per-block partials
-  double* result;   // diagnostics final slots
-  int64_t diag_blocks;
-  hipStream_t stream;
-  int64_t steps;
-  int bx, by;       // step kernel block shape
-};
+
 
 namespace {
 
@@ -101,7 +83,8 @@ size_t lbm_workspace_bytes(const lbm_params* p) {
   const Geometry g = geometry(p);
   const Ops* o = lbm::ops_for(p->dim, p->storage);
   if (!o) return 0;
-  const size_t scratch = align_up(static_cast<size_t>(o->diag_blocks(g) + 1) * kDiagSlots * sizeof(double));
+  // diagnostics partials + final slots, then 16 doubles of closure slots
+  const size_t scratch = align_up((static_cast<size_t>(o->diag_blocks(g) + 1) * kDiagSlots + 16) * sizeof(double));
   return 2 * g.buf_bytes + scratch;
 }
 
@@ -135,6 +118,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const 
   c->partials = reinterpret_cast<double*>(c->ws + 2 * g.buf_bytes);
   c->diag_blocks = c->ops->diag_blocks(g);
   c->result = c->partials + c->diag_blocks * kDiagSlots;
+  c->closure_slots = c->result + kDiagSlots;
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->steps = 0;
   default_block(g, &c->bx, &c->by);
@@ -148,6 +132,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const 
     e = hipMemcpyAsync(sr, rho0, static_cast<size_t>(g.cells) * sizeof(double), hipMemcpyHostToDevice,
                        c->stream);
   if (e == hipSuccess) e = c->ops->init(g, c->coef, su, sr, c->cur, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->closure_slots, 0, 16 * sizeof(double), c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     delete c;

@@ -1,0 +1,308 @@
+// Device-side pieces of the learned coarse-grid correction (contract in
+// include/lbm_closure.h): restriction, network features, reset to equilibrium
+// and the guarded moment correction.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <string.h>
+
+#include "lbm.h"
+#include "lbm_closure.h"
+#include "lbm_device.hpp"
+#include "lbm_internal.hpp"
+
+namespace lbm {
+namespace {
+
+constexpr int kThreads = 256;
+
+// closure scratch slots (doubles) in the context workspace
+constexpr int kSlotMean = 0;      // 0..3: grid means of the three channels (physical units)
+constexpr int kSlotAccept = 4;    // 1.0 if accepted
+constexpr int kSlotDiv0 = 5;      // ||div u||
+constexpr int kSlotDiv1 = 6;      // ||div u'||
+constexpr int kSlotNacc = 7;      // running count of accepted corrections
+constexpr int kSlotNrej = 8;      // running count of rejected corrections
+
+__device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+__device__ double block_sum(double v) {
+  __shared__ double red[kThreads / 64];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < kThreads / 64; ++i) s += red[i];
+  return s;
+}
+
+// --------------------------------------------------------------------------
+__global__ void k_restrict(const float* __restrict__ fine, int nfx, int nfy, int r, double rho_ref,
+                           float* __restrict__ coarse) {
+  const int ncx = nfx / r, ncy = nfy / r;
+  const int64_t cc = static_cast<int64_t>(ncx) * ncy;
+  const int64_t fc = static_cast<int64_t>(nfx) * nfy;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= 3 * cc) return;
+  const int ch = static_cast<int>(idx / cc);
+  const int64_t c = idx % cc;
+  const int cx = static_cast<int>(c % ncx), cy = static_cast<int>(c / ncx);
+  double s = 0.0;
+  for (int j = 0; j < r; ++j)
+    for (int i = 0; i < r; ++i) s += fine[ch * fc + static_cast<int64_t>(cy * r + j) * nfx + cx * r + i];
+  const double mean = s / (static_cast<double>(r) * r);
+  coarse[idx] = static_cast<float>(ch == 0 ? rho_ref + static_cast<double>(r) * r * (mean - rho_ref) : mean);
+}
+
+__global__ void k_target(const float* __restrict__ mn, const float* __restrict__ m0, int64_t cells, float s_drho,
+                         float s_dq, float* __restrict__ t) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= 3 * cells) return;
+  t[i] = (mn[i] - m0[i]) / (i < cells ? s_drho : s_dq);
+}
+
+__global__ void k_features(const float* __restrict__ m, int dim, int64_t cells, double rho_ref, float s_rho,
+                           float s_u, float* __restrict__ x) {
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= cells) return;
+  const float rho = m[c];
+  x[c] = static_cast<float>((rho - rho_ref) / s_rho);
+  for (int j = 0; j < dim; ++j) x[(1 + j) * cells + c] = (m[(1 + j) * cells + c] / rho) / s_u;
+}
+
+// --------------------------------------------------------------------------
+// reset to the equilibrium of FP32 device moments (W = (rho, dx q))
+// --------------------------------------------------------------------------
+template <int D, typename TR, typename TM>
+__global__ __launch_bounds__(256) void k_set_eq(const float* __restrict__ m, int64_t cells, int64_t stride,
+                                                double dx, TR* __restrict__ rest, TM* __restrict__ move,
+                                                CoefT<double> k) {
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= cells) return;
+  const double rho = m[c];
+  double W[D + 1];
+  W[0] = rho - k.ref;
+#pragma unroll
+  for (int j = 0; j < D; ++j) W[1 + j] = dx * static_cast<double>(m[(1 + j) * cells + c]);
+  double eq[D + 1][2 * D + 1];
+  equilibrium<D, double>(W, 1.0 / rho, k, eq);
+#pragma unroll
+  for (int i = 0; i < D + 1; ++i) {
+    store_f32(rest + i * stride + c, static_cast<float>(eq[i][0]));
+#pragma unroll
+    for (int v = 0; v < 2 * D; ++v) store_f32(move + (i * 2 * D + v) * stride + c, static_cast<float>(eq[i][1 + v]));
+  }
+}
+
+// --------------------------------------------------------------------------
+// guarded correction (2D)
+// --------------------------------------------------------------------------
+// grid means of the scaled network output, one block
+__global__ __launch_bounds__(kThreads) void k_cl_means(const float* __restrict__ y, int64_t cells, float s_drho,
+                                                       float s_dq, double* __restrict__ slots) {
+  for (int ch = 0; ch < 3; ++ch) {
+    double acc = 0.0;
+    for (int64_t c = threadIdx.x; c < cells; c += kThreads) acc += static_cast<double>(y[ch * cells + c]);
+    const double s = block_sum(acc);
+    if (threadIdx.x == 0) slots[kSlotMean + ch] = s / static_cast<double>(cells) * (ch == 0 ? s_drho : s_dq);
+  }
+}
+
+// divergence norms of u and u' and the decision, one block
+__global__ __launch_bounds__(kThreads) void k_cl_guard(const float* __restrict__ m, const float* __restrict__ y,
+                                                       int nx, int ny, double dx, float s_drho, float s_dq,
+                                                       float factor, double* __restrict__ slots) {
+  const int64_t cells = static_cast<int64_t>(nx) * ny;
+  const double m0 = slots[kSlotMean], m1 = slots[kSlotMean + 1], m2 = slots[kSlotMean + 2];
+  auto uplain = [&](int x, int yy, int j) {
+    const int64_t c = static_cast<int64_t>(yy) * nx + x;
+    return static_cast<double>(m[(1 + j) * cells + c]) / static_cast<double>(m[c]);
+  };
+  auto ucorr = [&](int x, int yy, int j) {
+    const int64_t c = static_cast<int64_t>(yy) * nx + x;
+    const double rho = static_cast<double>(m[c]) + (static_cast<double>(y[c]) * s_drho - m0);
+    const double dq = static_cast<double>(y[(1 + j) * cells + c]) * s_dq - (j == 0 ? m1 : m2);
+    return (static_cast<double>(m[(1 + j) * cells + c]) + dq) / rho;
+  };
+  double a0 = 0.0, a1 = 0.0, bad = 0.0;
+  const double inv2dx = 1.0 / (2.0 * dx);
+  for (int64_t c = threadIdx.x; c < cells; c += kThreads) {
+    const int x = static_cast<int>(c % nx), yy = static_cast<int>(c / nx);
+    const int xp = wrapi(x + 1, nx), xm = wrapi(x - 1, nx), yp = wrapi(yy + 1, ny), ym = wrapi(yy - 1, ny);
+    const double d0 = (uplain(xp, yy, 0) - uplain(xm, yy, 0)) * inv2dx + (uplain(x, yp, 1) - uplain(x, ym, 1)) * inv2dx;
+    const double d1 = (ucorr(xp, yy, 0) - ucorr(xm, yy, 0)) * inv2dx + (ucorr(x, yp, 1) - ucorr(x, ym, 1)) * inv2dx;
+    a0 += d0 * d0;
+    a1 += d1 * d1;
+    if (!isfinite(ucorr(x, yy, 0)) || !isfinite(ucorr(x, yy, 1))) bad += 1.0;
+  }
+  const double s0 = block_sum(a0);
+  const double s1 = block_sum(a1);
+  const double sb = block_sum(bad);
+  if (threadIdx.x == 0) {
+    const double div0 = sqrt(dx * dx * s0), div1 = sqrt(dx * dx * s1);
+    const bool ok = sb == 0.0 && isfinite(div1) && div1 <= static_cast<double>(factor) * div0;
+    slots[kSlotDiv0] = div0;
+    slots[kSlotDiv1] = div1;
+    slots[kSlotAccept] = ok ? 1.0 : 0.0;
+    slots[ok ? kSlotNacc : kSlotNrej] += 1.0;
+  }
+}
+
+// g += f^eq(W + dW) - f^eq(W) in every cell, if the guard accepted
+template <int D, typename TR, typename TM>
+__global__ __launch_bounds__(256) void k_cl_apply(const float* __restrict__ y, int64_t cells, int64_t stride,
+                                                  double dx, double ref, TR* __restrict__ rest,
+                                                  TM* __restrict__ move, CoefT<double> k, float s_drho,
+                                                  float s_dq, const double* __restrict__ slots) {
+  if (slots[kSlotAccept] == 0.0) return;
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= cells) return;
+  double W[D + 1];
+#pragma unroll
+  for (int i = 0; i < D + 1; ++i) {
+    double a = static_cast<double>(load_f32(rest + i * stride + c));
+#pragma unroll
+    for (int v = 0; v < 2 * D; ++v) a += static_cast<double>(load_f32(move + (i * 2 * D + v) * stride + c));
+    W[i] = a;
+  }
+  W[0] += ref;  // full density; k.ref = 0 so both equilibria below are the plain ones
+  double W1[D + 1];
+  W1[0] = W[0] + (static_cast<double>(y[c]) * s_drho - slots[kSlotMean]);
+#pragma unroll
+  for (int j = 0; j < D; ++j)
+    W1[1 + j] = W[1 + j] + dx * (static_cast<double>(y[(1 + j) * cells + c]) * s_dq - slots[kSlotMean + 1 + j]);
+  double e0[D + 1][2 * D + 1], e1[D + 1][2 * D + 1];
+  equilibrium<D, double>(W, 1.0 / W[0], k, e0);
+  equilibrium<D, double>(W1, 1.0 / W1[0], k, e1);
+#pragma unroll
+  for (int i = 0; i < D + 1; ++i) {
+    TR* pr = rest + i * stride + c;
+    store_f32(pr, static_cast<float>(static_cast<double>(load_f32(pr)) + (e1[i][0] - e0[i][0])));
+#pragma unroll
+    for (int v = 0; v < 2 * D; ++v) {
+      TM* pm = move + (i * 2 * D + v) * stride + c;
+      store_f32(pm, static_cast<float>(static_cast<double>(load_f32(pm)) + (e1[i][1 + v] - e0[i][1 + v])));
+    }
+  }
+}
+
+template <int D, typename TR, typename TM, bool DEV>
+struct ClosureImpl {
+  static hipError_t set_eq(lbm_ctx* c, const float* m) {
+    auto p = planes_of<TR, TM>(c->cur, c->g.rest_bytes);
+    const CoefT<double> k = make_coef<double>(c->coef, D, DEV);
+    hipLaunchKernelGGL((k_set_eq<D, TR, TM>), dim3(static_cast<unsigned>((c->g.cells + 255) / 256)), dim3(256),
+                       0, c->stream, m, c->g.cells, c->g.stride, c->coef.dx, p.rest, p.move, k);
+    return hipGetLastError();
+  }
+  static hipError_t apply(lbm_ctx* c, const float* y, float s_drho, float s_dq, double* slots) {
+    auto p = planes_of<TR, TM>(c->cur, c->g.rest_bytes);
+    const CoefT<double> k = make_coef<double>(c->coef, D, false);
+    hipLaunchKernelGGL((k_cl_apply<D, TR, TM>), dim3(static_cast<unsigned>((c->g.cells + 255) / 256)), dim3(256),
+                       0, c->stream, y, c->g.cells, c->g.stride, c->coef.dx, DEV ? c->coef.ref : 0.0, p.rest,
+                       p.move, k, s_drho, s_dq, slots);
+    return hipGetLastError();
+  }
+};
+
+template <int D>
+hipError_t dispatch_set_eq(lbm_ctx* c, const float* m) {
+  switch (c->p.storage) {
+    case LBM_F32: return ClosureImpl<D, float, float, true>::set_eq(c, m);
+    case LBM_F32_RAW: return ClosureImpl<D, float, float, false>::set_eq(c, m);
+    case LBM_F16_DEV: return ClosureImpl<D, _Float16, _Float16, true>::set_eq(c, m);
+    case LBM_BF16_DEV: return ClosureImpl<D, bf16, bf16, true>::set_eq(c, m);
+    case LBM_F16_DEV_R32: return ClosureImpl<D, float, _Float16, true>::set_eq(c, m);
+    case LBM_BF16_DEV_R32: return ClosureImpl<D, float, bf16, true>::set_eq(c, m);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t dispatch_apply(lbm_ctx* c, const float* y, float s_drho, float s_dq, double* slots) {
+  switch (c->p.storage) {
+    case LBM_F32: return ClosureImpl<2, float, float, true>::apply(c, y, s_drho, s_dq, slots);
+    case LBM_F32_RAW: return ClosureImpl<2, float, float, false>::apply(c, y, s_drho, s_dq, slots);
+    case LBM_F16_DEV: return ClosureImpl<2, _Float16, _Float16, true>::apply(c, y, s_drho, s_dq, slots);
+    case LBM_BF16_DEV: return ClosureImpl<2, bf16, bf16, true>::apply(c, y, s_drho, s_dq, slots);
+    case LBM_F16_DEV_R32: return ClosureImpl<2, float, _Float16, true>::apply(c, y, s_drho, s_dq, slots);
+    case LBM_BF16_DEV_R32: return ClosureImpl<2, float, bf16, true>::apply(c, y, s_drho, s_dq, slots);
+  }
+  return hipErrorInvalidValue;
+}
+
+lbm_status dev(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EDEVICE; }
+
+}  // namespace
+}  // namespace lbm
+
+using namespace lbm;
+
+extern "C" {
+
+lbm_status lbm_restrict(const float* fine, int64_t nfx, int64_t nfy, int32_t r, double rho_ref, float* coarse,
+                        void* stream) {
+  if (!fine || !coarse || r < 1 || nfx < r || nfy < r || nfx % r || nfy % r || nfx > (1 << 30) || nfy > (1 << 30))
+    return LBM_EINVAL;
+  const int64_t n = 3 * (nfx / r) * (nfy / r);
+  hipLaunchKernelGGL(k_restrict, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), fine, static_cast<int>(nfx), static_cast<int>(nfy), r, rho_ref,
+                     coarse);
+  return dev(hipGetLastError());
+}
+
+lbm_status lbm_closure_features(const float* moments, int32_t dim, int64_t cells, double rho_ref, float s_rho,
+                                float s_u, float* x, void* stream) {
+  if (!moments || !x || (dim != 2 && dim != 3) || cells < 1 || !(s_rho > 0) || !(s_u > 0)) return LBM_EINVAL;
+  hipLaunchKernelGGL(k_features, dim3(static_cast<unsigned>((cells + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), moments, dim, cells, rho_ref, s_rho, s_u, x);
+  return dev(hipGetLastError());
+}
+
+lbm_status lbm_closure_target(const float* m_next, const float* m_now, int64_t cells, float s_drho, float s_dq,
+                              float* t, void* stream) {
+  if (!m_next || !m_now || !t || cells < 1 || !(s_drho > 0) || !(s_dq > 0)) return LBM_EINVAL;
+  hipLaunchKernelGGL(k_target, dim3(static_cast<unsigned>((3 * cells + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), m_next, m_now, cells, s_drho, s_dq, t);
+  return dev(hipGetLastError());
+}
+
+lbm_status lbm_set_equilibrium_device(lbm_ctx* c, const float* moments) {
+  if (!c || !moments) return LBM_EINVAL;
+  return dev(c->p.dim == 2 ? dispatch_set_eq<2>(c, moments) : dispatch_set_eq<3>(c, moments));
+}
+
+lbm_status lbm_closure_apply(lbm_ctx* c, const float* moments, const float* y, float s_drho, float s_dq,
+                             float guard_factor) {
+  if (!c || !moments || !y || c->p.dim != 2 || !(guard_factor > 0)) return LBM_EINVAL;
+  double* slots = c->closure_slots;
+  hipLaunchKernelGGL(k_cl_means, dim3(1), dim3(kThreads), 0, c->stream, y, c->g.cells, s_drho, s_dq, slots);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_cl_guard, dim3(1), dim3(kThreads), 0, c->stream, moments, y, c->g.nx, c->g.ny, c->p.dx,
+                       s_drho, s_dq, guard_factor, slots);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = dispatch_apply(c, y, s_drho, s_dq, slots);
+  return dev(e);
+}
+
+lbm_status lbm_closure_report_get(lbm_ctx* c, lbm_closure_report* out) {
+  if (!c || !out) return LBM_EINVAL;
+  double s[16];
+  hipError_t e = hipMemcpyAsync(s, c->closure_slots, sizeof(s), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return LBM_EDEVICE;
+  memset(out, 0, sizeof(*out));
+  out->n_accepted = static_cast<int64_t>(s[kSlotNacc]);
+  out->n_rejected = static_cast<int64_t>(s[kSlotNrej]);
+  out->accepted = s[kSlotAccept] != 0.0;
+  out->div_before = s[kSlotDiv0];
+  out->div_after = s[kSlotDiv1];
+  for (int i = 0; i < 3; ++i) out->mean[i] = s[kSlotMean + i];
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -85,3 +85,25 @@ __host__ __device__ inline PlaneSet<TR, TM> planes_of(void* base, size_t rest_by
 
 
 }  // namespace lbm
+
+// Host-side state of one run (the device memory belongs to the caller).
+struct lbm_ctx {
+  lbm_params p;
+  double mu;
+  double alpha_q;
+  uint32_t flags;
+  lbm::Geometry g;
+  const lbm::Ops* ops;
+  lbm::RunCoef coef;
+  char* ws;
+  size_t ws_bytes;
+  char* cur;        // buffer holding the state at step `steps`
+  char* nxt;        // the other buffer (also used as staging between steps)
+  double* partials; // diagnostics per-block partials
+  double* result;   // diagnostics final slots
+  double* closure_slots;  // lbm_closure_apply decision and report (8 doubles)
+  int64_t diag_blocks;
+  hipStream_t stream;
+  int64_t steps;
+  int bx, by;       // step kernel block shape
+};

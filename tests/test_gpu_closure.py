@@ -1,0 +1,161 @@
+"""Device pieces of the coarse-grid correction against the FP64 closure oracle."""
+
+import math
+
+import numpy as np
+import pytest
+
+import inputs
+from oracle import closure as ocl
+from oracle import scheme
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2607_24059_amd import closure as cl  # noqa: E402
+from paper_2607_24059_amd import cnn, lbm  # noqa: E402
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+
+
+def _moments_f32(rho, q):
+    return np.concatenate([rho[None], q]).astype(np.float32)
+
+
+def test_restriction_matches_oracle():
+    rng = np.random.default_rng(0)
+    n, r = 128, 8
+    rho = 1 + 1e-4 * rng.standard_normal((n, n))
+    q = rng.standard_normal((2, n, n))
+    m = _moments_f32(rho, q)
+    out = torch.empty((3, n // r, n // r), dtype=torch.float32, device="cuda")
+    cl.lbm_restrict(dev(m), n, n, r, 1.0, out, torch.cuda.current_stream())
+    rc, qc = ocl.restrict(m[0].astype(np.float64), m[1:].astype(np.float64), r)
+    got = out.double().cpu().numpy()
+    assert np.max(np.abs(got[0] - rc)) <= 1e-6 and np.max(np.abs(got[1:] - qc)) <= 1e-6
+
+
+def test_features_match_definition():
+    rng = np.random.default_rng(1)
+    cells = 4096
+    m = _moments_f32(1 + 1e-3 * rng.standard_normal(cells), rng.standard_normal((2, cells)))
+    x = torch.empty((3, cells), dtype=torch.float32, device="cuda")
+    cl.lbm_closure_features(dev(m), 2, cells, 1.0, 2e-3, 0.7, x, torch.cuda.current_stream())
+    ref = ocl.net_input(m[0].astype(np.float64), m[1:].astype(np.float64), {"s_rho": 2e-3, "s_u": 0.7})
+    assert np.allclose(x.double().cpu().numpy(), ref, rtol=1e-5, atol=1e-5)
+
+
+def _ctx_state(n=64, steps=9, seed=3, storage="f32"):
+    p = scheme.params_for_grid(2, n, 0.01, omega_q=1.3)
+    u0 = inputs.random_field_2d(n, seed, umax=0.05 / p.dx)
+    prm = lbm.make_params(2, (n, n), p.dx, p.dt, p.nu, p.omega_rho, p.omega_q, p.alpha_rho, storage=storage)
+    eng = lbm.Engine.create(prm, u0)
+    eng.step(steps)
+    return p, u0, eng
+
+
+def test_set_equilibrium_device_is_the_equilibrium():
+    p, u0, eng = _ctx_state()
+    n = 64
+    rng = np.random.default_rng(2)
+    rho = 1 + 1e-3 * rng.standard_normal((n, n))
+    q = rho * inputs.random_field_2d(n, 7, umax=0.05 / p.dx)
+    m = _moments_f32(rho, q)
+    cl.lbm_set_equilibrium_device(eng.ctx, dev(m))
+    r2, q2 = eng.moments()
+    assert np.max(np.abs(r2 - m[0])) <= 2e-7 and np.max(np.abs(q2 - m[1:])) <= 1e-6 * np.abs(m[1:]).max()
+    # one step from it equals the oracle's step from f^eq of the same moments
+    eng.step(1)
+    r3, q3 = eng.moments()
+    eng.close()
+    f = scheme.equilibrium(m[0].astype(np.float64), m[1:].astype(np.float64), p)
+    r_ref, q_ref = scheme.moments(scheme.step(f, p), p)
+    assert np.max(np.abs(r3 - r_ref)) <= 1e-6 and np.max(np.abs(q3 - q_ref)) <= 1e-5 * np.abs(q_ref).max()
+
+
+def test_correction_and_guard_match_oracle():
+    p, u0, eng = _ctx_state()
+    n = 64
+    cells = n * n
+    s = torch.cuda.current_stream()
+    m = torch.empty((3, n, n), dtype=torch.float32, device="cuda")
+    eng.moments_device(m)
+    rho, q = eng.moments()
+    rng = np.random.default_rng(5)
+    y = rng.standard_normal((3, n, n)) * 0.5
+    s_drho, s_dq = 1e-6, 1e-3
+    cl.lbm_closure_apply(eng.ctx, m, dev(y), s_drho, s_dq, 1e9)
+    rep = cl.lbm_closure_report_get(eng.ctx)
+    r2, q2 = eng.moments()
+    # oracle: zero-mean correction, guard on the FP32 moments
+    y32 = np.float32(y).astype(np.float64)
+    d_rho, d_q = ocl.net_output_to_dw(y32, {"s_drho": np.float32(s_drho), "s_dq": np.float32(s_dq)})
+    mh = m.double().cpu().numpy()
+    ok, div0, div1 = ocl.guard(mh[0], mh[1:], d_rho, d_q, p.dx, 1e9)
+    assert ok and rep["accepted"] and rep["n_accepted"] == 1
+    assert rep["div_before"] == pytest.approx(div0, rel=1e-9)
+    assert rep["div_after"] == pytest.approx(div1, rel=1e-9)
+    assert np.max(np.abs(r2 - (rho + d_rho))) <= 1e-6
+    assert np.max(np.abs(q2 - (q + d_q))) <= 1e-5 * np.abs(q).max()
+    assert abs(r2.sum() - rho.sum()) <= 1e-6 * cells   # mass unchanged by the projection
+    eng.close()
+
+
+def test_guard_rejects_and_leaves_state_untouched():
+    p, u0, eng = _ctx_state()
+    n = 64
+    m = torch.empty((3, n, n), dtype=torch.float32, device="cuda")
+    eng.moments_device(m)
+    before = eng.save_state()
+    rng = np.random.default_rng(6)
+    y = rng.standard_normal((3, n, n)) * 1e6    # a corrupted network output
+    cl.lbm_closure_apply(eng.ctx, m, dev(y), 1e-3, 1.0, 2.0)
+    rep = cl.lbm_closure_report_get(eng.ctx)
+    assert not rep["accepted"] and rep["n_rejected"] == 1
+    assert np.array_equal(eng.save_state(), before)
+    eng.close()
+
+
+def test_corrupted_network_run_equals_plain_coarse():
+    """The whole corrected loop with weights x1e6: every correction rejected,
+    the run bit-identical to the plain coarse scheme."""
+    p, u0, eng = _ctx_state(64, 0, 8)
+    n = 64
+    s = torch.cuda.current_stream()
+    net = cnn.Net(seed=1)
+    net.p.mul_(1e6)
+    net.repack()
+    m = torch.empty((3, n, n), dtype=torch.float32, device="cuda")
+    x = torch.empty((1, 3, n, n), dtype=torch.float32, device="cuda")
+    for _ in range(5):
+        eng.step(4)
+        eng.moments_device(m)
+        cl.lbm_closure_features(m, 2, n * n, 1.0, 1e-3, 1.0, x, s)
+        y = net.forward(x)
+        cl.lbm_closure_apply(eng.ctx, m, y, 1e-4, 1e-2, 2.0)
+    rep = cl.lbm_closure_report_get(eng.ctx)
+    got = eng.save_state()
+    eng.close()
+    _, _, ref = _ctx_state(64, 20, 8)
+    assert rep["n_accepted"] == 0 and rep["n_rejected"] == 5
+    assert np.array_equal(got, ref.save_state())
+    ref.close()
+
+
+def test_end_to_end_small_configuration():
+    """Data generation, training and evaluation on a tiny configuration
+    (coarse 64^2, fine 256^2): the loop runs and produces finite numbers."""
+    cfg = cl.Config(coarse_n=64, factor=4, train_seeds=[0, 1], test_seeds=[1000], pairs_per_seed=4,
+                    horizon=16, epochs=2, batch=2, eval_levels=(64, 128))
+    x, t, scales = cl.build_dataset(cfg, log=lambda *a: None)
+    assert x.shape == (8, 3, 64, 64) and all(math.isfinite(v) and v > 0 for v in scales.values())
+    net, hist = cl.train(cfg, x, t, log=lambda *a: None)
+    assert all(math.isfinite(h) for h in hist)
+    ev = cl.evaluate(cfg, net, scales, log=lambda *a: None)
+    assert math.isfinite(ev["closure"]) and math.isfinite(ev["plain"]["64"])
+    assert ev["accepted"] + ev["rejected"] == 4
