@@ -118,9 +118,16 @@ size_t lbm_workspace_bytes(const lbm_params* p);
 lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const double* rho0,
                     void* workspace, size_t ws_bytes, void* hip_stream);
 
-/* Advance nsteps >= 0 time steps (relaxation then transport, Section 2), one
- * fused kernel launch per step.  Asynchronous. */
+/* Advance nsteps >= 0 time steps (relaxation then transport, Section 2).
+ * Each launch fuses relaxation and transport; in 2D a launch advances two steps
+ * by default (the intermediate state of each tile and its one-cell border
+ * kept on chip), with a single-step launch for an odd remainder.  The result
+ * is bit-identical for any fusion setting.  Asynchronous. */
 lbm_status lbm_step(lbm_ctx* ctx, int64_t nsteps);
+
+/* Time steps per launch: 1, or 2 (2D only; the default in 2D).  LBM_EINVAL
+ * if the setting is not available for the context's dimension. */
+lbm_status lbm_set_fusion(lbm_ctx* ctx, int32_t steps_per_launch);
 
 /* Moments of the current state: rho [cells] and q [dim][cells] = (1/dx) sum f_q,
  * summed in FP64 from the stored populations.  Host FP64 outputs; q may be
@@ -136,7 +143,10 @@ lbm_status lbm_moments_device(lbm_ctx* ctx, float* out);
  * struct is filled either way).  Synchronises. */
 lbm_status lbm_diagnostics(lbm_ctx* ctx, lbm_diag* out);
 
-/* Size of a full state snapshot: every population plane plus the step count. */
+/* Size of a full state snapshot: every population plane (without padding:
+ * the D+1 rest planes of cells x rest element, then the (D+1) 2D moving planes
+ * of cells x moving element, in the element types of the storage mode), then
+ * the step count as int64. */
 size_t lbm_state_bytes(const lbm_ctx* ctx);
 /* Copy the full state to / from host memory (synchronises).  Restarting from
  * moments alone is not a continuation (the non-equilibrium part is lost), so

@@ -50,8 +50,9 @@ lbm_status lbm_batch_init(lbm_batch** out, int32_t dim, int32_t storage, int32_t
                           void* hip_stream, int32_t* bad_run);
 
 /* Choose the tile shape of every size class (runs grouped by nx rounded up to
- * a power of two) by timing each candidate on the batch's own buffers; the
- * state is not changed.  If cache_path is non-NULL (else the environment
+ * a power of two), then the number of blocks of the persistent launch (4, 8,
+ * 16 or 32 per compute unit, or one per tile), by timing each candidate on the
+ * batch's own buffers; the state is not changed.  If cache_path is non-NULL (else the environment
  * variable LBM_AUTOTUNE_CACHE, if set) previously tuned shapes for this
  * device, dimension and storage are read from that text file and new ones are
  * appended.  Rebuilds the step graph.  Synchronises. */
@@ -69,6 +70,10 @@ lbm_status lbm_batch_info(const lbm_batch* b, int64_t* total_cells, int64_t* til
 
 /* Tile width (cells along x) chosen for run r's size class. */
 int32_t lbm_batch_tile_width(const lbm_batch* b, int32_t run);
+
+/* Blocks of the persistent step launch (a grid of at least the tile count
+ * means one block per tile); chosen by lbm_batch_autotune. */
+int32_t lbm_batch_grid(const lbm_batch* b);
 
 void lbm_batch_destroy(lbm_batch* b);
 

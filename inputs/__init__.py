@@ -15,6 +15,9 @@ from .fields import (  # noqa: F401
     random_field_2d,
     random_field_3d,
     random_field_box,
+    random_pressure_2d,
+    pressure_coefficients,
+    pressure_at,
     well_prepared_density,
     batch_run_specs,
 )

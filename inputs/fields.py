@@ -248,6 +248,53 @@ def random_field_box(shape, dx: float, seed: int, umax: float = 1.0, mmax: int =
     return u * (umax / float(np.sqrt(np.max(np.sum(u * u, axis=0)))))
 
 
+def pressure_coefficients(u: np.ndarray, length: float = TWO_PI):
+    """Fourier coefficients of the kinematic pressure of a periodic 2D field.
+
+    u: samples (2, m, m) at cell centres of a band-limited field whose
+    products u_i u_j are resolved on the m x m grid (no aliasing).  The
+    incompressible pressure solves  lap Phi = -d_i d_j (u_i u_j)  (the
+    divergence of the momentum equation), i.e. Phi_hat = -k_i k_j P_ij_hat / |k|^2
+    with zero mean.  Returns (c, k) with Phi(x, y) = sum c[ky, kx] exp(i (kx x + ky y)),
+    k the integer-scaled wavenumbers of numpy's FFT order.
+    """
+    m = u.shape[-1]
+    h = length / m
+    k = 2 * math.pi * np.fft.fftfreq(m, d=h)
+    ky = k[:, None]
+    kx = k[None, :]
+    shift = np.exp(-1j * (kx + ky) * h / 2)           # samples sit at (j + 1/2) h
+    P = [[np.fft.fft2(u[i] * u[j]) * shift / (m * m) for j in range(2)] for i in range(2)]
+    kk = [kx, ky]
+    k2 = kx * kx + ky * ky
+    num = sum(kk[i] * kk[j] * P[i][j] for i in range(2) for j in range(2))
+    c = np.zeros_like(num)
+    nz = k2 > 0
+    c[nz] = -num[nz] / k2[nz]
+    return c, k
+
+
+def pressure_at(c: np.ndarray, k: np.ndarray, n: int, length: float = TWO_PI) -> np.ndarray:
+    """Evaluate sum c[ky, kx] exp(i k . x) at the cell centres of an n x n grid."""
+    x = cell_centres(n, length)
+    e = np.exp(1j * np.outer(k, x))                    # [k, position]
+    return np.real(e.T @ c @ e)
+
+
+def random_pressure_2d(n: int, seed: int, umax: float = 1.0, kmax: int = 16,
+                       length: float = TWO_PI, norm_n: int = 256) -> np.ndarray:
+    """Kinematic pressure of random_field_2d(n, seed, umax, kmax) at cell centres.
+
+    The velocity has modes |k| <= kmax, so u_i u_j has |k| <= 2 kmax and is
+    resolved exactly on a 4 kmax + 4 grid; the pressure coefficients computed
+    there are evaluated at the n x n cell centres.
+    """
+    m = 4 * kmax + 4
+    u = random_field_2d(m, seed, umax, kmax, length, norm_n)
+    c, k = pressure_coefficients(u, length)
+    return pressure_at(c, k, n, length)
+
+
 # --------------------------------------------------------------------------- #
 # The batch workload: many independent runs of uneven size and viscosity      #
 # --------------------------------------------------------------------------- #

@@ -39,6 +39,7 @@ SIGNATURES = {
     "lbm_batch_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                  C.POINTER(C.c_int64)]),
     "lbm_batch_tile_width": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "lbm_batch_grid": (C.c_int32, [C.c_void_p]),
     "lbm_batch_destroy": (None, [C.c_void_p]),
 }
 
@@ -119,6 +120,10 @@ def lbm_batch_tile_width(h: int, run: int) -> int:
     return int(blib().lbm_batch_tile_width(C.c_void_p(h), run))
 
 
+def lbm_batch_grid(h: int) -> int:
+    return int(blib().lbm_batch_grid(C.c_void_p(h)))
+
+
 def lbm_batch_destroy(h: int) -> None:
     blib().lbm_batch_destroy(C.c_void_p(h))
 
@@ -169,6 +174,9 @@ class Batch:
 
     def info(self):
         return lbm_batch_info(self.handle)
+
+    def grid(self) -> int:
+        return lbm_batch_grid(self.handle)
 
     def tile_width(self, r: int) -> int:
         return lbm_batch_tile_width(self.handle, r)

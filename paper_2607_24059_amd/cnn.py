@@ -127,9 +127,13 @@ class Net:
                        for ci, co in LAYERS]
         self.packed_t = [torch.empty(lbm_conv_packed_bytes(ci, co), dtype=torch.uint8, device=device)
                          for ci, co in LAYERS]
-        self.stream = torch.cuda.current_stream()
         self._acts = {}
         self.repack()
+
+    @property
+    def stream(self):
+        """Every launch goes to torch's current stream (so a caller can capture it)."""
+        return self.torch.cuda.current_stream()
 
     def views(self, flat):
         out, off = [], 0

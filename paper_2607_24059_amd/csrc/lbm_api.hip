@@ -122,6 +122,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const 
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->steps = 0;
   default_block(g, &c->bx, &c->by);
+  c->fuse = c->ops->step2 ? 2 : 1;
 
   // stage u0 (and rho0) as FP64 in the idle buffer, then build the equilibrium
   double* su = reinterpret_cast<double*>(c->nxt);
@@ -144,14 +145,24 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const 
 
 lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
   if (!c || nsteps < 0) return LBM_EINVAL;
-  for (int64_t s = 0; s < nsteps; ++s) {
-    hipError_t e = c->ops->step(c->g, c->coef, c->cur, c->nxt, c->bx, c->by, c->stream);
+  while (nsteps > 0) {
+    const bool two = c->fuse == 2 && nsteps >= 2;
+    hipError_t e = two ? c->ops->step2(c->g, c->coef, c->cur, c->nxt, c->stream)
+                       : c->ops->step(c->g, c->coef, c->cur, c->nxt, c->bx, c->by, c->stream);
     if (e != hipSuccess) return LBM_EDEVICE;
     char* t = c->cur;
     c->cur = c->nxt;
     c->nxt = t;
-    c->steps += 1;
+    c->steps += two ? 2 : 1;
+    nsteps -= two ? 2 : 1;
   }
+  return LBM_OK;
+}
+
+lbm_status lbm_set_fusion(lbm_ctx* c, int32_t steps_per_launch) {
+  if (!c || steps_per_launch < 1 || steps_per_launch > 2) return LBM_EINVAL;
+  if (steps_per_launch == 2 && !c->ops->step2) return LBM_EINVAL;
+  c->fuse = steps_per_launch;
   return LBM_OK;
 }
 
@@ -196,28 +207,55 @@ lbm_status lbm_diagnostics(lbm_ctx* c, lbm_diag* out) {
   return out->nonfinite > 0 ? LBM_ENONFINITE : LBM_OK;
 }
 
+// The snapshot holds every plane without its padding: the rest planes
+// (D+1 x cells x rest element), the moving planes ((D+1) 2D x cells x moving
+// element), then the step count.
+static size_t compact_rest(const lbm_ctx* c) {
+  return static_cast<size_t>(c->p.dim + 1) * c->g.cells * c->g.rest_elem;
+}
+static size_t compact_move(const lbm_ctx* c) {
+  return static_cast<size_t>(c->p.dim + 1) * 2 * c->p.dim * c->g.cells * c->g.move_elem;
+}
+
 size_t lbm_state_bytes(const lbm_ctx* c) {
   if (!c) return 0;
-  return c->g.buf_bytes + sizeof(int64_t);
+  return compact_rest(c) + compact_move(c) + sizeof(int64_t);
+}
+
+static hipError_t copy_planes(lbm_ctx* c, char* host, bool to_host) {
+  const Geometry& g = c->g;
+  const int ns = c->p.dim + 1, nm = ns * 2 * c->p.dim;
+  const size_t wr = static_cast<size_t>(g.cells) * g.rest_elem, pr = static_cast<size_t>(g.stride) * g.rest_elem;
+  const size_t wm = static_cast<size_t>(g.cells) * g.move_elem, pm = static_cast<size_t>(g.stride) * g.move_elem;
+  char* dev_rest = c->cur;
+  char* dev_move = c->cur + g.rest_bytes;
+  hipError_t e;
+  if (to_host) {
+    e = hipMemcpy2DAsync(host, wr, dev_rest, pr, wr, ns, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpy2DAsync(host + ns * wr, wm, dev_move, pm, wm, nm, hipMemcpyDeviceToHost, c->stream);
+  } else {
+    e = hipMemcpy2DAsync(dev_rest, pr, host, wr, wr, ns, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpy2DAsync(dev_move, pm, host + ns * wr, wm, wm, nm, hipMemcpyHostToDevice, c->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  return e;
 }
 
 lbm_status lbm_save_state(lbm_ctx* c, void* host, size_t bytes) {
   if (!c || !host) return LBM_EINVAL;
   if (bytes != lbm_state_bytes(c)) return LBM_ESTATE;
-  hipError_t e = hipMemcpyAsync(host, c->cur, c->g.buf_bytes, hipMemcpyDeviceToHost, c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  if (e != hipSuccess) return LBM_EDEVICE;
-  memcpy(static_cast<char*>(host) + c->g.buf_bytes, &c->steps, sizeof(int64_t));
+  if (copy_planes(c, static_cast<char*>(host), true) != hipSuccess) return LBM_EDEVICE;
+  memcpy(static_cast<char*>(host) + compact_rest(c) + compact_move(c), &c->steps, sizeof(int64_t));
   return LBM_OK;
 }
 
 lbm_status lbm_load_state(lbm_ctx* c, const void* host, size_t bytes) {
   if (!c || !host) return LBM_EINVAL;
   if (bytes != lbm_state_bytes(c)) return LBM_ESTATE;
-  hipError_t e = hipMemcpyAsync(c->cur, host, c->g.buf_bytes, hipMemcpyHostToDevice, c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  if (e != hipSuccess) return LBM_EDEVICE;
-  memcpy(&c->steps, static_cast<const char*>(host) + c->g.buf_bytes, sizeof(int64_t));
+  if (copy_planes(c, const_cast<char*>(static_cast<const char*>(host)), false) != hipSuccess) return LBM_EDEVICE;
+  memcpy(&c->steps, static_cast<const char*>(host) + compact_rest(c) + compact_move(c), sizeof(int64_t));
   return LBM_OK;
 }
 

@@ -134,7 +134,8 @@ struct lbm_batch {
   int64_t ntiles = 0;
   int64_t total_cells = 0;
   int parity = 0;  // state buffer index holding the current step
-  int grid = 0;    // persistent grid size
+  int grid = 0;    // persistent grid size (blocks); >= ntiles means one block per tile
+  int cus = 256;   // compute units of the device
   hipStream_t stream = nullptr;
   BatchKernel kernel = nullptr;
   hipGraphExec_t exec_main = nullptr;  // kGraphSteps steps starting at parity 0
@@ -317,7 +318,7 @@ lbm_status lbm_batch_init(lbm_batch** out, int32_t dim, int32_t storage, int32_t
     lbm_params p = params_of(dim, storage, runs[r]);
     double mu = 0, aq = 0;
     lbm_status st = lbm_check_params(&p, &mu, &aq, nullptr);
-    if (st == LBM_OK && !u0[r]) st = LBM_EINVAL;
+    if (st == LBM_OK && (!u0[r] || runs[r].n[2] > 32767)) st = LBM_EINVAL;  // tile z is 16-bit
     if (st != LBM_OK) {
       if (bad_run) *bad_run = r;
       return st;
@@ -386,6 +387,7 @@ lbm_status lbm_batch_init(lbm_batch** out, int32_t dim, int32_t storage, int32_t
     hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
       cus = 256;
+    b->cus = cus;
     b->grid = 8 * cus;  // 8 resident 256-thread blocks per CU at the kernel's register use
     e = rebuild(b);
   }
@@ -409,7 +411,7 @@ lbm_status lbm_batch_autotune(lbm_batch* b, const char* cache_path) {
       char arch[128];
       int d, st, cl, bx;
       while (fscanf(f, "%127s %d %d %d %d", arch, &d, &st, &cl, &bx) == 5)
-        if (key == arch && d == b->dim && st == b->storage && (bx == 64 || bx == 128 || bx == 256))
+        if (key == arch && d == b->dim && st == b->storage && (cl == -1 || bx == 64 || bx == 128 || bx == 256))
           cached[cl] = bx;
       fclose(f);
     }
@@ -452,6 +454,33 @@ lbm_status lbm_batch_autotune(lbm_batch* b, const char* cache_path) {
     }
     kv.second = best_bx;
     fresh.emplace_back(cl, best_bx);
+  }
+  // persistent grid size for the whole list: blocks per CU, or one block per tile (0)
+  if (e == hipSuccess) e = upload_tiles(b, build_tiles(b, {}));
+  if (e == hipSuccess && cached.count(-1)) {
+    const int per_cu = cached[-1];
+    b->grid = per_cu > 0 ? per_cu * b->cus : static_cast<int>(std::min<int64_t>(b->ntiles, 0x7fffffff));
+  } else if (e == hipSuccess) {
+    const int cands[] = {4, 8, 16, 32, 0};
+    float best = 1e30f;
+    int best_pc = 8;
+    for (int pc : cands) {
+      if (e != hipSuccess) break;
+      b->grid = pc > 0 ? pc * b->cus : static_cast<int>(std::min<int64_t>(b->ntiles, 0x7fffffff));
+      for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch_step(b, b->parity, b->ntiles, b->stream);
+      if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+      for (int it = 0; it < 5 && e == hipSuccess; ++it) e = launch_step(b, b->parity, b->ntiles, b->stream);
+      if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess && ms < best) {
+        best = ms;
+        best_pc = pc;
+      }
+    }
+    b->grid = best_pc > 0 ? best_pc * b->cus : static_cast<int>(std::min<int64_t>(b->ntiles, 0x7fffffff));
+    fresh.emplace_back(-1, best_pc);
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
@@ -510,6 +539,8 @@ lbm_status lbm_batch_info(const lbm_batch* b, int64_t* total_cells, int64_t* til
   if (steps) *steps = b->steps;
   return LBM_OK;
 }
+
+int32_t lbm_batch_grid(const lbm_batch* b) { return b ? b->grid : -1; }
 
 int32_t lbm_batch_tile_width(const lbm_batch* b, int32_t run) {
   if (!b || run < 0 || run >= b->nruns) return -1;

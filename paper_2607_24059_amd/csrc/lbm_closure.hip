@@ -100,21 +100,39 @@ __global__ __launch_bounds__(256) void k_set_eq(const float* __restrict__ m, int
 // --------------------------------------------------------------------------
 // guarded correction (2D)
 // --------------------------------------------------------------------------
-// grid means of the scaled network output, one block
-__global__ __launch_bounds__(kThreads) void k_cl_means(const float* __restrict__ y, int64_t cells, float s_drho,
-                                                       float s_dq, double* __restrict__ slots) {
+// Two-stage deterministic reductions: per-block partials in the context's
+// diagnostics scratch, then one block sums them in a fixed order.
+constexpr int kRedSlots = 4;
+
+// per-block sums of the three output channels
+__global__ __launch_bounds__(kThreads) void k_cl_means(const float* __restrict__ y, int64_t cells,
+                                                       double* __restrict__ part) {
   for (int ch = 0; ch < 3; ++ch) {
     double acc = 0.0;
-    for (int64_t c = threadIdx.x; c < cells; c += kThreads) acc += static_cast<double>(y[ch * cells + c]);
+    for (int64_t c = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; c < cells;
+         c += static_cast<int64_t>(gridDim.x) * kThreads)
+      acc += static_cast<double>(y[ch * cells + c]);
+    const double s = block_sum(acc);
+    if (threadIdx.x == 0) part[blockIdx.x * kRedSlots + ch] = s;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_cl_means_final(const double* __restrict__ part, int nb,
+                                                             int64_t cells, float s_drho, float s_dq,
+                                                             double* __restrict__ slots) {
+  for (int ch = 0; ch < 3; ++ch) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kThreads) acc += part[b * kRedSlots + ch];
     const double s = block_sum(acc);
     if (threadIdx.x == 0) slots[kSlotMean + ch] = s / static_cast<double>(cells) * (ch == 0 ? s_drho : s_dq);
   }
 }
 
-// divergence norms of u and u' and the decision, one block
+// per-block divergence sums of u and u' and non-finite counts
 __global__ __launch_bounds__(kThreads) void k_cl_guard(const float* __restrict__ m, const float* __restrict__ y,
                                                        int nx, int ny, double dx, float s_drho, float s_dq,
-                                                       float factor, double* __restrict__ slots) {
+                                                       const double* __restrict__ slots,
+                                                       double* __restrict__ part) {
   const int64_t cells = static_cast<int64_t>(nx) * ny;
   const double m0 = slots[kSlotMean], m1 = slots[kSlotMean + 1], m2 = slots[kSlotMean + 2];
   auto uplain = [&](int x, int yy, int j) {
@@ -129,7 +147,8 @@ __global__ __launch_bounds__(kThreads) void k_cl_guard(const float* __restrict__
   };
   double a0 = 0.0, a1 = 0.0, bad = 0.0;
   const double inv2dx = 1.0 / (2.0 * dx);
-  for (int64_t c = threadIdx.x; c < cells; c += kThreads) {
+  for (int64_t c = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; c < cells;
+       c += static_cast<int64_t>(gridDim.x) * kThreads) {
     const int x = static_cast<int>(c % nx), yy = static_cast<int>(c / nx);
     const int xp = wrapi(x + 1, nx), xm = wrapi(x - 1, nx), yp = wrapi(yy + 1, ny), ym = wrapi(yy - 1, ny);
     const double d0 = (uplain(xp, yy, 0) - uplain(xm, yy, 0)) * inv2dx + (uplain(x, yp, 1) - uplain(x, ym, 1)) * inv2dx;
@@ -141,6 +160,25 @@ __global__ __launch_bounds__(kThreads) void k_cl_guard(const float* __restrict__
   const double s0 = block_sum(a0);
   const double s1 = block_sum(a1);
   const double sb = block_sum(bad);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x * kRedSlots + 0] = s0;
+    part[blockIdx.x * kRedSlots + 1] = s1;
+    part[blockIdx.x * kRedSlots + 2] = sb;
+  }
+}
+
+// the decision, one block
+__global__ __launch_bounds__(kThreads) void k_cl_decide(const double* __restrict__ part, int nb, double dx,
+                                                        float factor, double* __restrict__ slots) {
+  double a0 = 0.0, a1 = 0.0, ab = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kThreads) {
+    a0 += part[b * kRedSlots + 0];
+    a1 += part[b * kRedSlots + 1];
+    ab += part[b * kRedSlots + 2];
+  }
+  const double s0 = block_sum(a0);
+  const double s1 = block_sum(a1);
+  const double sb = block_sum(ab);
   if (threadIdx.x == 0) {
     const double div0 = sqrt(dx * dx * s0), div1 = sqrt(dx * dx * s1);
     const bool ok = sb == 0.0 && isfinite(div1) && div1 <= static_cast<double>(factor) * div0;
@@ -278,11 +316,27 @@ lbm_status lbm_closure_apply(lbm_ctx* c, const float* moments, const float* y, f
                              float guard_factor) {
   if (!c || !moments || !y || c->p.dim != 2 || !(guard_factor > 0)) return LBM_EINVAL;
   double* slots = c->closure_slots;
-  hipLaunchKernelGGL(k_cl_means, dim3(1), dim3(kThreads), 0, c->stream, y, c->g.cells, s_drho, s_dq, slots);
+  double* part = c->partials;  // diagnostics scratch: diag_blocks * 16 doubles
+  int64_t nb = c->g.cells / 2048;
+  const int64_t cap = c->diag_blocks * 16 / kRedSlots;
+  if (nb > 256) nb = 256;
+  if (nb > cap) nb = cap;
+  if (nb < 1) nb = 1;
+  const int nbi = static_cast<int>(nb);
+  hipLaunchKernelGGL(k_cl_means, dim3(nbi), dim3(kThreads), 0, c->stream, y, c->g.cells, part);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_cl_guard, dim3(1), dim3(kThreads), 0, c->stream, moments, y, c->g.nx, c->g.ny, c->p.dx,
-                       s_drho, s_dq, guard_factor, slots);
+    hipLaunchKernelGGL(k_cl_means_final, dim3(1), dim3(kThreads), 0, c->stream, part, nbi, c->g.cells, s_drho,
+                       s_dq, slots);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_cl_guard, dim3(nbi), dim3(kThreads), 0, c->stream, moments, y, c->g.nx, c->g.ny, c->p.dx,
+                       s_drho, s_dq, slots, part);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_cl_decide, dim3(1), dim3(kThreads), 0, c->stream, part, nbi, c->p.dx, guard_factor, slots);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = dispatch_apply(c, y, s_drho, s_dq, slots);

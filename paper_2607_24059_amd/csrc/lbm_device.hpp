@@ -156,19 +156,14 @@ __device__ __forceinline__ void collide(float (&g)[D + 1][2 * D + 1], const Coef
 }
 
 
-// One lattice update of cell (x, y, z): gather the post-relaxation values of
-// the upwind neighbours (pull form of the transport phase: f_{+e_j}(t+dt, x)
-// = f*_{+e_j}(t, x - dx e_j), periodic), sum the moments, relax, and write the
-// cell's own post-relaxation values.  Every stored value is read once and
-// written once per step.  Used by the single-run and the batched kernels, so
-// both produce bit-identical states.
+// Gather the post-relaxation values of the upwind neighbours of cell (x, y, z):
+// the pull form of the transport phase, f_{+e_j}(t+dt, x) = f*_{+e_j}(t, x - dx e_j),
+// on the periodic grid.  c is the cell's linear index.
 template <int D, typename TR, typename TM>
-__device__ __forceinline__ void step_cell(const TR* __restrict__ sr, const TM* __restrict__ sm,
-                                          TR* __restrict__ dr, TM* __restrict__ dm, int x, int y,
-                                          int z, int nx, int ny, int nz, int64_t stride,
-                                          const Coef& k) {
+__device__ __forceinline__ void gather_cell(const TR* __restrict__ sr, const TM* __restrict__ sm, int x, int y,
+                                            int z, int nx, int ny, int nz, int64_t stride, int64_t c,
+                                            float (&g)[D + 1][2 * D + 1]) {
   const int64_t plane = static_cast<int64_t>(nx) * ny;
-  const int64_t c = static_cast<int64_t>(z) * plane + static_cast<int64_t>(y) * nx + x;
   int64_t src[2 * D];
   src[0] = (x == 0) ? c + (nx - 1) : c - 1;                                   // +x from x-1
   src[1] = (x == nx - 1) ? c - (nx - 1) : c + 1;                              // -x from x+1
@@ -178,13 +173,27 @@ __device__ __forceinline__ void step_cell(const TR* __restrict__ sr, const TM* _
     src[4] = (z == 0) ? c + static_cast<int64_t>(nz - 1) * plane : c - plane;      // +z
     src[5] = (z == nz - 1) ? c - static_cast<int64_t>(nz - 1) * plane : c + plane; // -z
   }
-  float g[D + 1][2 * D + 1];
 #pragma unroll
   for (int i = 0; i < D + 1; ++i) {
     g[i][0] = load_f32(sr + i * stride + c);
 #pragma unroll
     for (int m = 0; m < 2 * D; ++m) g[i][1 + m] = load_f32(sm + (i * 2 * D + m) * stride + src[m]);
   }
+}
+
+// One lattice update of cell (x, y, z): gather, sum the moments, relax, and
+// write the cell's own post-relaxation values.  Every stored value is read
+// once and written once per step.  Used by the single-run and the batched
+// kernels, so both produce bit-identical states.
+template <int D, typename TR, typename TM>
+__device__ __forceinline__ void step_cell(const TR* __restrict__ sr, const TM* __restrict__ sm,
+                                          TR* __restrict__ dr, TM* __restrict__ dm, int x, int y,
+                                          int z, int nx, int ny, int nz, int64_t stride,
+                                          const Coef& k) {
+  const int64_t plane = static_cast<int64_t>(nx) * ny;
+  const int64_t c = static_cast<int64_t>(z) * plane + static_cast<int64_t>(y) * nx + x;
+  float g[D + 1][2 * D + 1];
+  gather_cell<D, TR, TM>(sr, sm, x, y, z, nx, ny, nz, stride, c, g);
   collide<D>(g, k);
 #pragma unroll
   for (int i = 0; i < D + 1; ++i) {

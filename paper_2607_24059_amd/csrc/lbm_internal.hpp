@@ -34,6 +34,8 @@ struct Ops {
                      void* dst, hipStream_t s);
   hipError_t (*step)(const Geometry&, const RunCoef&, const void* src, void* dst, int bx, int by,
                      hipStream_t s);
+  // two steps in one launch (2D only; nullptr where not available)
+  hipError_t (*step2)(const Geometry&, const RunCoef&, const void* src, void* dst, hipStream_t s);
   hipError_t (*moments)(const Geometry&, const RunCoef&, const void* src, double* out64,
                         float* out32, hipStream_t s);
   hipError_t (*diag)(const Geometry&, const RunCoef&, const void* src, double* partials,
@@ -106,4 +108,5 @@ struct lbm_ctx {
   hipStream_t stream;
   int64_t steps;
   int bx, by;       // step kernel block shape
+  int fuse;         // time steps per launch: 1, or 2 (2D two-step kernel)
 };

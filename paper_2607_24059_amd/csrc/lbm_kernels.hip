@@ -57,6 +57,64 @@ __global__ __launch_bounds__(256) void k_step(const TR* __restrict__ sr,
 }
 
 // ----------------------------------------------------------------------------
+// two steps in one launch (2D): the block advances its TX x TY tile plus a
+// one-cell border by one step, keeps that intermediate state in LDS in the
+// storage type (rounded exactly as a store to HBM would be), then advances the
+// tile by the second step reading the border from LDS.  Each state value is
+// read from HBM (TX+2)(TY+2)/(TX TY) times and written once per two steps, and
+// the result is bit-identical to two single steps.
+// ----------------------------------------------------------------------------
+template <typename TR, typename TM, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_step2_2d(const TR* __restrict__ sr, const TM* __restrict__ sm,
+                                                  TR* __restrict__ dr, TM* __restrict__ dm, int nx, int ny,
+                                                  int64_t stride, Coef k) {
+  constexpr int EX = TX + 2, EY = TY + 2, EN = EX * EY;
+  __shared__ TR s_rest[3][EN];
+  __shared__ TM s_move[12][EN];
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  for (int e = threadIdx.x; e < EN; e += NT) {
+    const int ex = e % EX, ey = e / EX;
+    int x = x0 - 1 + ex, y = y0 - 1 + ey;
+    x = ((x % nx) + nx) % nx;  // the border may wrap (several times on tiny grids)
+    y = ((y % ny) + ny) % ny;
+    const int64_t c = static_cast<int64_t>(y) * nx + x;
+    float g[3][5];
+    gather_cell<2, TR, TM>(sr, sm, x, y, 0, nx, ny, 1, stride, c, g);
+    collide<2>(g, k);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      store_f32(&s_rest[i][e], g[i][0]);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) store_f32(&s_move[i * 4 + m][e], g[i][1 + m]);
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < TX * TY; t += NT) {
+    const int tx = t % TX, ty = t / TX;
+    const int x = x0 + tx, y = y0 + ty;
+    if (x >= nx || y >= ny) continue;
+    const int e = (ty + 1) * EX + (tx + 1);
+    float g[3][5];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      g[i][0] = load_f32(&s_rest[i][e]);
+      g[i][1] = load_f32(&s_move[i * 4 + 0][e - 1]);   // +x from x-1
+      g[i][2] = load_f32(&s_move[i * 4 + 1][e + 1]);   // -x from x+1
+      g[i][3] = load_f32(&s_move[i * 4 + 2][e - EX]);  // +y from y-1
+      g[i][4] = load_f32(&s_move[i * 4 + 3][e + EX]);  // -y from y+1
+    }
+    collide<2>(g, k);
+    const int64_t c = static_cast<int64_t>(y) * nx + x;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      store_stream(dr + i * stride + c, g[i][0]);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) store_stream(dm + (i * 4 + m) * stride + c, g[i][1 + m]);
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
 // moments: rho = ref + sum_l g_rho,l and q_j = (sum_l g_qj,l) / dx, in FP64
 // ----------------------------------------------------------------------------
 template <int D, typename TR, typename TM>
@@ -291,6 +349,27 @@ struct Impl {
     return hipGetLastError();
   }
 
+  // Tile of the two-step kernel, measured on MI355X at 4096^2 (cells x cells,
+  // threads): 4-byte planes 64x8 on 512 threads (79 GLUPS; 64x8/256: 76,
+  // 128x4: 78, 32x8: 64, 256x4: 56); 2-byte planes 128x8 on 256 threads
+  // (138 GLUPS; 64x8: 119, 128x4: 131).
+  static constexpr bool kWide = sizeof(TM) == 4;
+  static constexpr int kT2X = kWide ? 64 : 128, kT2Y = 8, kT2N = kWide ? 512 : 256;
+
+  static hipError_t step2(const Geometry& g, const RunCoef& r, const void* src, void* dst, hipStream_t s) {
+    if constexpr (D != 2) {
+      return hipErrorInvalidValue;
+    } else {
+      auto a = planes_of<TR, TM>(const_cast<void*>(src), g.rest_bytes);
+      auto b = planes_of<TR, TM>(dst, g.rest_bytes);
+      const Coef k = make_coef<float>(r, D, DEV);
+      dim3 grid((g.nx + kT2X - 1) / kT2X, (g.ny + kT2Y - 1) / kT2Y, 1);
+      hipLaunchKernelGGL((k_step2_2d<TR, TM, kT2X, kT2Y, kT2N>), grid, dim3(kT2N), 0, s, a.rest, a.move, b.rest,
+                         b.move, g.nx, g.ny, g.stride, k);
+      return hipGetLastError();
+    }
+  }
+
   static hipError_t moments(const Geometry& g, const RunCoef& r, const void* src, double* out64,
                             float* out32, hipStream_t s) {
     auto a = planes_of<TR, TM>(const_cast<void*>(src), g.rest_bytes);
@@ -324,7 +403,7 @@ struct Impl {
   }
 
   static const Ops* ops() {
-    static const Ops o = {&init, &step, &moments, &diag, &diag_blocks};
+    static const Ops o = {&init, &step, D == 2 ? &step2 : nullptr, &moments, &diag, &diag_blocks};
     return &o;
   }
 };

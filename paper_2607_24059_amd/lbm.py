@@ -76,6 +76,7 @@ SIGNATURES = {
     "lbm_init": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(lbm_params), C.c_void_p, C.c_void_p,
                            C.c_void_p, C.c_size_t, C.c_void_p]),
     "lbm_step": (C.c_int, [C.c_void_p, C.c_int64]),
+    "lbm_set_fusion": (C.c_int, [C.c_void_p, C.c_int32]),
     "lbm_moments": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "lbm_moments_device": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lbm_diagnostics": (C.c_int, [C.c_void_p, C.POINTER(lbm_diag)]),
@@ -151,6 +152,10 @@ def lbm_init(p: lbm_params, u0: np.ndarray, rho0: np.ndarray | None, workspace_p
 
 def lbm_step(ctx: int, nsteps: int) -> None:
     _ok(lib().lbm_step(C.c_void_p(ctx), C.c_int64(nsteps)), "lbm_step")
+
+
+def lbm_set_fusion(ctx: int, steps_per_launch: int) -> None:
+    _ok(lib().lbm_set_fusion(C.c_void_p(ctx), int(steps_per_launch)), "lbm_set_fusion")
 
 
 def lbm_moments(ctx: int, rho: np.ndarray, q: np.ndarray | None) -> None:
@@ -249,6 +254,9 @@ class Engine:
 
     def step(self, n: int) -> None:
         lbm_step(self.ctx, n)
+
+    def set_fusion(self, steps_per_launch: int) -> None:
+        lbm_set_fusion(self.ctx, steps_per_launch)
 
     def moments(self):
         rho = np.empty(self.shape)

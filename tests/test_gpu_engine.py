@@ -188,7 +188,7 @@ def test_nonfinite_reported():
     blob = eng.save_state()
     f = blob[:-8].view(np.float32)
     f[5] = np.nan          # rho rest plane, cell 5
-    f[n * n + 7] = np.inf  # q_x rest plane (plane stride is n*n rounded to 256 = 256), cell 7
+    f[n * n + 7] = np.inf  # q_x rest plane (the snapshot holds cells x planes, no padding), cell 7
     eng.load_state(blob)
     d = eng.diagnostics()
     eng.close()
@@ -256,3 +256,33 @@ def test_full_size_3d_256_sampled():
         r_ref, q_ref = _patch_reference(u0, p, centre, steps)
         assert abs(rho[centre] - r_ref) <= 1e-6
         assert np.max(np.abs(q[(slice(None),) + centre] - q_ref)) <= 1e-5 * 0.05 / p.dx
+
+
+# --------------------------------------------------------------------------- #
+# two steps per launch (2D): bit-identical to single-step launches            #
+# --------------------------------------------------------------------------- #
+
+@pytest.mark.parametrize("storage", ["f32", "f16_dev", "bf16_dev", "f16_dev_r32", "f32_raw"])
+@pytest.mark.parametrize("shape,steps", [((64, 64), 10), ((75, 75), 11), ((9, 130), 7), ((200, 3), 8),
+                                         ((1, 1), 4), ((300, 257), 5)])
+def test_two_step_fusion_is_bitwise(storage, shape, steps):
+    ny, nx = shape
+    dx = 2 * math.pi / max(shape)
+    p = scheme.Params(dim=2, dx=dx, dt=dx * dx / 8, nu=0.02)
+    u = inputs.random_field_box(shape, dx, seed=11, umax=0.05 / dx)
+    blobs = []
+    for fuse in (1, 2):
+        eng = _engine(p, u, storage=storage)
+        eng.set_fusion(fuse)
+        eng.step(steps)
+        blobs.append(eng.save_state())
+        eng.close()
+    assert np.array_equal(blobs[0], blobs[1])
+
+
+def test_two_step_fusion_not_available_in_3d():
+    p = scheme.params_for_grid(3, 8, 0.01)
+    eng = _engine(p, inputs.abc_flow(8, 0.1, 0.1, 0.1))
+    with pytest.raises(lbm.LbmError):
+        eng.set_fusion(2)
+    eng.close()
