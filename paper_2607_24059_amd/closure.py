@@ -373,6 +373,16 @@ def solenoidal(u):
     return np.stack([np.fft.ifft2(ux - kx * div / k2).real, np.fft.ifft2(uy - ky * div / k2).real])
 
 
+def rel_q(m, ref, sol=False):
+    """Relative L2 error of the momentum q (the conserved moment; rho = 1 + O(dx^2)
+    in the incompressible limit, so q and u agree to leading order while q needs
+    no density, whose deviation scales with dx^2 and differs on every grid)."""
+    q, qr = m[1:], ref[1:]
+    if sol:
+        q, qr = solenoidal(q), solenoidal(qr)
+    return float(np.linalg.norm((q - qr).ravel()) / np.linalg.norm(qr.ravel()))
+
+
 def rel_u_sol(m, ref):
     """Relative L2 error of the divergence-free part of u.  The scheme's
     artificial compressibility carries acoustic waves whose speed 1/dx differs
@@ -396,7 +406,9 @@ def evaluate(cfg: Config, net, scales, log=print, seeds=None, storage="f32", lev
     chunks = cfg.horizon // cfg.every
     res = {"plain": {n: [] for n in levels}, "closure": [], "time_plain": {n: 0.0 for n in levels},
            "time_closure": 0.0, "accepted": 0, "rejected": 0,
-           "plain_raw": {n: [] for n in levels}, "closure_raw": []}
+           "plain_raw": {n: [] for n in levels}, "closure_raw": [],
+           "plain_q": {n: [] for n in levels}, "closure_q": [], "plain_qsol": {n: [] for n in levels},
+           "closure_qsol": []}
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     mbuf = torch.empty((3, nc, nc), dtype=torch.float32, device="cuda")
@@ -426,6 +438,8 @@ def evaluate(cfg: Config, net, scales, log=print, seeds=None, storage="f32", lev
             res["time_plain"][n] += ev0.elapsed_time(ev1)
             res["plain"][n].append(rel_u_sol(_host(mbuf), judge_h))
             res["plain_raw"][n].append(rel_u(_host(mbuf), judge_h))
+            res["plain_q"][n].append(rel_q(_host(mbuf), judge_h))
+            res["plain_qsol"][n].append(rel_q(_host(mbuf), judge_h, True))
             eng.close()
         run = CorrectedRun(cfg, net, scales, starts[nc], storage=storage, use_graph=use_graph)
         if use_graph:
@@ -443,12 +457,18 @@ def evaluate(cfg: Config, net, scales, log=print, seeds=None, storage="f32", lev
         torch.cuda.synchronize()
         res["closure"].append(rel_u_sol(_host(mbuf), judge_h))
         res["closure_raw"].append(rel_u(_host(mbuf), judge_h))
+        res["closure_q"].append(rel_q(_host(mbuf), judge_h))
+        res["closure_qsol"].append(rel_q(_host(mbuf), judge_h, True))
         run.close()
         log(f"[closure] seed {seed}: solenoidal error plain " +
             ", ".join(f"{n}: {res['plain'][n][-1]:.3e}" for n in levels)
             + f"; corrected {nc}: {res['closure'][-1]:.3e} | raw plain "
             + ", ".join(f"{n}: {res['plain_raw'][n][-1]:.3e}" for n in levels)
-            + f"; corrected {res['closure_raw'][-1]:.3e} (accepted {rep['n_accepted']}, "
+            + f"; corrected {res['closure_raw'][-1]:.3e} | q plain "
+            + ", ".join(f"{n}: {res['plain_q'][n][-1]:.3e}" for n in levels)
+            + f"; corrected {res['closure_q'][-1]:.3e} | q_sol plain "
+            + ", ".join(f"{n}: {res['plain_qsol'][n][-1]:.3e}" for n in levels)
+            + f"; corrected {res['closure_qsol'][-1]:.3e} (accepted {rep['n_accepted']}, "
               f"rejected {rep['n_rejected']})")
     out = {"plain": {str(n): float(np.mean(v)) for n, v in res["plain"].items()},
            "closure": float(np.mean(res["closure"])),
@@ -457,6 +477,10 @@ def evaluate(cfg: Config, net, scales, log=print, seeds=None, storage="f32", lev
            "time_closure_ms": res["time_closure"] / len(seeds),
            "plain_raw": {str(n): float(np.mean(v)) for n, v in res["plain_raw"].items()},
            "closure_raw": float(np.mean(res["closure_raw"])),
+           "plain_q": {str(n): float(np.mean(v)) for n, v in res["plain_q"].items()},
+           "closure_q": float(np.mean(res["closure_q"])),
+           "plain_qsol": {str(n): float(np.mean(v)) for n, v in res["plain_qsol"].items()},
+           "closure_qsol": float(np.mean(res["closure_qsol"])),
            "accepted": res["accepted"], "rejected": res["rejected"], "seeds": list(seeds),
            "horizon": cfg.horizon, "storage": storage}
     out["speedup_equal_error"] = equal_error_speedup(out)

@@ -349,12 +349,11 @@ struct Impl {
     return hipGetLastError();
   }
 
-  // Tile of the two-step kernel, measured on MI355X at 4096^2 (cells x cells,
-  // threads): 4-byte planes 64x8 on 512 threads (79 GLUPS; 64x8/256: 76,
-  // 128x4: 78, 32x8: 64, 256x4: 56); 2-byte planes 128x8 on 256 threads
-  // (138 GLUPS; 64x8: 119, 128x4: 131).
-  static constexpr bool kWide = sizeof(TM) == 4;
-  static constexpr int kT2X = kWide ? 64 : 128, kT2Y = 8, kT2N = kWide ? 512 : 256;
+  // Tile of the two-step kernel: 128x8 cells on 512 threads, the fastest shape
+  // measured on MI355X at 4096^2 for 4- and 2-byte planes (FP32 81 GLUPS, FP16
+  // 147 GLUPS; 64x8/512: 77/127, 64x8/256: 76/119, 128x4: 78/131,
+  // 256x2: 80/123, 32x8: 64/83).
+  static constexpr int kT2X = 128, kT2Y = 8, kT2N = 512;
 
   static hipError_t step2(const Geometry& g, const RunCoef& r, const void* src, void* dst, hipStream_t s) {
     if constexpr (D != 2) {

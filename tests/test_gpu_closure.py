@@ -153,7 +153,10 @@ def test_end_to_end_small_configuration():
     cfg = cl.Config(coarse_n=64, factor=4, train_seeds=[0, 1], test_seeds=[1000], pairs_per_seed=4,
                     horizon=16, epochs=2, batch=2, eval_levels=(64, 128))
     x, t, scales = cl.build_dataset(cfg, log=lambda *a: None)
-    assert x.shape == (8, 3, 64, 64) and all(math.isfinite(v) and v > 0 for v in scales.values())
+    assert tuple(x.shape) == (8, 3, 64, 64)
+    assert all(math.isfinite(v) for v in scales.values())
+    assert scales["s_rho"] > 0 and scales["s_u"] > 0 and scales["s_dq"] > 0
+    assert scales["s_drho"] == 0.0  # divergence-free targets: momentum-only correction
     net, hist = cl.train(cfg, x, t, log=lambda *a: None)
     assert all(math.isfinite(h) for h in hist)
     ev = cl.evaluate(cfg, net, scales, log=lambda *a: None)
