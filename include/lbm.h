@@ -45,7 +45,8 @@ typedef enum lbm_status {
   LBM_ESTATE = 6       /* state blob of the wrong size or layout */
 } lbm_status;
 
-/* Storage of the distributions in HBM.  Arithmetic is FP32 in every mode.
+/* Storage of the distributions in HBM.  Arithmetic is FP32 in every mode
+ * except LBM_F64, which loads, updates and stores FP64.
  * Every mode except LBM_F32_RAW stores g = f - fbar, the deviation from the
  * reference equilibrium fbar = f^eq(rho_ref, q = 0); the collision works on g
  * directly (the equilibria are affine in W_rho for P(rho) = rho), so the large
@@ -57,14 +58,19 @@ typedef enum lbm_status {
  *   LBM_F16_DEV_R32   moving populations as FP16 g, the rest population of
  *                     each set as FP32 g
  *   LBM_BF16_DEV_R32  as above with BF16 moving populations
- *   LBM_F32_RAW       the populations f themselves in FP32                */
+ *   LBM_F32_RAW       the populations f themselves in FP32
+ *   LBM_F64           g in FP64 with FP64 arithmetic: the reference mode for
+ *                     long fine-grid runs, where FP32 rounding accumulates over
+ *                     many steps; one step per launch (lbm_set_fusion(2)
+ *                     fails) and not available in lbm_batch              */
 typedef enum lbm_storage {
   LBM_F32 = 0,
   LBM_F16_DEV = 1,
   LBM_BF16_DEV = 2,
   LBM_F16_DEV_R32 = 3,
   LBM_BF16_DEV_R32 = 4,
-  LBM_F32_RAW = 5
+  LBM_F32_RAW = 5,
+  LBM_F64 = 6
 } lbm_storage;
 
 /* Flag bits reported in lbm_diag.flags and by lbm_check_params(). */

@@ -119,7 +119,9 @@ class Config:
     lr: float = 1e-3
     guard: float = 2.0
     eval_levels: tuple = (256, 512, 1024)
-    project_targets: bool = True   # train on the divergence-free part of the momentum difference
+    project_targets: bool = True   # correct the divergence-free momentum only (else rho and q)
+    fine_storage: str = "f64"      # the fine reference runs: FP32 rounding accumulates over their
+                                   # factor^2 more steps to well above the coarse error
 
     @property
     def fine_n(self):
@@ -160,7 +162,7 @@ class FineRun:
         self.nf = cfg.fine_n
         self.stream = stream
         u0, rho0 = _field(cfg, self.nf, seed)
-        self.eng = _engine(cfg, self.nf, u0, rho0=rho0)
+        self.eng = _engine(cfg, self.nf, u0, storage=cfg.fine_storage, rho0=rho0)
         self.m = torch.empty((3, self.nf, self.nf), dtype=torch.float32, device="cuda")
 
     def advance(self, coarse_steps: int) -> None:
@@ -175,66 +177,85 @@ class FineRun:
         self.eng.close()
 
 
-def coarse_after(cfg: Config, eng: Engine, m0, out):
-    """Coarse moments after `every` plain steps from the equilibrium of m0."""
-    lbm_set_equilibrium_device(eng.ctx, m0)
-    eng.step(cfg.every)
-    eng.moments_device(out)
-
-
-def _project_targets(t):
-    """Data preparation (not part of the corrected run): keep the divergence-free
-    part of each momentum difference and no density difference.  The fine and
-    coarse grids carry acoustic waves at different speeds (1/dx) whose relative
-    phase over a window no coarse-grid model can predict; the solenoidal part is
-    the incompressible dynamics the correction can learn."""
+def _projected_next(m_c, m_f, out, stream, project=True):
+    """out = m_c + P(m_f - m_c) with P keeping the divergence-free part of the
+    momentum difference and no density difference (host data preparation).
+    The fine and coarse grids carry acoustic waves at different speeds (1/dx)
+    whose relative phase no coarse-grid model can predict; the solenoidal part
+    is the incompressible dynamics the correction can learn."""
     import torch
-    for i in range(t.shape[0]):
-        th = t[i].double().cpu().numpy()
-        th[1:] = solenoidal(th[1:])
-        th[0] = 0.0
-        t[i].copy_(torch.from_numpy(th))
+    if not project:
+        out.copy_(m_f)
+        return
+    stream.synchronize()
+    mc = m_c.double().cpu().numpy()
+    d = m_f.double().cpu().numpy() - mc
+    nxt = mc.copy()
+    if d.shape[0] == 3:
+        nxt[1:] += solenoidal(d[1:])
+    out.copy_(torch.from_numpy(nxt))
 
 
 def build_dataset(cfg: Config, log=print):
-    """Pairs (coarse state after `every` steps from a restricted fine snapshot,
-    restricted fine snapshot `every` coarse steps later), windows spread over
-    the evaluation horizon; returns the network inputs, targets and scales."""
+    """Training pairs along a shadow coarse trajectory.
+
+    For each training seed a fine run (FP64 storage) and a coarse run start
+    from the same restricted state.  After every window of `every` coarse
+    steps the pair (coarse moments, restricted fine moments) is formed, and
+    the coarse run is nudged onto the fine one by the same guarded correction
+    the corrected run applies (its populations keep their non-equilibrium
+    part), with the projected difference as the correction.  So the network
+    sees coarse states exactly as the corrected run produces them, not states
+    freshly set to equilibrium (whose first step lacks the viscous flux of the
+    non-equilibrium part).  pairs_per_seed windows, evenly spread over the
+    horizon, are kept; returns the network inputs, targets and scales."""
     import torch
     s = torch.cuda.current_stream()
     nc = cfg.coarse_n
     cells = nc * nc
-    stride = max(cfg.every, cfg.horizon // cfg.pairs_per_seed)
+    windows = max(1, cfg.horizon // cfg.every)
+    keep_every = max(1, windows // cfg.pairs_per_seed)
     P = len(cfg.train_seeds) * cfg.pairs_per_seed
     mc = torch.empty((P, 3, nc, nc), dtype=torch.float32, device="cuda")
     mn = torch.empty_like(mc)
-    m_start = torch.empty((3, nc, nc), dtype=torch.float32, device="cuda")
+    m_c = torch.empty((3, nc, nc), dtype=torch.float32, device="cuda")
+    m_f = torch.empty_like(m_c)
+    m_next = torch.empty_like(m_c)
+    y = torch.empty_like(m_c)
     rng = np.random.default_rng(12345)
     perm = rng.permutation(P)  # shuffled storage order: minibatches are contiguous slices
-    ceng = _engine(cfg, nc)
     t0 = time.time()
     for si, seed in enumerate(cfg.train_seeds):
         fine = FineRun(cfg, seed, s)
-        for k in range(cfg.pairs_per_seed):
-            j = int(perm[si * cfg.pairs_per_seed + k])
-            fine.restricted(nc, m_start)
-            coarse_after(cfg, ceng, m_start, mc[j])
+        ceng = _engine(cfg, nc)
+        fine.restricted(nc, m_f)
+        lbm_set_equilibrium_device(ceng.ctx, m_f)
+        k = 0
+        for w in range(windows):
+            ceng.step(cfg.every)
+            ceng.moments_device(m_c)
             fine.advance(cfg.every)
-            fine.restricted(nc, mn[j])
-            fine.advance(stride - cfg.every)
+            fine.restricted(nc, m_f)
+            _projected_next(m_c, m_f, m_next, s, cfg.project_targets)
+            if w % keep_every == keep_every - 1 and k < cfg.pairs_per_seed:
+                j = int(perm[si * cfg.pairs_per_seed + k])
+                mc[j].copy_(m_c)
+                mn[j].copy_(m_next)
+                k += 1
+            # nudge: g += f^eq(W + dW) - f^eq(W), dW = projected difference
+            lbm_closure_target(m_next, m_c, cells, 1.0, 1.0, y, s)
+            lbm_closure_apply(ceng.ctx, m_c, y, 1.0, 1.0, 1e30)
+        ceng.close()
         fine.close()
         if si % 20 == 0:
             torch.cuda.synchronize()
             log(f"[closure] data seed {seed} ({si + 1}/{len(cfg.train_seeds)}) {time.time() - t0:.1f}s")
-    ceng.close()
     # scales: rms of the raw features and of the raw moment differences
     x = torch.empty_like(mc)
     t = torch.empty_like(mc)
     for i in range(P):
         lbm_closure_features(mc[i], 2, cells, 1.0, 1.0, 1.0, x[i], s)
         lbm_closure_target(mn[i], mc[i], cells, 1.0, 1.0, t[i], s)
-    if cfg.project_targets:
-        _project_targets(t)
     picks = range(0, P, max(1, P // 64))
     raw = np.zeros(3)
     rawd = np.zeros(3)
@@ -250,7 +271,6 @@ def build_dataset(cfg: Config, log=print):
         lbm_closure_features(mc[i], 2, cells, 1.0, scales["s_rho"], scales["s_u"], x[i], s)
         lbm_closure_target(mn[i], mc[i], cells, scales["s_drho"], scales["s_dq"], t[i], s)
     if cfg.project_targets:
-        _project_targets(t)
         scales["s_drho"] = 0.0  # the correction moves momentum only
     torch.cuda.synchronize()
     log(f"[closure] dataset: {P} pairs, scales {scales}, {time.time() - t0:.1f}s")
@@ -542,6 +562,9 @@ def main(argv=None):
     ap.add_argument("--horizon", type=int, default=256)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--every", type=int, default=4)
+    ap.add_argument("--full-targets", action="store_true",
+                    help="correct rho and the whole momentum, not only its divergence-free part")
     ap.add_argument("--out", default="closure_model.npz")
     ap.add_argument("--json", default=None)
     args = ap.parse_args(argv)
@@ -549,7 +572,8 @@ def main(argv=None):
     torch.cuda.set_device(0)
     cfg = Config(train_seeds=list(range(args.train_seeds)),
                  test_seeds=list(range(1000, 1000 + args.test_seeds)),
-                 pairs_per_seed=args.pairs, horizon=args.horizon, epochs=args.epochs, lr=args.lr)
+                 pairs_per_seed=args.pairs, horizon=args.horizon, epochs=args.epochs, lr=args.lr,
+                 every=args.every, project_targets=not args.full_targets)
 
     def log(*a):
         print(*a, file=sys.stderr, flush=True)

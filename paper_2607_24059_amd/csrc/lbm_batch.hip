@@ -299,7 +299,7 @@ std::string device_key() {
 extern "C" {
 
 size_t lbm_batch_workspace_bytes(int32_t dim, int32_t storage, int32_t nruns, const lbm_run_spec* runs) {
-  if (nruns <= 0 || !runs) return 0;
+  if (nruns <= 0 || !runs || !batch_kernel(dim, storage)) return 0;
   for (int r = 0; r < nruns; ++r) {
     lbm_params p = params_of(dim, storage, runs[r]);
     if (lbm_check_params(&p, nullptr, nullptr, nullptr) != LBM_OK) return 0;
@@ -312,6 +312,7 @@ lbm_status lbm_batch_init(lbm_batch** out, int32_t dim, int32_t storage, int32_t
                           void* workspace, size_t ws_bytes, void* hip_stream, int32_t* bad_run) {
   if (!out || !runs || !u0 || !workspace || nruns <= 0) return LBM_EINVAL;
   *out = nullptr;
+  if (!batch_kernel(dim, storage)) return LBM_EINVAL;  // no batched FP64 reference mode
   if (bad_run) *bad_run = -1;
   std::vector<RunCoef> coefs;
   for (int r = 0; r < nruns; ++r) {

@@ -91,9 +91,9 @@ __global__ __launch_bounds__(256) void k_set_eq(const float* __restrict__ m, int
   equilibrium<D, double>(W, 1.0 / rho, k, eq);
 #pragma unroll
   for (int i = 0; i < D + 1; ++i) {
-    store_f32(rest + i * stride + c, static_cast<float>(eq[i][0]));
+    store_real(rest + i * stride + c, eq[i][0]);
 #pragma unroll
-    for (int v = 0; v < 2 * D; ++v) store_f32(move + (i * 2 * D + v) * stride + c, static_cast<float>(eq[i][1 + v]));
+    for (int v = 0; v < 2 * D; ++v) store_real(move + (i * 2 * D + v) * stride + c, eq[i][1 + v]);
   }
 }
 
@@ -201,9 +201,9 @@ __global__ __launch_bounds__(256) void k_cl_apply(const float* __restrict__ y, i
   double W[D + 1];
 #pragma unroll
   for (int i = 0; i < D + 1; ++i) {
-    double a = static_cast<double>(load_f32(rest + i * stride + c));
+    double a = load_f64(rest + i * stride + c);
 #pragma unroll
-    for (int v = 0; v < 2 * D; ++v) a += static_cast<double>(load_f32(move + (i * 2 * D + v) * stride + c));
+    for (int v = 0; v < 2 * D; ++v) a += load_f64(move + (i * 2 * D + v) * stride + c);
     W[i] = a;
   }
   W[0] += ref;  // full density; k.ref = 0 so both equilibria below are the plain ones
@@ -218,11 +218,11 @@ __global__ __launch_bounds__(256) void k_cl_apply(const float* __restrict__ y, i
 #pragma unroll
   for (int i = 0; i < D + 1; ++i) {
     TR* pr = rest + i * stride + c;
-    store_f32(pr, static_cast<float>(static_cast<double>(load_f32(pr)) + (e1[i][0] - e0[i][0])));
+    store_real(pr, load_f64(pr) + (e1[i][0] - e0[i][0]));
 #pragma unroll
     for (int v = 0; v < 2 * D; ++v) {
       TM* pm = move + (i * 2 * D + v) * stride + c;
-      store_f32(pm, static_cast<float>(static_cast<double>(load_f32(pm)) + (e1[i][1 + v] - e0[i][1 + v])));
+      store_real(pm, load_f64(pm) + (e1[i][1 + v] - e0[i][1 + v]));
     }
   }
 }
@@ -255,6 +255,7 @@ hipError_t dispatch_set_eq(lbm_ctx* c, const float* m) {
     case LBM_BF16_DEV: return ClosureImpl<D, bf16, bf16, true>::set_eq(c, m);
     case LBM_F16_DEV_R32: return ClosureImpl<D, float, _Float16, true>::set_eq(c, m);
     case LBM_BF16_DEV_R32: return ClosureImpl<D, float, bf16, true>::set_eq(c, m);
+    case LBM_F64: return ClosureImpl<D, double, double, true>::set_eq(c, m);
   }
   return hipErrorInvalidValue;
 }
@@ -267,6 +268,7 @@ hipError_t dispatch_apply(lbm_ctx* c, const float* y, float s_drho, float s_dq, 
     case LBM_BF16_DEV: return ClosureImpl<2, bf16, bf16, true>::apply(c, y, s_drho, s_dq, slots);
     case LBM_F16_DEV_R32: return ClosureImpl<2, float, _Float16, true>::apply(c, y, s_drho, s_dq, slots);
     case LBM_BF16_DEV_R32: return ClosureImpl<2, float, bf16, true>::apply(c, y, s_drho, s_dq, slots);
+    case LBM_F64: return ClosureImpl<2, double, double, true>::apply(c, y, s_drho, s_dq, slots);
   }
   return hipErrorInvalidValue;
 }

@@ -54,6 +54,35 @@ __device__ __forceinline__ uint16_t bf16_bits(float v) {
 }
 __device__ __forceinline__ void store_f32(bf16* p, float v) { p->bits = bf16_bits(v); }
 
+// FP64 storage (the reference mode): loaded, updated and stored in FP64.
+__device__ __forceinline__ double load_f64(const double* p) { return *p; }
+template <typename T>
+__device__ __forceinline__ double load_f64(const T* p) { return static_cast<double>(load_f32(p)); }
+
+// Store an FP64 value: kept whole in FP64 storage, otherwise rounded to FP32
+// first and then to the element type (the rounding of every FP32 path).
+__device__ __forceinline__ void store_real(double* p, double v) { *p = v; }
+template <typename T>
+__device__ __forceinline__ void store_real(T* p, double v) { store_f32(p, static_cast<float>(v)); }
+
+// Arithmetic type of the update for a storage element type.
+template <typename T>
+struct ComputeOf {
+  using type = float;
+};
+template <>
+struct ComputeOf<double> {
+  using type = double;
+};
+
+template <typename R>
+__device__ __forceinline__ R load_as(const double* p) { return static_cast<R>(*p); }
+template <typename R, typename T>
+__device__ __forceinline__ R load_as(const T* p) { return static_cast<R>(load_f32(p)); }
+
+__device__ __forceinline__ float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // Streaming stores for the step kernel: the next step reads these values from
 // HBM anyway (the state is far larger than the caches), so they are written
 // with the non-temporal hint and do not displace the neighbour lines that the
@@ -65,6 +94,7 @@ __device__ __forceinline__ void store_stream(_Float16* p, float v) {
 __device__ __forceinline__ void store_stream(bf16* p, float v) {
   __builtin_nontemporal_store(bf16_bits(v), reinterpret_cast<uint16_t*>(p));
 }
+__device__ __forceinline__ void store_stream(double* p, double v) { __builtin_nontemporal_store(v, p); }
 
 // ----------------------------------------------------------------------------
 // lattice description: D2Q5 / D3Q7 per set, D+1 sets
@@ -133,25 +163,26 @@ __device__ __forceinline__ void equilibrium(const R (&W)[D + 1], R inv, const Co
 }
 
 // Relax the populations of one cell in place: f* = f + omega (f^eq - f),
-// equation (LBM_scheme).  g[i][l] holds plain values (ref = 0) or deviations.
-template <int D>
-__device__ __forceinline__ void collide(float (&g)[D + 1][2 * D + 1], const Coef& k) {
-  float W[D + 1];
+// equation (LBM_scheme).  g[i][l] holds plain values (ref = 0) or deviations;
+// R is the arithmetic type (FP32, or FP64 for the FP64 storage).
+template <int D, typename R>
+__device__ __forceinline__ void collide(R (&g)[D + 1][2 * D + 1], const CoefT<R>& k) {
+  R W[D + 1];
 #pragma unroll
   for (int i = 0; i < D + 1; ++i) {
-    float s = g[i][0];
+    R s = g[i][0];
 #pragma unroll
     for (int l = 1; l < 2 * D + 1; ++l) s = s + g[i][l];
     W[i] = s;
   }
-  const float inv = 1.0f / (W[0] + k.ref);
-  float eq[D + 1][2 * D + 1];
-  equilibrium<D, float>(W, inv, k, eq);
+  const R inv = R(1) / (W[0] + k.ref);
+  R eq[D + 1][2 * D + 1];
+  equilibrium<D, R>(W, inv, k, eq);
 #pragma unroll
   for (int i = 0; i < D + 1; ++i) {
-    const float w = (i == 0) ? k.w_rho : k.w_q;
+    const R w = (i == 0) ? k.w_rho : k.w_q;
 #pragma unroll
-    for (int l = 0; l < 2 * D + 1; ++l) g[i][l] = __builtin_fmaf(w, eq[i][l] - g[i][l], g[i][l]);
+    for (int l = 0; l < 2 * D + 1; ++l) g[i][l] = fma_r(w, eq[i][l] - g[i][l], g[i][l]);
   }
 }
 
@@ -159,10 +190,10 @@ __device__ __forceinline__ void collide(float (&g)[D + 1][2 * D + 1], const Coef
 // Gather the post-relaxation values of the upwind neighbours of cell (x, y, z):
 // the pull form of the transport phase, f_{+e_j}(t+dt, x) = f*_{+e_j}(t, x - dx e_j),
 // on the periodic grid.  c is the cell's linear index.
-template <int D, typename TR, typename TM>
+template <int D, typename TR, typename TM, typename R>
 __device__ __forceinline__ void gather_cell(const TR* __restrict__ sr, const TM* __restrict__ sm, int x, int y,
                                             int z, int nx, int ny, int nz, int64_t stride, int64_t c,
-                                            float (&g)[D + 1][2 * D + 1]) {
+                                            R (&g)[D + 1][2 * D + 1]) {
   const int64_t plane = static_cast<int64_t>(nx) * ny;
   int64_t src[2 * D];
   src[0] = (x == 0) ? c + (nx - 1) : c - 1;                                   // +x from x-1
@@ -175,9 +206,9 @@ __device__ __forceinline__ void gather_cell(const TR* __restrict__ sr, const TM*
   }
 #pragma unroll
   for (int i = 0; i < D + 1; ++i) {
-    g[i][0] = load_f32(sr + i * stride + c);
+    g[i][0] = load_as<R>(sr + i * stride + c);
 #pragma unroll
-    for (int m = 0; m < 2 * D; ++m) g[i][1 + m] = load_f32(sm + (i * 2 * D + m) * stride + src[m]);
+    for (int m = 0; m < 2 * D; ++m) g[i][1 + m] = load_as<R>(sm + (i * 2 * D + m) * stride + src[m]);
   }
 }
 
@@ -185,16 +216,16 @@ __device__ __forceinline__ void gather_cell(const TR* __restrict__ sr, const TM*
 // write the cell's own post-relaxation values.  Every stored value is read
 // once and written once per step.  Used by the single-run and the batched
 // kernels, so both produce bit-identical states.
-template <int D, typename TR, typename TM>
+template <int D, typename TR, typename TM, typename R = typename ComputeOf<TM>::type>
 __device__ __forceinline__ void step_cell(const TR* __restrict__ sr, const TM* __restrict__ sm,
                                           TR* __restrict__ dr, TM* __restrict__ dm, int x, int y,
                                           int z, int nx, int ny, int nz, int64_t stride,
-                                          const Coef& k) {
+                                          const CoefT<R>& k) {
   const int64_t plane = static_cast<int64_t>(nx) * ny;
   const int64_t c = static_cast<int64_t>(z) * plane + static_cast<int64_t>(y) * nx + x;
-  float g[D + 1][2 * D + 1];
-  gather_cell<D, TR, TM>(sr, sm, x, y, z, nx, ny, nz, stride, c, g);
-  collide<D>(g, k);
+  R g[D + 1][2 * D + 1];
+  gather_cell<D, TR, TM, R>(sr, sm, x, y, z, nx, ny, nz, stride, c, g);
+  collide<D, R>(g, k);
 #pragma unroll
   for (int i = 0; i < D + 1; ++i) {
     store_stream(dr + i * stride + c, g[i][0]);

@@ -8,6 +8,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 #include "lbm_device.hpp"
 #include "lbm_internal.hpp"
 
@@ -34,10 +36,9 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ u0,
   equilibrium<D, double>(W, 1.0 / rho, k, eq);
 #pragma unroll
   for (int i = 0; i < D + 1; ++i) {
-    store_f32(rest + i * stride + c, static_cast<float>(eq[i][0]));
+    store_real(rest + i * stride + c, eq[i][0]);
 #pragma unroll
-    for (int m = 0; m < 2 * D; ++m)
-      store_f32(move + (i * 2 * D + m) * stride + c, static_cast<float>(eq[i][1 + m]));
+    for (int m = 0; m < 2 * D; ++m) store_real(move + (i * 2 * D + m) * stride + c, eq[i][1 + m]);
   }
 }
 
@@ -48,7 +49,7 @@ template <int D, typename TR, typename TM>
 __global__ __launch_bounds__(256) void k_step(const TR* __restrict__ sr,
                                               const TM* __restrict__ sm, TR* __restrict__ dr,
                                               TM* __restrict__ dm, int nx, int ny, int nz,
-                                              int64_t stride, Coef k) {
+                                              int64_t stride, CoefT<typename ComputeOf<TM>::type> k) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
@@ -122,9 +123,9 @@ __device__ __forceinline__ void cell_sums(const TR* __restrict__ r, const TM* __
                                           int64_t c, int64_t stride, double (&s)[D + 1]) {
 #pragma unroll
   for (int i = 0; i < D + 1; ++i) {
-    double a = static_cast<double>(load_f32(r + i * stride + c));
+    double a = load_f64(r + i * stride + c);
 #pragma unroll
-    for (int v = 0; v < 2 * D; ++v) a += static_cast<double>(load_f32(m + (i * 2 * D + v) * stride + c));
+    for (int v = 0; v < 2 * D; ++v) a += load_f64(m + (i * 2 * D + v) * stride + c);
     s[i] = a;
   }
 }
@@ -341,7 +342,7 @@ struct Impl {
                          int by, hipStream_t s) {
     auto a = planes_of<TR, TM>(const_cast<void*>(src), g.rest_bytes);
     auto b = planes_of<TR, TM>(dst, g.rest_bytes);
-    const Coef k = make_coef<float>(r, D, DEV);
+    const auto k = make_coef<typename ComputeOf<TM>::type>(r, D, DEV);
     dim3 block(bx, by, 1);
     dim3 grid((g.nx + bx - 1) / bx, (g.ny + by - 1) / by, g.nz);
     hipLaunchKernelGGL((k_step<D, TR, TM>), grid, block, 0, s, a.rest, a.move, b.rest, b.move, g.nx,
@@ -354,9 +355,13 @@ struct Impl {
   // 147 GLUPS; 64x8/512: 77/127, 64x8/256: 76/119, 128x4: 78/131,
   // 256x2: 80/123, 32x8: 64/83).
   static constexpr int kT2X = 128, kT2Y = 8, kT2N = 512;
+  // two steps per launch in 2D, for the FP32/16-bit storages (the FP64
+  // reference mode would need 156 KB of LDS for this tile and runs one step
+  // per launch)
+  static constexpr bool kHasStep2 = D == 2 && !std::is_same<TM, double>::value;
 
   static hipError_t step2(const Geometry& g, const RunCoef& r, const void* src, void* dst, hipStream_t s) {
-    if constexpr (D != 2) {
+    if constexpr (!kHasStep2) {
       return hipErrorInvalidValue;
     } else {
       auto a = planes_of<TR, TM>(const_cast<void*>(src), g.rest_bytes);
@@ -402,7 +407,7 @@ struct Impl {
   }
 
   static const Ops* ops() {
-    static const Ops o = {&init, &step, D == 2 ? &step2 : nullptr, &moments, &diag, &diag_blocks};
+    static const Ops o = {&init, &step, kHasStep2 ? &step2 : nullptr, &moments, &diag, &diag_blocks};
     return &o;
   }
 };
@@ -418,6 +423,7 @@ const Ops* ops_for(int dim, int storage) {
       case LBM_BF16_DEV: return Impl<2, bf16, bf16, true>::ops();
       case LBM_F16_DEV_R32: return Impl<2, float, _Float16, true>::ops();
       case LBM_BF16_DEV_R32: return Impl<2, float, bf16, true>::ops();
+      case LBM_F64: return Impl<2, double, double, true>::ops();
     }
   } else if (dim == 3) {
     switch (storage) {
@@ -427,6 +433,7 @@ const Ops* ops_for(int dim, int storage) {
       case LBM_BF16_DEV: return Impl<3, bf16, bf16, true>::ops();
       case LBM_F16_DEV_R32: return Impl<3, float, _Float16, true>::ops();
       case LBM_BF16_DEV_R32: return Impl<3, float, bf16, true>::ops();
+      case LBM_F64: return Impl<3, double, double, true>::ops();
     }
   }
   return nullptr;
@@ -440,6 +447,7 @@ bool storage_elems(int storage, size_t* rest_elem, size_t* move_elem) {
     case LBM_BF16_DEV: *rest_elem = 2; *move_elem = 2; return true;
     case LBM_F16_DEV_R32:
     case LBM_BF16_DEV_R32: *rest_elem = 4; *move_elem = 2; return true;
+    case LBM_F64: *rest_elem = 8; *move_elem = 8; return true;
   }
   return false;
 }

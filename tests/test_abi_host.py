@@ -2,6 +2,7 @@
 headers declare, and validates parameters without touching a GPU."""
 
 import glob
+import math
 import os
 import re
 
@@ -83,12 +84,21 @@ def test_low_frequency_warning_flag():
 
 
 def test_workspace_bytes_cover_both_buffers():
-    for storage, per in (("f32", 4 * 15), ("f16_dev", 2 * 15), ("f16_dev_r32", 4 * 3 + 2 * 12)):
+    for storage, per in (("f32", 4 * 15), ("f16_dev", 2 * 15), ("f16_dev_r32", 4 * 3 + 2 * 12),
+                         ("f64", 8 * 15)):
         nb = lbm.lbm_workspace_bytes(_params(storage=storage, n=(4096, 4096)))
         assert nb >= 2 * per * 4096 * 4096
         assert nb < 2 * per * 4096 * 4096 * 1.01
     nb3 = lbm.lbm_workspace_bytes(_params(dim=3, n=(256, 256, 256)))
     assert nb3 >= 2 * 28 * 4 * 256 ** 3
+
+
+def test_batch_has_no_fp64_mode():
+    """The FP64 reference storage is single-run only: the batch sizes it as invalid."""
+    from paper_2607_24059_amd import batch
+    spec = batch.make_run((64, 64, 1), 2 * math.pi / 64, (2 * math.pi / 64) ** 2 / 8, 1e-3)
+    assert batch.lbm_batch_workspace_bytes(2, lbm.STORAGE["f64"], [spec]) == 0
+    assert batch.lbm_batch_workspace_bytes(2, lbm.STORAGE["f32"], [spec]) > 0
 
 
 def test_strerror():

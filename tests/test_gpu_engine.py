@@ -82,6 +82,35 @@ def test_raw_fp32_storage_runs_close():
     assert err <= 5e-5
 
 
+FP64_TOL = 1e-11
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_fp64_storage_matches_oracle_to_rounding(dim):
+    """LBM_F64 (deviations in FP64, FP64 arithmetic) agrees with the FP64 oracle
+    to accumulated FP64 rounding after 1000 steps (2D) / 200 steps (3D)."""
+    if dim == 2:
+        n, steps = 96, 1000
+        p = scheme.params_for_grid(2, n, 1e-3)
+        u0 = inputs.random_field_2d(n, 4, umax=0.05 / p.dx)
+    else:
+        n, steps = 24, 200
+        p = scheme.params_for_grid(3, n, 1e-2)
+        u0 = inputs.abc_flow(n)
+    print(f"[gpu parity] f64 dim={dim} n={n} steps={steps}", flush=True)
+    eng = _engine(p, u0, storage="f64")
+    eng.step(steps)
+    rho, q = eng.moments()
+    with pytest.raises(lbm.LbmError):
+        eng.set_fusion(2)   # one step per launch in the FP64 mode
+    eng.close()
+    r_ref, q_ref, _ = scheme.simulate(u0, p, steps)
+    err = _rel_l2(q / rho, q_ref / r_ref)
+    print(f"[gpu parity] f64 rel-L2(u) = {err:.3e}", flush=True)
+    assert err <= FP64_TOL, err
+    assert np.max(np.abs(rho - r_ref)) <= 1e-13
+
+
 @pytest.mark.parametrize("shape", [(8, 8), (75, 75), (40, 96), (3, 130), (129, 1)])
 def test_random_field_2d_ragged(shape):
     """Non power-of-two and ragged grids: wrap-around and partial blocks."""

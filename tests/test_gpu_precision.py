@@ -25,7 +25,7 @@ from paper_2607_24059_amd import lbm  # noqa: E402
 
 STEPS = 1000
 BARS = {"f32": 1e-5, "f16_dev_r32": 2e-3, "bf16_dev_r32": 2e-3, "f32_raw": None,
-        "f16_dev": None, "bf16_dev": None}
+        "f16_dev": None, "bf16_dev": None, "f64": 1e-11}
 RESULTS = {}
 
 
