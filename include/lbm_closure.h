@@ -57,6 +57,21 @@ lbm_status lbm_set_equilibrium_device(lbm_ctx* ctx, const float* moments);
 lbm_status lbm_closure_apply(lbm_ctx* ctx, const float* moments, const float* y, float s_drho, float s_dq,
                              float guard_factor);
 
+/* One whole correction of a 2D context, in five launches on its stream:
+ *   moments (written to `moments`, [3][cells] FP32, as lbm_moments_device),
+ *   the network output y = lbm_net_infer(moments, rho_ref of ctx, s_rho, s_u,
+ *   packed, bias) ([3][cells] FP32),
+ *   the guard and the update of lbm_closure_apply(ctx, moments, y, s_drho,
+ *   s_dq, guard_factor).
+ * The same result as those calls made one by one, except that the grid means
+ * of y are summed per 16 x 16 tile first (a different FP64 summation order).
+ * nx and ny must be multiples of 16; packed and bias are host arrays of the
+ * four layers' device pointers (lbm_cnn.h).  Nothing in it needs the host,
+ * so a caller can capture it in a graph. */
+lbm_status lbm_closure_correct(lbm_ctx* ctx, const void* const* packed, const float* const* bias,
+                               float s_rho, float s_u, float s_drho, float s_dq, float guard_factor,
+                               float* moments, float* y);
+
 typedef struct lbm_closure_report {
   int64_t n_accepted; /* corrections applied since lbm_init */
   int64_t n_rejected; /* corrections refused by the guard since lbm_init */

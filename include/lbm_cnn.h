@@ -43,6 +43,24 @@ lbm_status lbm_conv_forward(const float* x, int32_t batch, int32_t cin, int32_t 
                             const void* packed, int32_t cout, const float* bias, const float* mask,
                             uint32_t flags, float* y, void* stream);
 
+/* Inference of the whole correction network in one launch, for 2D moment
+ * planes m[3][h][w] (rho, q_x, q_y; FP32):
+ *   x = ((rho - rho_ref)/s_rho, (q_x/rho)/s_u, (q_y/rho)/s_u)   (as lbm_closure_features)
+ *   y = L4(relu(L3(relu(L2(relu(L1(x)))))))   channels 3 -> 32 -> 32 -> 32 -> 3
+ * where L_l is the 3x3 periodic convolution of lbm_conv_forward with the
+ * forward-packed operand packed[l] (lbm_conv_pack, transpose = 0) and the
+ * bias bias[l]; packed and bias are host arrays of 4 device pointers.  The
+ * result equals the four lbm_conv_forward calls bit for bit; the activations
+ * never leave the chip.  y: [3][h][w] FP32.  partials receives, for each
+ * 16 x 16 tile t (row-major over the tiles), the FP64 sums of the tile's
+ * three output channels in partials[4t .. 4t+2] (partials[4t+3] = 0);
+ * lbm_net_partials_bytes(h, w) bytes.  h and w: positive multiples of 16;
+ * s_rho, s_u > 0.  Returns LBM_EINVAL otherwise. */
+size_t lbm_net_partials_bytes(int32_t h, int32_t w);
+lbm_status lbm_net_infer(const float* moments, int32_t h, int32_t w, double rho_ref, float s_rho,
+                         float s_u, const void* const* packed, const float* const* bias, float* y,
+                         double* partials, void* stream);
+
 /* Scratch bytes for lbm_conv_wgrad. */
 size_t lbm_conv_wgrad_scratch_bytes(int32_t batch, int32_t cin, int32_t cout, int32_t h, int32_t w);
 

@@ -45,6 +45,8 @@ SIGNATURES = {
                                      C.c_void_p]),
     "lbm_set_equilibrium_device": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lbm_closure_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_float, C.c_float, C.c_float]),
+    "lbm_closure_correct": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_float,
+                                      C.c_float, C.c_float, C.c_float, C.c_float, C.c_void_p, C.c_void_p]),
     "lbm_closure_report_get": (C.c_int, [C.c_void_p, C.POINTER(lbm_closure_report)]),
 }
 
@@ -89,6 +91,12 @@ def lbm_set_equilibrium_device(ctx, moments):
 def lbm_closure_apply(ctx, moments, y, s_drho, s_dq, guard_factor):
     _ok(xlib().lbm_closure_apply(C.c_void_p(ctx), _p(moments), _p(y), s_drho, s_dq, guard_factor),
         "lbm_closure_apply")
+
+
+def lbm_closure_correct(ctx, net, s_rho, s_u, s_drho, s_dq, guard_factor, moments, y):
+    packed, bias = net.layer_pointers()
+    _ok(xlib().lbm_closure_correct(C.c_void_p(ctx), packed, bias, s_rho, s_u, s_drho, s_dq, guard_factor,
+                                   _p(moments), _p(y)), "lbm_closure_correct")
 
 
 def lbm_closure_report_get(ctx):
@@ -317,7 +325,7 @@ class CorrectedRun:
     replayed.  The context's host-side step counter does not advance during
     replays."""
 
-    def __init__(self, cfg: Config, net, scales, m0, storage="f32", use_graph=True):
+    def __init__(self, cfg: Config, net, scales, m0, storage="f32", use_graph=True, fused=True):
         import torch
         self.torch = torch
         self.cfg, self.net, self.scales = cfg, net, scales
@@ -333,11 +341,17 @@ class CorrectedRun:
             lbm_set_equilibrium_device(self.eng.ctx, m0)
             self.m = torch.empty((3, nc, nc), dtype=torch.float32, device="cuda")
             self.x = torch.empty((1, 3, nc, nc), dtype=torch.float32, device="cuda")
+            self.y = torch.empty((3, nc, nc), dtype=torch.float32, device="cuda")
+            self.fused = fused
             self.net.forward(self.x.zero_())  # allocates the activation buffers outside any capture
 
     def _window(self):
         sc = self.scales
         self.eng.step(self.cfg.every)
+        if self.fused:
+            lbm_closure_correct(self.eng.ctx, self.net, sc["s_rho"], sc["s_u"], sc["s_drho"], sc["s_dq"],
+                                self.cfg.guard, self.m, self.y)
+            return
         self.eng.moments_device(self.m)
         lbm_closure_features(self.m, 2, self.cells, 1.0, sc["s_rho"], sc["s_u"], self.x, self.stream)
         y = self.net.forward(self.x)

@@ -31,6 +31,10 @@ SIGNATURES = {
     "lbm_adam": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_float, C.c_float,
                            C.c_float, C.c_float, C.c_int32, C.c_void_p]),
     "lbm_channel_rms": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lbm_net_partials_bytes": (C.c_size_t, [C.c_int32, C.c_int32]),
+    "lbm_net_infer": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_float, C.c_float,
+                                C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p,
+                                C.c_void_p]),
 }
 
 _bound = False
@@ -84,6 +88,16 @@ def lbm_reduce_scratch_bytes(n):
 
 def lbm_mse(out, target, n, grad, loss_dev, scratch, stream):
     _ok(clib().lbm_mse(_p(out), _p(target), n, _p(grad), _p(loss_dev), _p(scratch), _s(stream)), "lbm_mse")
+
+
+def lbm_net_partials_bytes(h, w):
+    return int(clib().lbm_net_partials_bytes(h, w))
+
+
+def lbm_net_infer(moments, h, w, rho_ref, s_rho, s_u, net, y, partials, stream):
+    packed, bias = net.layer_pointers()
+    _ok(clib().lbm_net_infer(_p(moments), h, w, rho_ref, s_rho, s_u, packed, bias, _p(y), _p(partials),
+                             _s(stream)), "lbm_net_infer")
 
 
 def lbm_adam(p, g, m, v, n, lr, b1, b2, eps, t, stream):
@@ -148,6 +162,12 @@ class Net:
             w, _ = self.views(self.p)[li]
             lbm_conv_pack(w, cin, cout, 0, self.packed[li], self.stream)
             lbm_conv_pack(w, cin, cout, 1, self.packed_t[li], self.stream)
+
+    def layer_pointers(self):
+        """Host arrays of the four layers' forward-packed operands and biases (device pointers)."""
+        packed = (C.c_void_p * 4)(*[t.data_ptr() for t in self.packed])
+        bias = (C.c_void_p * 4)(*[b.data_ptr() for _, b in self.views(self.p)])
+        return packed, bias
 
     def host_params(self):
         flat = self.p.double().cpu().numpy()

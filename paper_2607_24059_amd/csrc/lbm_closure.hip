@@ -100,8 +100,10 @@ __global__ __launch_bounds__(256) void k_set_eq(const float* __restrict__ m, int
 // --------------------------------------------------------------------------
 // guarded correction (2D)
 // --------------------------------------------------------------------------
-// Two-stage deterministic reductions: per-block partials in the context's
-// diagnostics scratch, then one block sums them in a fixed order.
+// Deterministic reductions in two stages: per-block (or per-tile) FP64
+// partials of 4 doubles in the context's diagnostics scratch, summed in a
+// fixed order by every block of the next launch, so no launch is spent on
+// the final sums alone.
 constexpr int kRedSlots = 4;
 
 // per-block sums of the three output channels
@@ -117,32 +119,44 @@ __global__ __launch_bounds__(kThreads) void k_cl_means(const float* __restrict__
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_cl_means_final(const double* __restrict__ part, int nb,
-                                                             int64_t cells, float s_drho, float s_dq,
-                                                             double* __restrict__ slots) {
+// ---- the guard in two launches -------------------------------------------
+// Sums of the first three entries of `count` 4-double partials, in a fixed
+// order; every thread of the block receives them.
+__device__ void reduce_partials3(const double* __restrict__ part, int64_t count, double (&out)[3]) {
+  __shared__ double bc[3];
   for (int ch = 0; ch < 3; ++ch) {
     double acc = 0.0;
-    for (int b = threadIdx.x; b < nb; b += kThreads) acc += part[b * kRedSlots + ch];
+    for (int64_t i = threadIdx.x; i < count; i += kThreads) acc += part[i * kRedSlots + ch];
     const double s = block_sum(acc);
-    if (threadIdx.x == 0) slots[kSlotMean + ch] = s / static_cast<double>(cells) * (ch == 0 ? s_drho : s_dq);
+    if (threadIdx.x == 0) bc[ch] = s;
   }
+  __syncthreads();
+  for (int ch = 0; ch < 3; ++ch) out[ch] = bc[ch];
+  __syncthreads();
 }
 
-// per-block divergence sums of u and u' and non-finite counts
-__global__ __launch_bounds__(kThreads) void k_cl_guard(const float* __restrict__ m, const float* __restrict__ y,
-                                                       int nx, int ny, double dx, float s_drho, float s_dq,
-                                                       const double* __restrict__ slots,
-                                                       double* __restrict__ part) {
+// Every block: the grid means of the output channels from their partial sums,
+// then the divergence sums of u and u' over its cells (grid-stride) into
+// div_part.  Block 0 records the means in the slots.
+__global__ __launch_bounds__(kThreads) void k_cl_guard2(const float* __restrict__ m, const float* __restrict__ y,
+                                                        int nx, int ny, double dx, float s_drho, float s_dq,
+                                                        const double* __restrict__ mean_part, int64_t n_mean_part,
+                                                        double* __restrict__ slots, double* __restrict__ div_part) {
   const int64_t cells = static_cast<int64_t>(nx) * ny;
-  const double m0 = slots[kSlotMean], m1 = slots[kSlotMean + 1], m2 = slots[kSlotMean + 2];
+  double sums[3];
+  reduce_partials3(mean_part, n_mean_part, sums);
+  double mean[3];
+  for (int ch = 0; ch < 3; ++ch) mean[ch] = sums[ch] / static_cast<double>(cells) * (ch == 0 ? s_drho : s_dq);
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    for (int ch = 0; ch < 3; ++ch) slots[kSlotMean + ch] = mean[ch];
   auto uplain = [&](int x, int yy, int j) {
     const int64_t c = static_cast<int64_t>(yy) * nx + x;
     return static_cast<double>(m[(1 + j) * cells + c]) / static_cast<double>(m[c]);
   };
   auto ucorr = [&](int x, int yy, int j) {
     const int64_t c = static_cast<int64_t>(yy) * nx + x;
-    const double rho = static_cast<double>(m[c]) + (static_cast<double>(y[c]) * s_drho - m0);
-    const double dq = static_cast<double>(y[(1 + j) * cells + c]) * s_dq - (j == 0 ? m1 : m2);
+    const double rho = static_cast<double>(m[c]) + (static_cast<double>(y[c]) * s_drho - mean[0]);
+    const double dq = static_cast<double>(y[(1 + j) * cells + c]) * s_dq - mean[1 + j];
     return (static_cast<double>(m[(1 + j) * cells + c]) + dq) / rho;
   };
   double a0 = 0.0, a1 = 0.0, bad = 0.0;
@@ -161,41 +175,34 @@ __global__ __launch_bounds__(kThreads) void k_cl_guard(const float* __restrict__
   const double s1 = block_sum(a1);
   const double sb = block_sum(bad);
   if (threadIdx.x == 0) {
-    part[blockIdx.x * kRedSlots + 0] = s0;
-    part[blockIdx.x * kRedSlots + 1] = s1;
-    part[blockIdx.x * kRedSlots + 2] = sb;
+    div_part[blockIdx.x * kRedSlots + 0] = s0;
+    div_part[blockIdx.x * kRedSlots + 1] = s1;
+    div_part[blockIdx.x * kRedSlots + 2] = sb;
+    div_part[blockIdx.x * kRedSlots + 3] = 0.0;
   }
 }
 
-// the decision, one block
-__global__ __launch_bounds__(kThreads) void k_cl_decide(const double* __restrict__ part, int nb, double dx,
-                                                        float factor, double* __restrict__ slots) {
-  double a0 = 0.0, a1 = 0.0, ab = 0.0;
-  for (int b = threadIdx.x; b < nb; b += kThreads) {
-    a0 += part[b * kRedSlots + 0];
-    a1 += part[b * kRedSlots + 1];
-    ab += part[b * kRedSlots + 2];
-  }
-  const double s0 = block_sum(a0);
-  const double s1 = block_sum(a1);
-  const double sb = block_sum(ab);
-  if (threadIdx.x == 0) {
-    const double div0 = sqrt(dx * dx * s0), div1 = sqrt(dx * dx * s1);
-    const bool ok = sb == 0.0 && isfinite(div1) && div1 <= static_cast<double>(factor) * div0;
+// Every block takes the decision from the divergence partials (the same in
+// all blocks), block 0 records it, and accepted corrections update the cells
+// (one thread per cell): g += f^eq(W + dW) - f^eq(W).
+template <int D, typename TR, typename TM>
+__global__ __launch_bounds__(256) void k_cl_apply2(const float* __restrict__ y, int64_t cells, int64_t stride,
+                                                   double dx, double ref, TR* __restrict__ rest,
+                                                   TM* __restrict__ move, CoefT<double> k, float s_drho,
+                                                   float s_dq, double* __restrict__ slots,
+                                                   const double* __restrict__ div_part, int64_t n_div_part,
+                                                   float factor) {
+  double sums[3];
+  reduce_partials3(div_part, n_div_part, sums);
+  const double div0 = sqrt(dx * dx * sums[0]), div1 = sqrt(dx * dx * sums[1]);
+  const bool ok = sums[2] == 0.0 && isfinite(div1) && div1 <= static_cast<double>(factor) * div0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     slots[kSlotDiv0] = div0;
     slots[kSlotDiv1] = div1;
     slots[kSlotAccept] = ok ? 1.0 : 0.0;
     slots[ok ? kSlotNacc : kSlotNrej] += 1.0;
   }
-}
-
-// g += f^eq(W + dW) - f^eq(W) in every cell, if the guard accepted
-template <int D, typename TR, typename TM>
-__global__ __launch_bounds__(256) void k_cl_apply(const float* __restrict__ y, int64_t cells, int64_t stride,
-                                                  double dx, double ref, TR* __restrict__ rest,
-                                                  TM* __restrict__ move, CoefT<double> k, float s_drho,
-                                                  float s_dq, const double* __restrict__ slots) {
-  if (slots[kSlotAccept] == 0.0) return;
+  if (!ok) return;
   const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (c >= cells) return;
   double W[D + 1];
@@ -236,12 +243,13 @@ struct ClosureImpl {
                        0, c->stream, m, c->g.cells, c->g.stride, c->coef.dx, p.rest, p.move, k);
     return hipGetLastError();
   }
-  static hipError_t apply(lbm_ctx* c, const float* y, float s_drho, float s_dq, double* slots) {
+  static hipError_t apply(lbm_ctx* c, const float* y, float s_drho, float s_dq, double* slots,
+                          const double* div_part, int64_t n_div_part, float factor) {
     auto p = planes_of<TR, TM>(c->cur, c->g.rest_bytes);
     const CoefT<double> k = make_coef<double>(c->coef, D, false);
-    hipLaunchKernelGGL((k_cl_apply<D, TR, TM>), dim3(static_cast<unsigned>((c->g.cells + 255) / 256)), dim3(256),
-                       0, c->stream, y, c->g.cells, c->g.stride, c->coef.dx, DEV ? c->coef.ref : 0.0, p.rest,
-                       p.move, k, s_drho, s_dq, slots);
+    hipLaunchKernelGGL((k_cl_apply2<D, TR, TM>), dim3(static_cast<unsigned>((c->g.cells + 255) / 256)),
+                       dim3(256), 0, c->stream, y, c->g.cells, c->g.stride, c->coef.dx, DEV ? c->coef.ref : 0.0,
+                       p.rest, p.move, k, s_drho, s_dq, slots, div_part, n_div_part, factor);
     return hipGetLastError();
   }
 };
@@ -260,17 +268,40 @@ hipError_t dispatch_set_eq(lbm_ctx* c, const float* m) {
   return hipErrorInvalidValue;
 }
 
-hipError_t dispatch_apply(lbm_ctx* c, const float* y, float s_drho, float s_dq, double* slots) {
+hipError_t dispatch_apply(lbm_ctx* c, const float* y, float s_drho, float s_dq, double* slots,
+                          const double* div_part, int64_t n, float factor) {
   switch (c->p.storage) {
-    case LBM_F32: return ClosureImpl<2, float, float, true>::apply(c, y, s_drho, s_dq, slots);
-    case LBM_F32_RAW: return ClosureImpl<2, float, float, false>::apply(c, y, s_drho, s_dq, slots);
-    case LBM_F16_DEV: return ClosureImpl<2, _Float16, _Float16, true>::apply(c, y, s_drho, s_dq, slots);
-    case LBM_BF16_DEV: return ClosureImpl<2, bf16, bf16, true>::apply(c, y, s_drho, s_dq, slots);
-    case LBM_F16_DEV_R32: return ClosureImpl<2, float, _Float16, true>::apply(c, y, s_drho, s_dq, slots);
-    case LBM_BF16_DEV_R32: return ClosureImpl<2, float, bf16, true>::apply(c, y, s_drho, s_dq, slots);
-    case LBM_F64: return ClosureImpl<2, double, double, true>::apply(c, y, s_drho, s_dq, slots);
+    case LBM_F32: return ClosureImpl<2, float, float, true>::apply(c, y, s_drho, s_dq, slots, div_part, n, factor);
+    case LBM_F32_RAW: return ClosureImpl<2, float, float, false>::apply(c, y, s_drho, s_dq, slots, div_part, n, factor);
+    case LBM_F16_DEV: return ClosureImpl<2, _Float16, _Float16, true>::apply(c, y, s_drho, s_dq, slots, div_part, n, factor);
+    case LBM_BF16_DEV: return ClosureImpl<2, bf16, bf16, true>::apply(c, y, s_drho, s_dq, slots, div_part, n, factor);
+    case LBM_F16_DEV_R32: return ClosureImpl<2, float, _Float16, true>::apply(c, y, s_drho, s_dq, slots, div_part, n, factor);
+    case LBM_BF16_DEV_R32: return ClosureImpl<2, float, bf16, true>::apply(c, y, s_drho, s_dq, slots, div_part, n, factor);
+    case LBM_F64: return ClosureImpl<2, double, double, true>::apply(c, y, s_drho, s_dq, slots, div_part, n, factor);
   }
   return hipErrorInvalidValue;
+}
+
+// Guard blocks: one per 2048 cells, at most 256 (each block reduces every
+// partial of the previous stage, so their number is kept small).
+int guard_blocks(int64_t cells) {
+  int64_t nb = cells / 2048;
+  if (nb > 256) nb = 256;
+  if (nb < 1) nb = 1;
+  return static_cast<int>(nb);
+}
+
+// The guard and the guarded update, from per-tile (or per-block) FP64 sums of
+// the network output in mean_part; the divergence partials go after them in
+// the context's scratch.
+hipError_t guard_and_apply(lbm_ctx* c, const float* moments, const float* y, float s_drho, float s_dq, float factor,
+                           const double* mean_part, int64_t n_mean_part, double* div_part) {
+  const int nbg = guard_blocks(c->g.cells);
+  hipLaunchKernelGGL(k_cl_guard2, dim3(nbg), dim3(kThreads), 0, c->stream, moments, y, c->g.nx, c->g.ny, c->p.dx,
+                     s_drho, s_dq, mean_part, n_mean_part, c->closure_slots, div_part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return dispatch_apply(c, y, s_drho, s_dq, c->closure_slots, div_part, nbg, factor);
 }
 
 lbm_status dev(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EDEVICE; }
@@ -317,31 +348,33 @@ lbm_status lbm_set_equilibrium_device(lbm_ctx* c, const float* moments) {
 lbm_status lbm_closure_apply(lbm_ctx* c, const float* moments, const float* y, float s_drho, float s_dq,
                              float guard_factor) {
   if (!c || !moments || !y || c->p.dim != 2 || !(guard_factor > 0)) return LBM_EINVAL;
-  double* slots = c->closure_slots;
-  double* part = c->partials;  // diagnostics scratch: diag_blocks * 16 doubles
-  int64_t nb = c->g.cells / 2048;
-  const int64_t cap = c->diag_blocks * 16 / kRedSlots;
-  if (nb > 256) nb = 256;
-  if (nb > cap) nb = cap;
-  if (nb < 1) nb = 1;
-  const int nbi = static_cast<int>(nb);
-  hipLaunchKernelGGL(k_cl_means, dim3(nbi), dim3(kThreads), 0, c->stream, y, c->g.cells, part);
+  // diagnostics scratch (diag_blocks * 16 doubles): mean partials, then divergence partials
+  double* part = c->partials;
+  const int nbm = guard_blocks(c->g.cells);
+  if (static_cast<int64_t>(2 * nbm) * kRedSlots > c->diag_blocks * 16) return LBM_EINVAL;
+  hipLaunchKernelGGL(k_cl_means, dim3(nbm), dim3(kThreads), 0, c->stream, y, c->g.cells, part);
   hipError_t e = hipGetLastError();
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_cl_means_final, dim3(1), dim3(kThreads), 0, c->stream, part, nbi, c->g.cells, s_drho,
-                       s_dq, slots);
-    e = hipGetLastError();
-  }
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_cl_guard, dim3(nbi), dim3(kThreads), 0, c->stream, moments, y, c->g.nx, c->g.ny, c->p.dx,
-                       s_drho, s_dq, slots, part);
-    e = hipGetLastError();
-  }
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_cl_decide, dim3(1), dim3(kThreads), 0, c->stream, part, nbi, c->p.dx, guard_factor, slots);
-    e = hipGetLastError();
-  }
-  if (e == hipSuccess) e = dispatch_apply(c, y, s_drho, s_dq, slots);
+  if (e == hipSuccess)
+    e = guard_and_apply(c, moments, y, s_drho, s_dq, guard_factor, part, nbm, part + nbm * kRedSlots);
+  return dev(e);
+}
+
+lbm_status lbm_closure_correct(lbm_ctx* c, const void* const* packed, const float* const* bias, float s_rho,
+                               float s_u, float s_drho, float s_dq, float guard_factor, float* moments, float* y) {
+  if (!c || !packed || !bias || !moments || !y || c->p.dim != 2 || !(guard_factor > 0) || !(s_rho > 0) ||
+      !(s_u > 0))
+    return LBM_EINVAL;
+  for (int l = 0; l < 4; ++l)
+    if (!packed[l] || !bias[l]) return LBM_EINVAL;
+  const int64_t tiles = net_infer_tiles(c->g.ny, c->g.nx);
+  const int nbg = guard_blocks(c->g.cells);
+  if (tiles == 0 || (tiles + nbg) * kRedSlots > c->diag_blocks * 16) return LBM_EINVAL;
+  double* part = c->partials;
+  hipError_t e = c->ops->moments(c->g, c->coef, c->cur, nullptr, moments, c->stream);
+  if (e == hipSuccess)
+    e = net_infer_launch(moments, c->g.ny, c->g.nx, c->p.rho_ref, s_rho, s_u, packed, bias, y, part, c->stream);
+  if (e == hipSuccess)
+    e = guard_and_apply(c, moments, y, s_drho, s_dq, guard_factor, part, tiles, part + tiles * kRedSlots);
   return dev(e);
 }
 

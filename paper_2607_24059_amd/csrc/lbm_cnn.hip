@@ -19,12 +19,18 @@
 #include "lbm.h"
 #include "lbm_cnn.h"
 #include "lbm_device.hpp"
+#include "lbm_internal.hpp"
 
 namespace lbm {
 namespace {
 
 typedef short s4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+
+struct NetWeights {
+  const uint16_t* packed[4];  // forward-packed BF16 operands of the four layers
+  const float* bias[4];
+};
 
 constexpr int kSeg = 64;       // pixels per block row segment
 constexpr int kThreads = 256;  // 4 waves, 16 pixels each
@@ -319,6 +325,133 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
 }
 
 // ----------------------------------------------------------------------------
+// fused inference of the correction network (3 -> 32 -> 32 -> 32 -> 3)
+//
+// One block computes a 16 x 16 output tile through all four layers.  The
+// layers shrink the region by one pixel per side, so the block loads a
+// 24 x 24 input region (periodic wrap) and keeps every intermediate
+// activation (22^2, 20^2, 18^2 pixels x 32 channels, channel-last BF16) in
+// LDS.  The recomputed borders cost (22^2 + 20^2 + 18^2) / (3 * 16^2) = 1.57x
+// the MFMA work of the three inner layers, in exchange for no activation
+// traffic to HBM and one launch instead of five.  Each wave keeps the B
+// fragments (weights) of the current layer in registers and walks 16-pixel
+// M-tiles of the layer's output region.  The k order, the MFMA sequence, the
+// bias, the ReLU and the BF16 rounding of each activation are those of
+// k_conv_fwd, so the output equals the layer-by-layer forward bit for bit.
+// ----------------------------------------------------------------------------
+constexpr int kInfT = 16;        // output tile edge
+constexpr int kInfS0 = kInfT + 8;  // input region edge (halo 4)
+constexpr int kInfCh = 32;       // hidden channels
+constexpr int kInfStride = 40;   // LDS elements per pixel of a hidden activation (32 + 8 pad)
+
+// One layer on the block's LDS regions: input region SIN x SIN (pixel stride
+// IN_STRIDE elements), output region SOUT = SIN - 2.
+template <int CINP, int COUTP, int SIN, int IN_STRIDE, bool LAST>
+__device__ __forceinline__ void infer_layer(const uint16_t* in, uint16_t* out, const uint16_t* __restrict__ packed,
+                                            const float* __restrict__ bias, float* ys) {
+  constexpr int SOUT = SIN - 2;
+  constexpr int KP = k_pad(CINP);
+  constexpr int KS = KP / 16;
+  constexpr int NT = COUTP / 16;
+  constexpr int NPIX = SOUT * SOUT;
+  constexpr int MT = (NPIX + 15) / 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+  s4 bf[NT][KS];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+      bf[nt][ks] = *reinterpret_cast<const s4*>(packed + (nt * 16 + li) * KP + ks * 16 + 4 * lq);
+  for (int mt = wave; mt < MT; mt += kThreads / 64) {
+    int o = mt * 16 + li;
+    if (o >= NPIX) o = NPIX - 1;  // padding rows of the last M-tile: read a valid pixel, result dropped
+    const int oy = o / SOUT, ox = o % SOUT;
+    f4 acc[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[nt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k0 = ks * 16 + 4 * lq;
+      const int tap = k0 / CINP, ci0 = k0 % CINP;
+      s4 a = s4{0, 0, 0, 0};
+      if (tap < 9) {
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        a = *reinterpret_cast<const s4*>(in + ((oy + 1 + dy) * SIN + (ox + 1 + dx)) * IN_STRIDE + ci0);
+      }
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bf[nt][ks], acc[nt], 0, 0, 0);
+    }
+    // lane holds output channel nt*16 + li of pixels mt*16 + 4*lq + r
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int co = nt * 16 + li;
+      if (LAST && co >= 3) continue;
+      const float bv = bias[co];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int op = mt * 16 + 4 * lq + r;
+        if (op >= NPIX) continue;
+        float v = acc[nt][r] + bv;
+        if (LAST) {
+          ys[co * NPIX + op] = v;
+        } else {
+          v = fmaxf(v, 0.0f);
+          out[op * kInfStride + co] = bf16_bits(v);
+        }
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_net_infer(const float* __restrict__ m, int h, int w, double rho_ref,
+                                                        float s_rho, float s_u, NetWeights nw,
+                                                        float* __restrict__ y, double* __restrict__ part) {
+  __shared__ __attribute__((aligned(16))) uint16_t a0[kInfS0 * kInfS0 * 4];
+  __shared__ __attribute__((aligned(16))) uint16_t a1[(kInfS0 - 2) * (kInfS0 - 2) * kInfStride];
+  __shared__ __attribute__((aligned(16))) uint16_t a2[(kInfS0 - 4) * (kInfS0 - 4) * kInfStride];
+  __shared__ float ys[3 * kInfT * kInfT];
+  const int tx0 = blockIdx.x * kInfT, ty0 = blockIdx.y * kInfT;
+  const int64_t cells = static_cast<int64_t>(h) * w;
+  // features of the input region, as lbm_closure_features computes them
+  for (int i = threadIdx.x; i < kInfS0 * kInfS0; i += kThreads) {
+    const int ry = i / kInfS0, rx = i % kInfS0;
+    const int gy = ((ty0 - 4 + ry) % h + h) % h, gx = ((tx0 - 4 + rx) % w + w) % w;
+    const int64_t c = static_cast<int64_t>(gy) * w + gx;
+    const float rho = m[c];
+    a0[i * 4 + 0] = bf16_bits(static_cast<float>((rho - rho_ref) / s_rho));
+    a0[i * 4 + 1] = bf16_bits((m[cells + c] / rho) / s_u);
+    a0[i * 4 + 2] = bf16_bits((m[2 * cells + c] / rho) / s_u);
+    a0[i * 4 + 3] = 0;
+  }
+  __syncthreads();
+  infer_layer<4, kInfCh, kInfS0, 4, false>(a0, a1, nw.packed[0], nw.bias[0], nullptr);
+  __syncthreads();
+  infer_layer<kInfCh, kInfCh, kInfS0 - 2, kInfStride, false>(a1, a2, nw.packed[1], nw.bias[1], nullptr);
+  __syncthreads();
+  infer_layer<kInfCh, kInfCh, kInfS0 - 4, kInfStride, false>(a2, a1, nw.packed[2], nw.bias[2], nullptr);
+  __syncthreads();
+  infer_layer<kInfCh, 16, kInfS0 - 6, kInfStride, true>(a1, nullptr, nw.packed[3], nw.bias[3], ys);
+  __syncthreads();
+  // output tile and its per-channel FP64 sums (fixed order)
+  const int t = threadIdx.x;  // one pixel of the 16 x 16 tile per thread
+  const int64_t c = static_cast<int64_t>(ty0 + t / kInfT) * w + tx0 + t % kInfT;
+  double sums[3];
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    const float v = ys[ch * kInfT * kInfT + t];
+    y[ch * cells + c] = v;
+    sums[ch] = block_sum(static_cast<double>(v));
+  }
+  if (t == 0) {
+    const int64_t tile = static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) part[tile * 4 + ch] = sums[ch];
+    part[tile * 4 + 3] = 0.0;
+  }
+}
+
+// ----------------------------------------------------------------------------
 // dispatch on the padded channel counts
 // ----------------------------------------------------------------------------
 template <int CINP, int COUTP>
@@ -392,6 +525,28 @@ bool shape_ok(int cin, int cout) {
 
 lbm_status dev(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EDEVICE; }
 
+}  // namespace
+
+hipError_t net_infer_launch(const float* m, int h, int w, double rho_ref, float s_rho, float s_u,
+                            const void* const* packed, const float* const* bias, float* y, double* part,
+                            hipStream_t s) {
+  NetWeights nw;
+  for (int l = 0; l < 4; ++l) {
+    nw.packed[l] = static_cast<const uint16_t*>(packed[l]);
+    nw.bias[l] = bias[l];
+  }
+  hipLaunchKernelGGL(k_net_infer, dim3(w / kInfT, h / kInfT), dim3(kThreads), 0, s, m, h, w, rho_ref, s_rho, s_u,
+                     nw, y, part);
+  return hipGetLastError();
+}
+
+int64_t net_infer_tiles(int h, int w) {
+  if (h < kInfT || w < kInfT || h % kInfT || w % kInfT) return 0;
+  return static_cast<int64_t>(h / kInfT) * (w / kInfT);
+}
+
+namespace {
+
 int red_blocks(int64_t n) {
   int64_t b = (n + kThreads - 1) / kThreads;
   if (b > kRedBlocks) b = kRedBlocks;
@@ -430,6 +585,22 @@ lbm_status lbm_conv_forward(const float* x, int32_t batch, int32_t cin, int32_t 
   if (!x || !packed || !y || batch < 1 || h < 1 || w < kSeg || w % kSeg != 0 || !shape_ok(cin, cout))
     return LBM_EINVAL;
   return dev(conv_forward(x, batch, cin, h, w, packed, cout, bias, mask, flags, y, static_cast<hipStream_t>(stream)));
+}
+
+size_t lbm_net_partials_bytes(int32_t h, int32_t w) {
+  return static_cast<size_t>(net_infer_tiles(h, w)) * 4 * sizeof(double);
+}
+
+lbm_status lbm_net_infer(const float* moments, int32_t h, int32_t w, double rho_ref, float s_rho, float s_u,
+                         const void* const* packed, const float* const* bias, float* y, double* partials,
+                         void* stream) {
+  if (!moments || !packed || !bias || !y || !partials || net_infer_tiles(h, w) == 0 || !(s_rho > 0) ||
+      !(s_u > 0))
+    return LBM_EINVAL;
+  for (int l = 0; l < 4; ++l)
+    if (!packed[l] || !bias[l]) return LBM_EINVAL;
+  return dev(net_infer_launch(moments, h, w, rho_ref, s_rho, s_u, packed, bias, y, partials,
+                              static_cast<hipStream_t>(stream)));
 }
 
 size_t lbm_conv_wgrad_scratch_bytes(int32_t batch, int32_t cin, int32_t cout, int32_t h, int32_t w) {

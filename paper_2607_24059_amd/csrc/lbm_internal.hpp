@@ -57,6 +57,14 @@ bool storage_is_deviation(int storage);
 
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 
+// Fused inference of the correction network (lbm_cnn.hip): y[3][h][w] and
+// per-16x16-tile FP64 sums of y (4 doubles per tile) in part.
+hipError_t net_infer_launch(const float* m, int h, int w, double rho_ref, float s_rho, float s_u,
+                            const void* const* packed, const float* const* bias, float* y, double* part,
+                            hipStream_t s);
+// Tiles of the fused inference (0 if h or w is not a positive multiple of 16).
+int64_t net_infer_tiles(int h, int w);
+
 template <typename R>
 inline CoefT<R> make_coef(const RunCoef& r, int D, bool deviation) {
   CoefT<R> k;

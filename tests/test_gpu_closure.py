@@ -106,6 +106,42 @@ def test_correction_and_guard_match_oracle():
     eng.close()
 
 
+@pytest.mark.parametrize("guard", [1e9, 1e-3])
+def test_fused_correction_matches_modular(guard):
+    """lbm_closure_correct (moments, fused network, two-launch guard, update)
+    against the same steps called one by one: identical moments and network
+    output, the same decision, and states equal up to the FP64 summation order
+    of the grid means."""
+    n = 64
+    _, _, eng_a = _ctx_state(n, 9, 3)
+    _, _, eng_b = _ctx_state(n, 9, 3)
+    net = cnn.Net(seed=5)
+    net.p.mul_(0.05)
+    net.repack()
+    s_rho, s_u, s_drho, s_dq = 1e-3, 1.0, 1e-6, 1e-3
+    s = torch.cuda.current_stream()
+    m_a = torch.empty((3, n, n), dtype=torch.float32, device="cuda")
+    eng_a.moments_device(m_a)
+    x = torch.empty((1, 3, n, n), dtype=torch.float32, device="cuda")
+    cl.lbm_closure_features(m_a, 2, n * n, 1.0, s_rho, s_u, x, s)
+    y_a = net.forward(x)[0].clone()
+    cl.lbm_closure_apply(eng_a.ctx, m_a, y_a, s_drho, s_dq, guard)
+    m_b = torch.empty_like(m_a)
+    y_b = torch.empty_like(m_a)
+    cl.lbm_closure_correct(eng_b.ctx, net, s_rho, s_u, s_drho, s_dq, guard, m_b, y_b)
+    ra, rb = cl.lbm_closure_report_get(eng_a.ctx), cl.lbm_closure_report_get(eng_b.ctx)
+    assert torch.equal(m_a, m_b) and torch.equal(y_a, y_b)
+    assert ra["accepted"] == rb["accepted"] and ra["n_accepted"] == rb["n_accepted"]
+    assert rb["div_before"] == pytest.approx(ra["div_before"], rel=1e-12)
+    assert rb["div_after"] == pytest.approx(ra["div_after"], rel=1e-9)
+    assert np.allclose(rb["mean"], ra["mean"], rtol=1e-9, atol=1e-18)
+    r_a, q_a = eng_a.moments()
+    r_b, q_b = eng_b.moments()
+    assert np.max(np.abs(r_a - r_b)) <= 1e-7 and np.max(np.abs(q_a - q_b)) <= 1e-6 * np.abs(q_a).max()
+    eng_a.close()
+    eng_b.close()
+
+
 def test_guard_rejects_and_leaves_state_untouched():
     p, u0, eng = _ctx_state()
     n = 64

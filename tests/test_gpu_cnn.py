@@ -176,3 +176,41 @@ def test_channel_rms():
     out = cnn.channel_rms(dev(x), 3, torch.cuda.current_stream())
     ref = np.sqrt(np.mean(np.float32(x).astype(np.float64) ** 2, axis=1))
     assert np.allclose(out.cpu().numpy(), ref, rtol=1e-12)
+
+
+@pytest.mark.parametrize("h,w", [(16, 64), (48, 128), (64, 64)])
+def test_fused_inference_equals_layer_by_layer(h, w):
+    """lbm_net_infer (features + four layers in one launch, activations in LDS)
+    gives the output of lbm_closure_features + four lbm_conv_forward calls bit
+    for bit, and per-tile sums of that output."""
+    from paper_2607_24059_amd import closure as cl
+    rng = np.random.default_rng(h * 1000 + w)
+    rho = 1 + 1e-3 * rng.standard_normal((h, w))
+    q = 0.5 * rng.standard_normal((2, h, w))
+    m = dev(np.concatenate([rho[None], q]))
+    s_rho, s_u = 1e-3, 0.7
+    net = cnn.Net(seed=h + w)
+    s = torch.cuda.current_stream()
+    x = torch.empty((1, 3, h, w), dtype=torch.float32, device="cuda")
+    cl.lbm_closure_features(m, 2, h * w, 1.0, s_rho, s_u, x, s)
+    ref = net.forward(x)[0].clone()
+    y = torch.empty((3, h, w), dtype=torch.float32, device="cuda")
+    part = torch.empty(cnn.lbm_net_partials_bytes(h, w) // 8, dtype=torch.float64, device="cuda")
+    cnn.lbm_net_infer(m, h, w, 1.0, s_rho, s_u, net, y, part, s)
+    torch.cuda.synchronize()
+    assert torch.equal(y, ref)
+    yh = y.double().cpu().numpy()
+    sums = yh.reshape(3, h // 16, 16, w // 16, 16).sum(axis=(2, 4))  # [3][ty][tx]
+    got = part.cpu().numpy().reshape(-1, 4)
+    assert np.allclose(got[:, :3], sums.reshape(3, -1).T, rtol=1e-12, atol=1e-12 * np.abs(yh).sum())
+    assert np.all(got[:, 3] == 0)
+
+
+def test_fused_inference_rejects_ragged_shapes():
+    net = cnn.Net(seed=0)
+    m = torch.ones((3, 40, 64), dtype=torch.float32, device="cuda")
+    y = torch.empty_like(m)
+    part = torch.empty(64, dtype=torch.float64, device="cuda")
+    assert cnn.lbm_net_partials_bytes(40, 64) == 0
+    with pytest.raises(cnn.LbmError):
+        cnn.lbm_net_infer(m, 40, 64, 1.0, 1.0, 1.0, net, y, part, torch.cuda.current_stream())
