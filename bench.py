@@ -149,6 +149,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--variant-steps", type=int, default=200)
+    ap.add_argument("--no-equal-error", action="store_true")
+    ap.add_argument("--equal-error-seeds", type=int, default=2)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -235,10 +237,47 @@ def main():
             variants[f"batch512_{storage}"] = batch_variant(storage, 1000, probe)
         result["variants"] = variants
 
+    if not args.no_equal_error:
+        log("[bench] equal-error comparison (FP64 2048^2 judge, plain FP32 / FP16 levels, learned closure)")
+        result["equal_error"] = equal_error_section(args.equal_error_seeds)
+
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")
         result["cpu_baseline"] = cpu_baseline(n)
     print(json.dumps(result), flush=True)
+
+
+def _finite(v):
+    """JSON-safe copy: NaN / inf become null."""
+    if isinstance(v, dict):
+        return {k: _finite(x) for k, x in v.items()}
+    if isinstance(v, (list, tuple)):
+        return [_finite(x) for x in v]
+    if isinstance(v, float) and not math.isfinite(v):
+        return None
+    return v
+
+
+def equal_error_section(n_seeds: int) -> dict:
+    """Speedups over the plain FP32 scheme at equal error against the fine-grid
+    judge, on the closure workload: k^-3 fields (held-out seeds 1000...),
+    nu = 5e-4, coarse 256^2, judge = the plain scheme at 2048^2 in FP64
+    storage restricted to 256^2, 256 coarse steps.  Plain levels 256^2, 512^2,
+    1024^2 in FP32 and in FP16 + FP32-rest storage; the corrected 256^2 run
+    uses the committed trained network.  Errors: relative L2 of the
+    divergence-free part of u.  Times: HIP events around each run's steps."""
+    from paper_2607_24059_amd import closure, cnn
+    params, meta = closure.load_model(closure.WEIGHTS)
+    cfg = closure.Config(**{k: v for k, v in meta["config"].items()
+                            if k in ("coarse_n", "factor", "nu", "mach", "mu", "every", "guard")})
+    cfg.test_seeds = list(range(1000, 1000 + n_seeds))
+    net = cnn.Net(params=params)
+    ev = closure.evaluate(cfg, net, meta["scales"], log=log)
+    return _finite({"workload": f"k^-3 field, nu={cfg.nu}, coarse {cfg.coarse_n}^2, judge FP64 "
+                        f"{cfg.fine_n}^2 restricted, {cfg.horizon} coarse steps, "
+                        f"seeds {cfg.test_seeds[0]}..{cfg.test_seeds[-1]}",
+            "error_metric": "relative L2 of the divergence-free part of u",
+            "plain": ev["plain"], "closure": ev["closure"], "speedup": ev["speedup_equal_error"]})
 
 
 def batch_variant(storage: str, steps: int, probe: float, n_runs: int = 512) -> dict:

@@ -22,6 +22,7 @@ import argparse
 import ctypes as C
 import json
 import math
+import os
 import sys
 import time
 from dataclasses import asdict, dataclass, field
@@ -407,16 +408,6 @@ def solenoidal(u):
     return np.stack([np.fft.ifft2(ux - kx * div / k2).real, np.fft.ifft2(uy - ky * div / k2).real])
 
 
-def rel_q(m, ref, sol=False):
-    """Relative L2 error of the momentum q (the conserved moment; rho = 1 + O(dx^2)
-    in the incompressible limit, so q and u agree to leading order while q needs
-    no density, whose deviation scales with dx^2 and differs on every grid)."""
-    q, qr = m[1:], ref[1:]
-    if sol:
-        q, qr = solenoidal(q), solenoidal(qr)
-    return float(np.linalg.norm((q - qr).ravel()) / np.linalg.norm(qr.ravel()))
-
-
 def rel_u_sol(m, ref):
     """Relative L2 error of the divergence-free part of u.  The scheme's
     artificial compressibility carries acoustic waves whose speed 1/dx differs
@@ -427,26 +418,30 @@ def rel_u_sol(m, ref):
     return float(np.linalg.norm((u - ur).ravel()) / np.linalg.norm(ur.ravel()))
 
 
-def evaluate(cfg: Config, net, scales, log=print, seeds=None, storage="f32", levels=None, use_graph=True):
-    """Errors against the restricted fine judge after `horizon` coarse steps for
-    the plain scheme at each level and for the corrected coarse run, plus the
-    wall time of each run (HIP events)."""
+def evaluate(cfg: Config, net, scales, log=print, seeds=None, levels=None, plain_storages=("f32", "f16_dev_r32"),
+             use_graph=True):
+    """Errors against the restricted fine judge after `horizon` coarse steps,
+    for the plain scheme at each level in each storage and for the corrected
+    coarse run (FP32 storage), with the wall time of each run (HIP events
+    around the steps only).  Every run starts from the restriction of the fine
+    initial state to its own grid.  Errors are relative L2 over the coarse grid
+    of u (`u`) and of its divergence-free part (`u_sol`, the primary metric:
+    the acoustic waves of the artificial compressibility travel at speed ~1/dx
+    and differ on every grid)."""
     import torch
     s = torch.cuda.current_stream()
     nc = cfg.coarse_n
-    cells = nc * nc
     seeds = cfg.test_seeds if seeds is None else seeds
     levels = cfg.eval_levels if levels is None else levels
     chunks = cfg.horizon // cfg.every
-    res = {"plain": {n: [] for n in levels}, "closure": [], "time_plain": {n: 0.0 for n in levels},
-           "time_closure": 0.0, "accepted": 0, "rejected": 0,
-           "plain_raw": {n: [] for n in levels}, "closure_raw": [],
-           "plain_q": {n: [] for n in levels}, "closure_q": [], "plain_qsol": {n: [] for n in levels},
-           "closure_qsol": []}
+    err = {st: {n: {"u_sol": [], "u": []} for n in levels} for st in plain_storages}
+    tim = {st: {n: [] for n in levels} for st in plain_storages}
+    cerr = {"u_sol": [], "u": []}
+    ctim = []
+    acc = rej = 0
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     mbuf = torch.empty((3, nc, nc), dtype=torch.float32, device="cuda")
-    xbuf = torch.empty((1, 3, nc, nc), dtype=torch.float32, device="cuda")
     for seed in seeds:
         fine = FineRun(cfg, seed, s)
         starts = {}
@@ -458,24 +453,24 @@ def evaluate(cfg: Config, net, scales, log=print, seeds=None, storage="f32", lev
         fine.restricted(nc, judge)
         fine.close()
         judge_h = _host(judge)
-        for n in levels:
-            eng = _engine(cfg, n, storage=storage)
-            lbm_set_equilibrium_device(eng.ctx, starts[n])
-            torch.cuda.synchronize()
-            ev0.record(s)
-            eng.step(cfg.horizon * (n // nc) ** 2)
-            ev1.record(s)
-            mm = torch.empty((3, n, n), dtype=torch.float32, device="cuda")
-            eng.moments_device(mm)
-            lbm_restrict(mm, n, n, n // nc, 1.0, mbuf, s)
-            torch.cuda.synchronize()
-            res["time_plain"][n] += ev0.elapsed_time(ev1)
-            res["plain"][n].append(rel_u_sol(_host(mbuf), judge_h))
-            res["plain_raw"][n].append(rel_u(_host(mbuf), judge_h))
-            res["plain_q"][n].append(rel_q(_host(mbuf), judge_h))
-            res["plain_qsol"][n].append(rel_q(_host(mbuf), judge_h, True))
-            eng.close()
-        run = CorrectedRun(cfg, net, scales, starts[nc], storage=storage, use_graph=use_graph)
+        for st in plain_storages:
+            for n in levels:
+                eng = _engine(cfg, n, storage=st)
+                lbm_set_equilibrium_device(eng.ctx, starts[n])
+                torch.cuda.synchronize()
+                ev0.record(s)
+                eng.step(cfg.horizon * (n // nc) ** 2)
+                ev1.record(s)
+                mm = torch.empty((3, n, n), dtype=torch.float32, device="cuda")
+                eng.moments_device(mm)
+                lbm_restrict(mm, n, n, n // nc, 1.0, mbuf, s)
+                torch.cuda.synchronize()
+                tim[st][n].append(ev0.elapsed_time(ev1))
+                mh = _host(mbuf)
+                err[st][n]["u_sol"].append(rel_u_sol(mh, judge_h))
+                err[st][n]["u"].append(rel_u(mh, judge_h))
+                eng.close()
+        run = CorrectedRun(cfg, net, scales, starts[nc], use_graph=use_graph)
         if use_graph:
             run.run(0)  # capture the window graph outside the timed region
         torch.cuda.synchronize()
@@ -483,69 +478,80 @@ def evaluate(cfg: Config, net, scales, log=print, seeds=None, storage="f32", lev
         run.run(chunks)
         ev1.record(run.stream)
         torch.cuda.synchronize()
-        res["time_closure"] += ev0.elapsed_time(ev1)
+        ctim.append(ev0.elapsed_time(ev1))
         rep = run.report()
-        res["accepted"] += rep["n_accepted"]
-        res["rejected"] += rep["n_rejected"]
+        acc += rep["n_accepted"]
+        rej += rep["n_rejected"]
         run.moments(mbuf)
         torch.cuda.synchronize()
-        res["closure"].append(rel_u_sol(_host(mbuf), judge_h))
-        res["closure_raw"].append(rel_u(_host(mbuf), judge_h))
-        res["closure_q"].append(rel_q(_host(mbuf), judge_h))
-        res["closure_qsol"].append(rel_q(_host(mbuf), judge_h, True))
+        mh = _host(mbuf)
+        cerr["u_sol"].append(rel_u_sol(mh, judge_h))
+        cerr["u"].append(rel_u(mh, judge_h))
         run.close()
-        log(f"[closure] seed {seed}: solenoidal error plain " +
-            ", ".join(f"{n}: {res['plain'][n][-1]:.3e}" for n in levels)
-            + f"; corrected {nc}: {res['closure'][-1]:.3e} | raw plain "
-            + ", ".join(f"{n}: {res['plain_raw'][n][-1]:.3e}" for n in levels)
-            + f"; corrected {res['closure_raw'][-1]:.3e} | q plain "
-            + ", ".join(f"{n}: {res['plain_q'][n][-1]:.3e}" for n in levels)
-            + f"; corrected {res['closure_q'][-1]:.3e} | q_sol plain "
-            + ", ".join(f"{n}: {res['plain_qsol'][n][-1]:.3e}" for n in levels)
-            + f"; corrected {res['closure_qsol'][-1]:.3e} (accepted {rep['n_accepted']}, "
-              f"rejected {rep['n_rejected']})")
-    out = {"plain": {str(n): float(np.mean(v)) for n, v in res["plain"].items()},
-           "closure": float(np.mean(res["closure"])),
-           "per_seed_plain_coarse": res["plain"][nc], "per_seed_closure": res["closure"],
-           "time_plain_ms": {str(n): res["time_plain"][n] / len(seeds) for n in levels},
-           "time_closure_ms": res["time_closure"] / len(seeds),
-           "plain_raw": {str(n): float(np.mean(v)) for n, v in res["plain_raw"].items()},
-           "closure_raw": float(np.mean(res["closure_raw"])),
-           "plain_q": {str(n): float(np.mean(v)) for n, v in res["plain_q"].items()},
-           "closure_q": float(np.mean(res["closure_q"])),
-           "plain_qsol": {str(n): float(np.mean(v)) for n, v in res["plain_qsol"].items()},
-           "closure_qsol": float(np.mean(res["closure_qsol"])),
-           "accepted": res["accepted"], "rejected": res["rejected"], "seeds": list(seeds),
-           "horizon": cfg.horizon, "storage": storage}
-    out["speedup_equal_error"] = equal_error_speedup(out)
+        st0 = plain_storages[0]
+        log(f"[closure] seed {seed}: u_sol plain {st0} " +
+            ", ".join(f"{n}: {err[st0][n]['u_sol'][-1]:.3e}" for n in levels) +
+            f"; corrected {nc}: {cerr['u_sol'][-1]:.3e} | u plain " +
+            ", ".join(f"{n}: {err[st0][n]['u'][-1]:.3e}" for n in levels) +
+            f"; corrected {cerr['u'][-1]:.3e} (accepted {rep['n_accepted']}, rejected {rep['n_rejected']})")
+    mean = lambda v: float(np.mean(v))
+    out = {"levels": list(levels), "seeds": list(seeds), "horizon": cfg.horizon, "every": cfg.every,
+           "plain": {st: {"u_sol": {str(n): mean(err[st][n]["u_sol"]) for n in levels},
+                          "u": {str(n): mean(err[st][n]["u"]) for n in levels},
+                          "time_ms": {str(n): mean(tim[st][n]) for n in levels}} for st in plain_storages},
+           "closure": {"u_sol": mean(cerr["u_sol"]), "u": mean(cerr["u"]), "time_ms": mean(ctim),
+                       "accepted": acc, "rejected": rej},
+           "per_seed": {"plain_coarse_u_sol": err[plain_storages[0]][nc]["u_sol"],
+                        "closure_u_sol": cerr["u_sol"],
+                        "plain_coarse_u": err[plain_storages[0]][nc]["u"], "closure_u": cerr["u"]}}
+    ref = out["plain"][plain_storages[0]]
+    out["speedup_equal_error"] = {
+        "closure": equal_error_speedup(levels, ref["u_sol"], ref["time_ms"], out["closure"]["u_sol"],
+                                       out["closure"]["time_ms"])}
+    for st in plain_storages[1:]:
+        out["speedup_equal_error"][st] = {}
+        for n in levels:
+            r = equal_error_speedup(levels, ref["u_sol"], ref["time_ms"], out["plain"][st]["u_sol"][str(n)],
+                                    out["plain"][st]["time_ms"][str(n)])
+            r["speedup_same_resolution"] = ref["time_ms"][str(n)] / out["plain"][st]["time_ms"][str(n)]
+            out["speedup_equal_error"][st][str(n)] = r
     return out
 
 
-def equal_error_speedup(ev: dict):
-    """Resolution N* at which the plain scheme's error equals the corrected
-    run's, by log-log interpolation over the evaluated levels; speedup =
-    T_plain(N*) / T_closure with T_plain interpolated log-log as well."""
-    levels = sorted(int(n) for n in ev["plain"])
-    e = np.array([ev["plain"][str(n)] for n in levels])
-    tp = np.array([ev["time_plain_ms"][str(n)] for n in levels])
-    ec = ev["closure"]
-    if len(levels) < 2 or not ec < e[0]:
-        return {"N_star": float(levels[0]), "speedup": float(tp[0] / ev["time_closure_ms"]), "note": "no gain"}
-    ln, le, lt = np.log(levels), np.log(e), np.log(tp)
-    for i in range(len(levels) - 1):
-        if le[i + 1] <= math.log(ec) <= le[i]:
-            f = (math.log(ec) - le[i]) / (le[i + 1] - le[i])
-            nstar = math.exp(ln[i] + f * (ln[i + 1] - ln[i]))
-            tstar = math.exp(lt[i] + f * (lt[i + 1] - lt[i]))
-            return {"N_star": nstar, "speedup": tstar / ev["time_closure_ms"], "note": "interpolated"}
-    i = len(levels) - 2
-    slope_e = (le[i + 1] - le[i]) / (ln[i + 1] - ln[i])
-    slope_t = (lt[i + 1] - lt[i]) / (ln[i + 1] - ln[i])
-    if slope_e >= 0:
-        return {"N_star": float("nan"), "speedup": float("nan"), "note": "plain error not decreasing"}
-    lnstar = ln[i + 1] + (math.log(ec) - le[i + 1]) / slope_e
-    tstar = math.exp(lt[i + 1] + slope_t * (lnstar - ln[i + 1]))
-    return {"N_star": math.exp(lnstar), "speedup": tstar / ev["time_closure_ms"], "note": "extrapolated"}
+def equal_error_speedup(levels, err, time_ms, e_target, t_target):
+    """Speedup of a run with error e_target and wall time t_target over the
+    plain FP32 scheme at equal error.  N* is the resolution at which the plain
+    scheme's error equals e_target, by log-log interpolation of err(N) over
+    the levels where it still decreases (FP32 rounding, which grows with the
+    N^2 steps of a run, ends the second-order decrease at fine levels); beyond
+    the last decreasing level it is extrapolated along the last segment.
+    T_plain(N*) is interpolated (extrapolated) log-log the same way;
+    speedup = T_plain(N*) / t_target.  A target error above the coarsest
+    level's has no equal-error point (NaN)."""
+    lv = sorted(int(n) for n in levels)
+    e = [float(err[str(n)]) for n in lv]
+    t = [float(time_ms[str(n)]) for n in lv]
+    k = 1
+    while k < len(lv) and e[k] < e[k - 1]:
+        k += 1
+    lv, e, t = lv[:k], e[:k], t[:k]
+    if not e_target < e[0]:
+        return {"N_star": float("nan"), "speedup": float("nan"),
+                "note": "error above the plain scheme's at the coarsest level: no equal-error point"}
+    if len(lv) < 2:
+        return {"N_star": float("nan"), "speedup": float("nan"), "note": "one level only"}
+    ln, le, lt = np.log(lv), np.log(e), np.log(t)
+    lc = math.log(e_target)
+    i = next((j for j in range(len(lv) - 1) if le[j + 1] <= lc), len(lv) - 2)
+    f = (lc - le[i]) / (le[i + 1] - le[i])
+    nstar = math.exp(ln[i] + f * (ln[i + 1] - ln[i]))
+    tstar = math.exp(lt[i] + f * (lt[i + 1] - lt[i]))
+    note = "interpolated" if f <= 1.0 else "extrapolated beyond the finest decreasing level"
+    return {"N_star": nstar, "speedup": tstar / t_target, "note": note}
+
+
+# trained correction network shipped with the package (written by main())
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "closure_weights.npz")
 
 
 def save_model(path, net, scales, cfg, history, evaluation=None):

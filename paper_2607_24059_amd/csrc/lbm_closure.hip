@@ -282,10 +282,10 @@ hipError_t dispatch_apply(lbm_ctx* c, const float* y, float s_drho, float s_dq, 
   return hipErrorInvalidValue;
 }
 
-// Guard blocks: one per 2048 cells, at most 256 (each block reduces every
+// Guard blocks: one per 256 cells, at most 256 (each block reduces every
 // partial of the previous stage, so their number is kept small).
 int guard_blocks(int64_t cells) {
-  int64_t nb = cells / 2048;
+  int64_t nb = cells / 256;
   if (nb > 256) nb = 256;
   if (nb < 1) nb = 1;
   return static_cast<int>(nb);

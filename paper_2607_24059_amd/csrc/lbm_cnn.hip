@@ -343,10 +343,14 @@ constexpr int kInfT = 16;        // output tile edge
 constexpr int kInfS0 = kInfT + 8;  // input region edge (halo 4)
 constexpr int kInfCh = 32;       // hidden channels
 constexpr int kInfStride = 40;   // LDS elements per pixel of a hidden activation (32 + 8 pad)
+constexpr int kInferWaves = 8;   // waves per block
+constexpr int kInferMP = 4;      // M-tiles in flight per wave (8 x 4 = 32 M-tiles: one round of the 22^2 layer)
 
 // One layer on the block's LDS regions: input region SIN x SIN (pixel stride
-// IN_STRIDE elements), output region SOUT = SIN - 2.
-template <int CINP, int COUTP, int SIN, int IN_STRIDE, bool LAST>
+// IN_STRIDE elements), output region SOUT = SIN - 2.  NW waves split the
+// 16-pixel M-tiles; each wave carries MP M-tiles at once (MP x NT independent
+// accumulator chains, to keep the matrix pipeline busy).
+template <int CINP, int COUTP, int SIN, int IN_STRIDE, bool LAST, int NW, int MP>
 __device__ __forceinline__ void infer_layer(const uint16_t* in, uint16_t* out, const uint16_t* __restrict__ packed,
                                             const float* __restrict__ bias, float* ys) {
   constexpr int SOUT = SIN - 2;
@@ -363,58 +367,76 @@ __device__ __forceinline__ void infer_layer(const uint16_t* in, uint16_t* out, c
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks)
       bf[nt][ks] = *reinterpret_cast<const s4*>(packed + (nt * 16 + li) * KP + ks * 16 + 4 * lq);
-  for (int mt = wave; mt < MT; mt += kThreads / 64) {
-    int o = mt * 16 + li;
-    if (o >= NPIX) o = NPIX - 1;  // padding rows of the last M-tile: read a valid pixel, result dropped
-    const int oy = o / SOUT, ox = o % SOUT;
-    f4 acc[NT];
+  for (int mt0 = wave * MP; mt0 < MT; mt0 += NW * MP) {
+    int oy[MP], ox[MP];
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[nt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int j = 0; j < MP; ++j) {
+      int o = (mt0 + j) * 16 + li;
+      if (o >= NPIX) o = NPIX - 1;  // padding rows of the last M-tile: read a valid pixel, result dropped
+      oy[j] = o / SOUT;
+      ox[j] = o % SOUT;
+    }
+    f4 acc[MP][NT];
+#pragma unroll
+    for (int j = 0; j < MP; ++j)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[j][nt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const int k0 = ks * 16 + 4 * lq;
       const int tap = k0 / CINP, ci0 = k0 % CINP;
-      s4 a = s4{0, 0, 0, 0};
-      if (tap < 9) {
-        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-        a = *reinterpret_cast<const s4*>(in + ((oy + 1 + dy) * SIN + (ox + 1 + dx)) * IN_STRIDE + ci0);
+      const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+      s4 a[MP];
+#pragma unroll
+      for (int j = 0; j < MP; ++j) {
+        a[j] = s4{0, 0, 0, 0};
+        if (tap < 9) a[j] = *reinterpret_cast<const s4*>(in + ((oy[j] + 1 + dy) * SIN + (ox[j] + 1 + dx)) * IN_STRIDE + ci0);
       }
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bf[nt][ks], acc[nt], 0, 0, 0);
+      for (int j = 0; j < MP; ++j)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+          acc[j][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[j], bf[nt][ks], acc[j][nt], 0, 0, 0);
     }
-    // lane holds output channel nt*16 + li of pixels mt*16 + 4*lq + r
+    // lane holds output channel nt*16 + li of pixels (mt0 + j)*16 + 4*lq + r
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      const int co = nt * 16 + li;
-      if (LAST && co >= 3) continue;
-      const float bv = bias[co];
+    for (int j = 0; j < MP; ++j) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int op = mt * 16 + 4 * lq + r;
-        if (op >= NPIX) continue;
-        float v = acc[nt][r] + bv;
-        if (LAST) {
-          ys[co * NPIX + op] = v;
-        } else {
-          v = fmaxf(v, 0.0f);
-          out[op * kInfStride + co] = bf16_bits(v);
+      for (int nt = 0; nt < NT; ++nt) {
+        const int co = nt * 16 + li;
+        if (LAST && co >= 3) continue;
+        const float bv = bias[co];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int op = (mt0 + j) * 16 + 4 * lq + r;
+          if (op >= NPIX) continue;
+          float v = acc[j][nt][r] + bv;
+          if (LAST) {
+            ys[co * NPIX + op] = v;
+          } else {
+            v = fmaxf(v, 0.0f);
+            out[op * kInfStride + co] = bf16_bits(v);
+          }
         }
       }
     }
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_net_infer(const float* __restrict__ m, int h, int w, double rho_ref,
-                                                        float s_rho, float s_u, NetWeights nw,
-                                                        float* __restrict__ y, double* __restrict__ part) {
+template <int NW, int MP>
+__global__ __launch_bounds__(NW * 64) void k_net_infer(const float* __restrict__ m, int h, int w, double rho_ref,
+                                                       float s_rho, float s_u, NetWeights nw,
+                                                       float* __restrict__ y, double* __restrict__ part) {
+  constexpr int NTH = NW * 64;
   __shared__ __attribute__((aligned(16))) uint16_t a0[kInfS0 * kInfS0 * 4];
   __shared__ __attribute__((aligned(16))) uint16_t a1[(kInfS0 - 2) * (kInfS0 - 2) * kInfStride];
   __shared__ __attribute__((aligned(16))) uint16_t a2[(kInfS0 - 4) * (kInfS0 - 4) * kInfStride];
   __shared__ float ys[3 * kInfT * kInfT];
+  __shared__ double red[NW][3];
   const int tx0 = blockIdx.x * kInfT, ty0 = blockIdx.y * kInfT;
   const int64_t cells = static_cast<int64_t>(h) * w;
   // features of the input region, as lbm_closure_features computes them
-  for (int i = threadIdx.x; i < kInfS0 * kInfS0; i += kThreads) {
+  for (int i = threadIdx.x; i < kInfS0 * kInfS0; i += NTH) {
     const int ry = i / kInfS0, rx = i % kInfS0;
     const int gy = ((ty0 - 4 + ry) % h + h) % h, gx = ((tx0 - 4 + rx) % w + w) % w;
     const int64_t c = static_cast<int64_t>(gy) * w + gx;
@@ -425,28 +447,43 @@ __global__ __launch_bounds__(kThreads) void k_net_infer(const float* __restrict_
     a0[i * 4 + 3] = 0;
   }
   __syncthreads();
-  infer_layer<4, kInfCh, kInfS0, 4, false>(a0, a1, nw.packed[0], nw.bias[0], nullptr);
+  infer_layer<4, kInfCh, kInfS0, 4, false, NW, MP>(a0, a1, nw.packed[0], nw.bias[0], nullptr);
   __syncthreads();
-  infer_layer<kInfCh, kInfCh, kInfS0 - 2, kInfStride, false>(a1, a2, nw.packed[1], nw.bias[1], nullptr);
+  infer_layer<kInfCh, kInfCh, kInfS0 - 2, kInfStride, false, NW, MP>(a1, a2, nw.packed[1], nw.bias[1], nullptr);
   __syncthreads();
-  infer_layer<kInfCh, kInfCh, kInfS0 - 4, kInfStride, false>(a2, a1, nw.packed[2], nw.bias[2], nullptr);
+  infer_layer<kInfCh, kInfCh, kInfS0 - 4, kInfStride, false, NW, MP>(a2, a1, nw.packed[2], nw.bias[2], nullptr);
   __syncthreads();
-  infer_layer<kInfCh, 16, kInfS0 - 6, kInfStride, true>(a1, nullptr, nw.packed[3], nw.bias[3], ys);
+  infer_layer<kInfCh, 16, kInfS0 - 6, kInfStride, true, NW, MP>(a1, nullptr, nw.packed[3], nw.bias[3], ys);
   __syncthreads();
-  // output tile and its per-channel FP64 sums (fixed order)
-  const int t = threadIdx.x;  // one pixel of the 16 x 16 tile per thread
-  const int64_t c = static_cast<int64_t>(ty0 + t / kInfT) * w + tx0 + t % kInfT;
-  double sums[3];
+  // output tile and its per-channel FP64 sums (fixed order: pixels in thread
+  // order within a wave by a shuffle tree, then waves in order)
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int t = threadIdx.x; t < kInfT * kInfT; t += NTH) {
+    const int64_t c = static_cast<int64_t>(ty0 + t / kInfT) * w + tx0 + t % kInfT;
 #pragma unroll
-  for (int ch = 0; ch < 3; ++ch) {
-    const float v = ys[ch * kInfT * kInfT + t];
-    y[ch * cells + c] = v;
-    sums[ch] = block_sum(static_cast<double>(v));
+    for (int ch = 0; ch < 3; ++ch) {
+      const float v = ys[ch * kInfT * kInfT + t];
+      y[ch * cells + c] = v;
+      acc[ch] += static_cast<double>(v);
+    }
   }
-  if (t == 0) {
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch)
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) acc[ch] += __shfl_xor(acc[ch], off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) red[wave][ch] = acc[ch];
+  __syncthreads();
+  if (threadIdx.x == 0) {
     const int64_t tile = static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x;
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) part[tile * 4 + ch] = sums[ch];
+    for (int ch = 0; ch < 3; ++ch) {
+      double s = 0.0;
+      for (int wv = 0; wv < NW; ++wv) s += red[wv][ch];
+      part[tile * 4 + ch] = s;
+    }
     part[tile * 4 + 3] = 0.0;
   }
 }
@@ -535,8 +572,9 @@ hipError_t net_infer_launch(const float* m, int h, int w, double rho_ref, float 
     nw.packed[l] = static_cast<const uint16_t*>(packed[l]);
     nw.bias[l] = bias[l];
   }
-  hipLaunchKernelGGL(k_net_infer, dim3(w / kInfT, h / kInfT), dim3(kThreads), 0, s, m, h, w, rho_ref, s_rho, s_u,
-                     nw, y, part);
+  constexpr int NW = kInferWaves, MP = kInferMP;
+  hipLaunchKernelGGL((k_net_infer<NW, MP>), dim3(w / kInfT, h / kInfT), dim3(NW * 64), 0, s, m, h, w, rho_ref, s_rho,
+                     s_u, nw, y, part);
   return hipGetLastError();
 }
 

@@ -1,0 +1,32 @@
+"""Host logic of the closure driver (no GPU): the equal-error speedup."""
+
+import math
+
+import pytest
+
+from paper_2607_24059_amd import closure as cl
+
+LEVELS = (256, 512, 1024)
+ERR = {"256": 4e-5, "512": 1e-5, "1024": 3e-5}   # FP32 rounding lifts the finest level
+TIME = {"256": 0.9, "512": 4.6, "1024": 70.0}
+
+
+def test_interpolated_between_levels():
+    r = cl.equal_error_speedup(LEVELS, ERR, TIME, 2e-5, 1.0)
+    assert r["note"] == "interpolated"
+    assert r["N_star"] == pytest.approx(256 * math.sqrt(2), rel=1e-12)        # second order: e ~ N^-2
+    assert r["speedup"] == pytest.approx(0.9 * math.sqrt(4.6 / 0.9), rel=1e-12)
+
+
+def test_extrapolated_past_the_rounding_floor():
+    """Below the 512 error the 1024 level (larger error) is ignored and the
+    256 -> 512 segment extended."""
+    r = cl.equal_error_speedup(LEVELS, ERR, TIME, 5e-6, 2.0)
+    assert r["note"].startswith("extrapolated")
+    assert r["N_star"] == pytest.approx(256 * 2 ** 1.5, rel=1e-12)
+    assert r["speedup"] == pytest.approx(0.9 * (4.6 / 0.9) ** 1.5 / 2.0, rel=1e-12)
+
+
+def test_no_equal_error_point():
+    r = cl.equal_error_speedup(LEVELS, ERR, TIME, 5e-5, 3.0)
+    assert math.isnan(r["N_star"]) and math.isnan(r["speedup"])

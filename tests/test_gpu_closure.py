@@ -196,8 +196,10 @@ def test_end_to_end_small_configuration():
     net, hist = cl.train(cfg, x, t, log=lambda *a: None)
     assert all(math.isfinite(h) for h in hist)
     ev = cl.evaluate(cfg, net, scales, log=lambda *a: None)
-    assert math.isfinite(ev["closure"]) and math.isfinite(ev["plain"]["64"])
-    assert ev["accepted"] + ev["rejected"] == 4
+    assert math.isfinite(ev["closure"]["u_sol"]) and math.isfinite(ev["plain"]["f32"]["u_sol"]["64"])
+    assert math.isfinite(ev["plain"]["f16_dev_r32"]["time_ms"]["128"])
+    assert ev["closure"]["accepted"] + ev["closure"]["rejected"] == 4
+    assert "speedup" in ev["speedup_equal_error"]["closure"]
 
 
 def test_graph_replayed_window_equals_eager():
