@@ -34,7 +34,7 @@ PEAK_HBM_GBS = 8000.0                 # MI355X published HBM3E bandwidth
 METRIC = "MLUPS & % HBM peak; fp16-store / learned closure vs plain fp32 at fixed error"
 BYTES_PER_LUP = {("f32", 2): 120, ("f16_dev", 2): 60, ("bf16_dev", 2): 60, ("f16_dev_r32", 2): 72,
                  ("bf16_dev_r32", 2): 72, ("f32_raw", 2): 120, ("f32", 3): 224, ("f16_dev", 3): 112, ("bf16_dev", 3): 112,
-                 ("f16_dev_r32", 3): 128, ("bf16_dev_r32", 3): 128}
+                 ("f16_dev_r32", 3): 128, ("bf16_dev_r32", 3): 128, ("f16_neq", 2): 72, ("f16_neq", 3): 128}
 KERNEL_SOURCES = ("paper_2607_24059_amd/csrc/lbm_kernels.hip", "paper_2607_24059_amd/csrc/lbm_device.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step2_2d_f32_4096_traffic.json")
 
@@ -219,7 +219,7 @@ def main():
         ms_v, e = time_engine(n, 2, "f32", vs, 10, u0=u0, fuse=1)
         e.close()
         variants[f"2d_{n}_f32_one_step_per_launch"] = _variant(cells, ms_v, BYTES_PER_LUP[("f32", 2)], probe)
-        for storage in ("f16_dev", "bf16_dev", "f16_dev_r32"):
+        for storage in ("f16_dev", "bf16_dev", "f16_dev_r32", "f16_neq"):
             log(f"[bench] variant 2D {storage}")
             ms_v, e = time_engine(n, 2, storage, vs, 10, u0=u0)
             e.close()
@@ -227,7 +227,7 @@ def main():
         del u0
         n3 = 256
         u3, *_ = make_workload(n3, 3, 1e-3)
-        for storage in ("f32", "f16_dev", "f16_dev_r32"):
+        for storage in ("f32", "f16_dev", "f16_dev_r32", "f16_neq"):
             log(f"[bench] variant 3D {storage}")
             ms_v, e = time_engine(n3, 3, storage, vs, 10, u0=u3)
             e.close()

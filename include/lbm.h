@@ -59,6 +59,15 @@ typedef enum lbm_status {
  *                     each set as FP32 g
  *   LBM_BF16_DEV_R32  as above with BF16 moving populations
  *   LBM_F32_RAW       the populations f themselves in FP32
+ *   LBM_F16_NEQ       equilibrium-split storage: per cell the moments W in
+ *                     FP32 (W_rho as a deviation from rho_ref) in place of the
+ *                     rest planes, and per set and moving velocity the
+ *                     non-equilibrium part n = f* - f^eq(W) in FP16, times a
+ *                     power-of-two scale per set fixed by lbm_init from the
+ *                     initial state (saved with the state); the rest entry's
+ *                     part is minus the sum of the moving ones.  Same bytes as
+ *                     LBM_F16_DEV_R32 with about FP32 accuracy, since FP16 only
+ *                     rounds the small non-equilibrium parts
  *   LBM_F64           g in FP64 with FP64 arithmetic: the reference mode for
  *                     long fine-grid runs, where FP32 rounding accumulates over
  *                     many steps; one step per launch (lbm_set_fusion(2)
@@ -70,7 +79,8 @@ typedef enum lbm_storage {
   LBM_F16_DEV_R32 = 3,
   LBM_BF16_DEV_R32 = 4,
   LBM_F32_RAW = 5,
-  LBM_F64 = 6
+  LBM_F64 = 6,
+  LBM_F16_NEQ = 7
 } lbm_storage;
 
 /* Flag bits reported in lbm_diag.flags and by lbm_check_params(). */
@@ -152,7 +162,7 @@ lbm_status lbm_diagnostics(lbm_ctx* ctx, lbm_diag* out);
 /* Size of a full state snapshot: every population plane (without padding:
  * the D+1 rest planes of cells x rest element, then the (D+1) 2D moving planes
  * of cells x moving element, in the element types of the storage mode), then
- * the step count as int64. */
+ * the step count as int64, then for LBM_F16_NEQ the four FP32 per-set scales. */
 size_t lbm_state_bytes(const lbm_ctx* ctx);
 /* Copy the full state to / from host memory (synchronises).  Restarting from
  * moments alone is not a continuation (the non-equilibrium part is lost), so

@@ -418,7 +418,7 @@ def rel_u_sol(m, ref):
     return float(np.linalg.norm((u - ur).ravel()) / np.linalg.norm(ur.ravel()))
 
 
-def evaluate(cfg: Config, net, scales, log=print, seeds=None, levels=None, plain_storages=("f32", "f16_dev_r32"),
+def evaluate(cfg: Config, net, scales, log=print, seeds=None, levels=None, plain_storages=("f32", "f16_neq", "f16_dev_r32"),
              use_graph=True):
     """Errors against the restricted fine judge after `horizon` coarse steps,
     for the plain scheme at each level in each storage and for the corrected

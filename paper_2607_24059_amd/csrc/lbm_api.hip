@@ -63,6 +63,39 @@ size_t staging_bytes(const Geometry& g) { return static_cast<size_t>(g.dim + 1) 
 
 lbm_status dev(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EDEVICE; }
 
+// Power-of-two scales of the split storage, one per set: 2^13 / M_i rounded
+// down to a power of two, M_i the largest moving equilibrium deviation
+// |alpha_i W_i| + |F_ij| / (2 mu) of the initial state (FP64, on the host).
+// Non-equilibrium parts are a small fraction of M_i, so they sit well inside
+// FP16's normal range with 8x headroom below its largest finite value.
+void neq_scales(const lbm_params* p, double mu, double aq, const double* u0, const double* rho0, int64_t cells,
+                float out[4]) {
+  const int D = p->dim;
+  const double c = 1.0 / (2.0 * mu);
+  double M[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t x = 0; x < cells; ++x) {
+    const double rho = rho0 ? rho0[x] : p->rho_ref;
+    const double dr = rho - p->rho_ref;
+    double W[3] = {0.0, 0.0, 0.0};
+    for (int j = 0; j < D; ++j) W[j] = p->dx * rho * u0[j * cells + x];
+    for (int j = 0; j < D; ++j) {
+      M[0] = fmax(M[0], fabs(p->alpha_rho * dr) + c * fabs(W[j]));
+      for (int i = 0; i < D; ++i) {
+        const double F = W[i] * W[j] / rho + (i == j ? dr : 0.0);
+        M[1 + i] = fmax(M[1 + i], fabs(aq * W[i]) + c * fabs(F));
+      }
+    }
+  }
+  for (int i = 0; i < 4; ++i) {
+    out[i] = 1.0f;
+    if (i <= D && M[i] > 0.0 && isfinite(M[i])) {
+      int e = 13 - static_cast<int>(ceil(log2(M[i])));
+      e = e < -100 ? -100 : (e > 100 ? 100 : e);
+      out[i] = static_cast<float>(ldexp(1.0, e));
+    }
+  }
+}
+
 void default_block(const Geometry& g, int* bx, int* by) {
   int x = 256;
   while (x > 64 && x / 2 >= g.nx) x /= 2;
@@ -111,6 +144,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const 
   c->g = g;
   c->ops = lbm::ops_for(p->dim, p->storage);
   c->coef = RunCoef{p->dx, mu, p->alpha_rho, aq, p->omega_rho, p->omega_q, p->rho_ref};
+  if (p->storage == LBM_F16_NEQ) neq_scales(p, mu, aq, u0, rho0, g.cells, c->coef.neq_s);
   c->ws = static_cast<char*>(workspace);
   c->ws_bytes = ws_bytes;
   c->cur = c->ws;
@@ -209,7 +243,8 @@ lbm_status lbm_diagnostics(lbm_ctx* c, lbm_diag* out) {
 
 // The snapshot holds every plane without its padding: the rest planes
 // (D+1 x cells x rest element), the moving planes ((D+1) 2D x cells x moving
-// element), then the step count.
+// element), then the step count, then (split storage only) the four FP32
+// per-set scales the moving planes were written with.
 static size_t compact_rest(const lbm_ctx* c) {
   return static_cast<size_t>(c->p.dim + 1) * c->g.cells * c->g.rest_elem;
 }
@@ -217,9 +252,13 @@ static size_t compact_move(const lbm_ctx* c) {
   return static_cast<size_t>(c->p.dim + 1) * 2 * c->p.dim * c->g.cells * c->g.move_elem;
 }
 
+static size_t trailer_bytes(const lbm_ctx* c) {
+  return sizeof(int64_t) + (c->p.storage == LBM_F16_NEQ ? sizeof(c->coef.neq_s) : 0);
+}
+
 size_t lbm_state_bytes(const lbm_ctx* c) {
   if (!c) return 0;
-  return compact_rest(c) + compact_move(c) + sizeof(int64_t);
+  return compact_rest(c) + compact_move(c) + trailer_bytes(c);
 }
 
 static hipError_t copy_planes(lbm_ctx* c, char* host, bool to_host) {
@@ -247,7 +286,9 @@ lbm_status lbm_save_state(lbm_ctx* c, void* host, size_t bytes) {
   if (!c || !host) return LBM_EINVAL;
   if (bytes != lbm_state_bytes(c)) return LBM_ESTATE;
   if (copy_planes(c, static_cast<char*>(host), true) != hipSuccess) return LBM_EDEVICE;
-  memcpy(static_cast<char*>(host) + compact_rest(c) + compact_move(c), &c->steps, sizeof(int64_t));
+  char* t = static_cast<char*>(host) + compact_rest(c) + compact_move(c);
+  memcpy(t, &c->steps, sizeof(int64_t));
+  if (c->p.storage == LBM_F16_NEQ) memcpy(t + sizeof(int64_t), c->coef.neq_s, sizeof(c->coef.neq_s));
   return LBM_OK;
 }
 
@@ -255,7 +296,9 @@ lbm_status lbm_load_state(lbm_ctx* c, const void* host, size_t bytes) {
   if (!c || !host) return LBM_EINVAL;
   if (bytes != lbm_state_bytes(c)) return LBM_ESTATE;
   if (copy_planes(c, const_cast<char*>(static_cast<const char*>(host)), false) != hipSuccess) return LBM_EDEVICE;
-  memcpy(&c->steps, static_cast<const char*>(host) + compact_rest(c) + compact_move(c), sizeof(int64_t));
+  const char* t = static_cast<const char*>(host) + compact_rest(c) + compact_move(c);
+  memcpy(&c->steps, t, sizeof(int64_t));
+  if (c->p.storage == LBM_F16_NEQ) memcpy(c->coef.neq_s, t + sizeof(int64_t), sizeof(c->coef.neq_s));
   return LBM_OK;
 }
 

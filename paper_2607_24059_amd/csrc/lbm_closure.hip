@@ -87,6 +87,15 @@ __global__ __launch_bounds__(256) void k_set_eq(const float* __restrict__ m, int
   W[0] = rho - k.ref;
 #pragma unroll
   for (int j = 0; j < D; ++j) W[1 + j] = dx * static_cast<double>(m[(1 + j) * cells + c]);
+  if constexpr (IsNeq<TM>::value) {  // split storage: the moments, no non-equilibrium part
+#pragma unroll
+    for (int i = 0; i < D + 1; ++i) {
+      store_real(rest + i * stride + c, W[i]);
+#pragma unroll
+      for (int v = 0; v < 2 * D; ++v) store_f32(move + (i * 2 * D + v) * stride + c, 0.0f);
+    }
+    return;
+  }
   double eq[D + 1][2 * D + 1];
   equilibrium<D, double>(W, 1.0 / rho, k, eq);
 #pragma unroll
@@ -205,6 +214,17 @@ __global__ __launch_bounds__(256) void k_cl_apply2(const float* __restrict__ y, 
   if (!ok) return;
   const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (c >= cells) return;
+  if constexpr (IsNeq<TM>::value) {
+    // split storage: f + f^eq(W + dW) - f^eq(W) has moments W + dW and the same
+    // non-equilibrium part, so only the moment planes change
+    store_real(rest + c, load_f64(rest + c) + (static_cast<double>(y[c]) * s_drho - slots[kSlotMean]));
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      float* pr = rest + (1 + j) * stride + c;
+      store_real(pr, load_f64(pr) + dx * (static_cast<double>(y[(1 + j) * cells + c]) * s_dq - slots[kSlotMean + 1 + j]));
+    }
+    return;
+  }
   double W[D + 1];
 #pragma unroll
   for (int i = 0; i < D + 1; ++i) {
@@ -264,6 +284,7 @@ hipError_t dispatch_set_eq(lbm_ctx* c, const float* m) {
     case LBM_F16_DEV_R32: return ClosureImpl<D, float, _Float16, true>::set_eq(c, m);
     case LBM_BF16_DEV_R32: return ClosureImpl<D, float, bf16, true>::set_eq(c, m);
     case LBM_F64: return ClosureImpl<D, double, double, true>::set_eq(c, m);
+    case LBM_F16_NEQ: return ClosureImpl<D, float, neq16, true>::set_eq(c, m);
   }
   return hipErrorInvalidValue;
 }
@@ -278,6 +299,7 @@ hipError_t dispatch_apply(lbm_ctx* c, const float* y, float s_drho, float s_dq, 
     case LBM_F16_DEV_R32: return ClosureImpl<2, float, _Float16, true>::apply(c, y, s_drho, s_dq, slots, div_part, n, factor);
     case LBM_BF16_DEV_R32: return ClosureImpl<2, float, bf16, true>::apply(c, y, s_drho, s_dq, slots, div_part, n, factor);
     case LBM_F64: return ClosureImpl<2, double, double, true>::apply(c, y, s_drho, s_dq, slots, div_part, n, factor);
+    case LBM_F16_NEQ: return ClosureImpl<2, float, neq16, true>::apply(c, y, s_drho, s_dq, slots, div_part, n, factor);
   }
   return hipErrorInvalidValue;
 }

@@ -54,6 +54,22 @@ __device__ __forceinline__ uint16_t bf16_bits(float v) {
 }
 __device__ __forceinline__ void store_f32(bf16* p, float v) { p->bits = bf16_bits(v); }
 
+// Moving planes of the equilibrium-split storage (LBM_F16_NEQ): FP16 bits of a
+// scaled non-equilibrium part; a type of its own selects that storage's code.
+struct neq16 {
+  _Float16 v;
+};
+__device__ __forceinline__ float load_f32(const neq16* p) { return static_cast<float>(p->v); }
+__device__ __forceinline__ void store_f32(neq16* p, float v) { p->v = static_cast<_Float16>(v); }
+template <typename TM>
+struct IsNeq {
+  static constexpr bool value = false;
+};
+template <>
+struct IsNeq<neq16> {
+  static constexpr bool value = true;
+};
+
 // FP64 storage (the reference mode): loaded, updated and stored in FP64.
 __device__ __forceinline__ double load_f64(const double* p) { return *p; }
 template <typename T>
@@ -95,6 +111,9 @@ __device__ __forceinline__ void store_stream(bf16* p, float v) {
   __builtin_nontemporal_store(bf16_bits(v), reinterpret_cast<uint16_t*>(p));
 }
 __device__ __forceinline__ void store_stream(double* p, double v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void store_stream(neq16* p, float v) {
+  __builtin_nontemporal_store(static_cast<_Float16>(v), reinterpret_cast<_Float16*>(p));
+}
 
 // ----------------------------------------------------------------------------
 // lattice description: D2Q5 / D3Q7 per set, D+1 sets
@@ -190,12 +209,12 @@ __device__ __forceinline__ void collide(R (&g)[D + 1][2 * D + 1], const CoefT<R>
 // Gather the post-relaxation values of the upwind neighbours of cell (x, y, z):
 // the pull form of the transport phase, f_{+e_j}(t+dt, x) = f*_{+e_j}(t, x - dx e_j),
 // on the periodic grid.  c is the cell's linear index.
-template <int D, typename TR, typename TM, typename R>
-__device__ __forceinline__ void gather_cell(const TR* __restrict__ sr, const TM* __restrict__ sm, int x, int y,
-                                            int z, int nx, int ny, int nz, int64_t stride, int64_t c,
-                                            R (&g)[D + 1][2 * D + 1]) {
+// Linear indices of the upwind neighbour of cell c = (x, y, z) for each moving
+// velocity (periodic wrap).
+template <int D>
+__device__ __forceinline__ void upwind_sources(int x, int y, int z, int nx, int ny, int nz, int64_t c,
+                                               int64_t (&src)[2 * D]) {
   const int64_t plane = static_cast<int64_t>(nx) * ny;
-  int64_t src[2 * D];
   src[0] = (x == 0) ? c + (nx - 1) : c - 1;                                   // +x from x-1
   src[1] = (x == nx - 1) ? c - (nx - 1) : c + 1;                              // -x from x+1
   src[2] = (y == 0) ? c + static_cast<int64_t>(ny - 1) * nx : c - nx;         // +y from y-1
@@ -204,6 +223,14 @@ __device__ __forceinline__ void gather_cell(const TR* __restrict__ sr, const TM*
     src[4] = (z == 0) ? c + static_cast<int64_t>(nz - 1) * plane : c - plane;      // +z
     src[5] = (z == nz - 1) ? c - static_cast<int64_t>(nz - 1) * plane : c + plane; // -z
   }
+}
+
+template <int D, typename TR, typename TM, typename R>
+__device__ __forceinline__ void gather_cell(const TR* __restrict__ sr, const TM* __restrict__ sm, int x, int y,
+                                            int z, int nx, int ny, int nz, int64_t stride, int64_t c,
+                                            R (&g)[D + 1][2 * D + 1]) {
+  int64_t src[2 * D];
+  upwind_sources<D>(x, y, z, nx, ny, nz, c, src);
 #pragma unroll
   for (int i = 0; i < D + 1; ++i) {
     g[i][0] = load_as<R>(sr + i * stride + c);
@@ -231,6 +258,120 @@ __device__ __forceinline__ void step_cell(const TR* __restrict__ sr, const TM* _
     store_stream(dr + i * stride + c, g[i][0]);
 #pragma unroll
     for (int m = 0; m < 2 * D; ++m) store_stream(dm + (i * 2 * D + m) * stride + c, g[i][1 + m]);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Equilibrium-split storage (LBM_F16_NEQ)
+//
+// Per cell the moments W (FP32 planes in place of the rest planes; W_rho as a
+// deviation from rho_ref) and, per set i and moving velocity, the
+// non-equilibrium part n = f* - f^eq(W) of the stored post-relaxation
+// population, in FP16 after multiplication by a power of two s_i per set.
+// The rest entry's non-equilibrium part is minus the sum of the moving ones
+// (f* and f^eq both sum to W), so W is conserved exactly by the storage and
+// FP16 only ever rounds the small non-equilibrium parts.
+// ----------------------------------------------------------------------------
+template <int D>
+struct NeqScale {
+  float s[D + 1];    // stored value = n * s[i]
+  float inv[D + 1];  // 1 / s[i]
+};
+
+// 1 / rho in the split-storage paths: the hardware reciprocal (1 ulp), used by
+// every split-storage routine alike so that a cell's equilibrium rebuilt by a
+// neighbour equals the one the cell computed itself, bit for bit.
+__device__ __forceinline__ float recip_neq(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// The equilibrium (deviation) of set i, moving velocity 1 + m (axis m / 2,
+// + for even m), at a cell with moments W; the arithmetic of equilibrium<D, float>.
+template <int D>
+__device__ __forceinline__ float eq_moving(const float (&W)[D + 1], float inv, const Coef& k, int i, int m) {
+  const int j = m >> 1;
+  float base, flux;
+  if (i == 0) {
+    base = k.a_rho * W[0];
+    flux = k.c * W[1 + j];
+  } else {
+    const float wi = W[i];
+    base = k.a_q * wi;
+    float F = (wi * inv) * W[1 + j];
+    if (i - 1 == j) F = F + W[0];
+    flux = k.c * F;
+  }
+  return (m & 1) ? base - flux : base + flux;
+}
+
+// Pull-transported populations (deviations) of one cell from split storage.
+// w_at(i, nb): W_i of the cell (nb < 0) or of its upwind neighbour for moving
+// velocity nb; n_at(i, m, nb): stored (scaled) n of set i, velocity m there.
+template <int D, typename WAt, typename NAt>
+__device__ __forceinline__ void gather_neq(WAt w_at, NAt n_at, const Coef& k, const NeqScale<D>& sc,
+                                           float (&g)[D + 1][2 * D + 1]) {
+#pragma unroll
+  for (int i = 0; i < D + 1; ++i) {
+    float s = n_at(i, 0, -1);
+#pragma unroll
+    for (int m = 1; m < 2 * D; ++m) s = s + n_at(i, m, -1);
+    const float wl = w_at(i, -1);
+    const float d2a = (i == 0) ? k.d2a_rho : k.d2a_q;
+    g[i][0] = (wl - d2a * wl) - s * sc.inv[i];
+  }
+#pragma unroll
+  for (int m = 0; m < 2 * D; ++m) {
+    float Wn[D + 1];
+#pragma unroll
+    for (int i = 0; i < D + 1; ++i) Wn[i] = w_at(i, m);
+    const float inv = recip_neq(Wn[0] + k.ref);
+#pragma unroll
+    for (int i = 0; i < D + 1; ++i) g[i][1 + m] = eq_moving<D>(Wn, inv, k, i, m) + n_at(i, m, m) * sc.inv[i];
+  }
+}
+
+// Relaxation in split form: W = sum_l f_l (unchanged by the relaxation) and
+// n* = f* - f^eq(W) = (1 - omega)(f - f^eq(W)) for the moving velocities;
+// eq receives f^eq(W).
+template <int D>
+__device__ __forceinline__ void collide_neq(const float (&g)[D + 1][2 * D + 1], const Coef& k, float (&W)[D + 1],
+                                            float (&n)[D + 1][2 * D], float (&eq)[D + 1][2 * D + 1]) {
+#pragma unroll
+  for (int i = 0; i < D + 1; ++i) {
+    float s = g[i][0];
+#pragma unroll
+    for (int l = 1; l < 2 * D + 1; ++l) s = s + g[i][l];
+    W[i] = s;
+  }
+  const float inv = recip_neq(W[0] + k.ref);
+  equilibrium<D, float>(W, inv, k, eq);
+#pragma unroll
+  for (int i = 0; i < D + 1; ++i) {
+    const float r = 1.0f - ((i == 0) ? k.w_rho : k.w_q);
+#pragma unroll
+    for (int m = 0; m < 2 * D; ++m) n[i][m] = r * (g[i][1 + m] - eq[i][1 + m]);
+  }
+}
+
+// One lattice update of cell (x, y, z) in split storage.
+template <int D>
+__device__ __forceinline__ void step_cell_neq(const float* __restrict__ sr, const neq16* __restrict__ sm,
+                                              float* __restrict__ dr, neq16* __restrict__ dm, int x, int y, int z,
+                                              int nx, int ny, int nz, int64_t stride, const Coef& k,
+                                              const NeqScale<D>& sc) {
+  const int64_t plane = static_cast<int64_t>(nx) * ny;
+  const int64_t c = static_cast<int64_t>(z) * plane + static_cast<int64_t>(y) * nx + x;
+  int64_t src[2 * D];
+  upwind_sources<D>(x, y, z, nx, ny, nz, c, src);
+  auto w_at = [&](int i, int nb) { return sr[i * stride + (nb < 0 ? c : src[nb])]; };
+  auto n_at = [&](int i, int m, int nb) { return load_f32(sm + (i * 2 * D + m) * stride + (nb < 0 ? c : src[nb])); };
+  float g[D + 1][2 * D + 1];
+  gather_neq<D>(w_at, n_at, k, sc, g);
+  float W[D + 1], n[D + 1][2 * D], eq[D + 1][2 * D + 1];
+  collide_neq<D>(g, k, W, n, eq);
+#pragma unroll
+  for (int i = 0; i < D + 1; ++i) {
+    store_stream(dr + i * stride + c, W[i]);
+#pragma unroll
+    for (int m = 0; m < 2 * D; ++m) store_stream(dm + (i * 2 * D + m) * stride + c, n[i][m] * sc.s[i]);
   }
 }
 

@@ -13,7 +13,18 @@ namespace lbm {
 // Scalar coefficients of one run, in double (init) and float (step).
 struct RunCoef {
   double dx, mu, alpha_rho, alpha_q, omega_rho, omega_q, ref;
+  float neq_s[4] = {1.0f, 1.0f, 1.0f, 1.0f};  // split storage: power-of-two scale per set
 };
+
+template <int D>
+inline NeqScale<D> neq_scale_of(const RunCoef& r) {
+  NeqScale<D> sc;
+  for (int i = 0; i < D + 1; ++i) {
+    sc.s[i] = r.neq_s[i];
+    sc.inv[i] = 1.0f / r.neq_s[i];  // exact: a power of two
+  }
+  return sc;
+}
 
 // Geometry of one state buffer.
 struct Geometry {

@@ -32,6 +32,15 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ u0,
   W[0] = rho - k.ref;  // deviation when k.ref = rho_ref, plain when 0
 #pragma unroll
   for (int j = 0; j < D; ++j) W[1 + j] = dx * rho * u0[j * cells + c];
+  if constexpr (IsNeq<TM>::value) {  // split storage: the moments, no non-equilibrium part
+#pragma unroll
+    for (int i = 0; i < D + 1; ++i) {
+      store_real(rest + i * stride + c, W[i]);
+#pragma unroll
+      for (int m = 0; m < 2 * D; ++m) store_f32(move + (i * 2 * D + m) * stride + c, 0.0f);
+    }
+    return;
+  }
   double eq[D + 1][2 * D + 1];
   equilibrium<D, double>(W, 1.0 / rho, k, eq);
 #pragma unroll
@@ -49,12 +58,16 @@ template <int D, typename TR, typename TM>
 __global__ __launch_bounds__(256) void k_step(const TR* __restrict__ sr,
                                               const TM* __restrict__ sm, TR* __restrict__ dr,
                                               TM* __restrict__ dm, int nx, int ny, int nz,
-                                              int64_t stride, CoefT<typename ComputeOf<TM>::type> k) {
+                                              int64_t stride, CoefT<typename ComputeOf<TM>::type> k,
+                                              NeqScale<D> sc) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= nx || y >= ny) return;
-  step_cell<D, TR, TM>(sr, sm, dr, dm, x, y, z, nx, ny, nz, stride, k);
+  if constexpr (IsNeq<TM>::value)
+    step_cell_neq<D>(sr, sm, dr, dm, x, y, z, nx, ny, nz, stride, k, sc);
+  else
+    step_cell<D, TR, TM>(sr, sm, dr, dm, x, y, z, nx, ny, nz, stride, k);
 }
 
 // ----------------------------------------------------------------------------
@@ -65,10 +78,79 @@ __global__ __launch_bounds__(256) void k_step(const TR* __restrict__ sr,
 // read from HBM (TX+2)(TY+2)/(TX TY) times and written once per two steps, and
 // the result is bit-identical to two single steps.
 // ----------------------------------------------------------------------------
+// The two-step tile in split storage.  Phase 1 advances the extended tile by
+// one step from HBM (rebuilding the upwind neighbours' equilibria), rounds its
+// non-equilibrium parts to the stored FP16 values, and keeps the populations
+// they stand for, f* = f^eq(W) + n / s (rest: f^eq_rest(W) - sum_m n_m / s),
+// in LDS as FP32: exactly the values the next step's gather would rebuild from
+// HBM.  Phase 2 then gathers them like the plain kernel does, so the tile's
+// second step needs no neighbour equilibria and the result equals two single
+// steps bit for bit.
+template <int TX, int TY, int NT>
+__device__ __forceinline__ void step2_neq_tile(const float* __restrict__ sr, const neq16* __restrict__ sm,
+                                               float* __restrict__ dr, neq16* __restrict__ dm, int nx, int ny,
+                                               int64_t stride, const Coef& k, const NeqScale<2>& sc) {
+  constexpr int EX = TX + 2, EY = TY + 2, EN = EX * EY;
+  __shared__ float s_f[15][EN];
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  for (int e = threadIdx.x; e < EN; e += NT) {
+    const int ex = e % EX, ey = e / EX;
+    int x = x0 - 1 + ex, y = y0 - 1 + ey;
+    x = ((x % nx) + nx) % nx;  // the border may wrap (several times on tiny grids)
+    y = ((y % ny) + ny) % ny;
+    const int64_t c = static_cast<int64_t>(y) * nx + x;
+    int64_t src[4];
+    upwind_sources<2>(x, y, 0, nx, ny, 1, c, src);
+    auto w_at = [&](int i, int nb) { return sr[i * stride + (nb < 0 ? c : src[nb])]; };
+    auto n_at = [&](int i, int m, int nb) { return load_f32(sm + (i * 4 + m) * stride + (nb < 0 ? c : src[nb])); };
+    float g[3][5];
+    gather_neq<2>(w_at, n_at, k, sc, g);
+    float W[3], n[3][4], eq[3][5];
+    collide_neq<2>(g, k, W, n, eq);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      float nr[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) nr[m] = static_cast<float>(static_cast<_Float16>(n[i][m] * sc.s[i]));
+      const float s = ((nr[0] + nr[1]) + nr[2]) + nr[3];
+      s_f[i * 5][e] = (W[i] - ((i == 0) ? k.d2a_rho : k.d2a_q) * W[i]) - s * sc.inv[i];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) s_f[i * 5 + 1 + m][e] = eq[i][1 + m] + nr[m] * sc.inv[i];
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < TX * TY; t += NT) {
+    const int tx = t % TX, ty = t / TX;
+    const int x = x0 + tx, y = y0 + ty;
+    if (x >= nx || y >= ny) continue;
+    const int e = (ty + 1) * EX + (tx + 1);
+    float g[3][5];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      g[i][0] = s_f[i * 5][e];
+      g[i][1] = s_f[i * 5 + 1][e - 1];   // +x from x-1
+      g[i][2] = s_f[i * 5 + 2][e + 1];   // -x from x+1
+      g[i][3] = s_f[i * 5 + 3][e - EX];  // +y from y-1
+      g[i][4] = s_f[i * 5 + 4][e + EX];  // -y from y+1
+    }
+    float W[3], n[3][4], eq[3][5];
+    collide_neq<2>(g, k, W, n, eq);
+    const int64_t c = static_cast<int64_t>(y) * nx + x;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      store_stream(dr + i * stride + c, W[i]);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) store_stream(dm + (i * 4 + m) * stride + c, n[i][m] * sc.s[i]);
+    }
+  }
+}
+
+// The two-step tile in the population storages: the intermediate state of the
+// extended tile is kept in LDS in the storage types.
 template <typename TR, typename TM, int TX, int TY, int NT>
-__global__ __launch_bounds__(NT) void k_step2_2d(const TR* __restrict__ sr, const TM* __restrict__ sm,
-                                                  TR* __restrict__ dr, TM* __restrict__ dm, int nx, int ny,
-                                                  int64_t stride, Coef k) {
+__device__ __forceinline__ void step2_tile(const TR* __restrict__ sr, const TM* __restrict__ sm,
+                                           TR* __restrict__ dr, TM* __restrict__ dm, int nx, int ny,
+                                           int64_t stride, const Coef& k) {
   constexpr int EX = TX + 2, EY = TY + 2, EN = EX * EY;
   __shared__ TR s_rest[3][EN];
   __shared__ TM s_move[12][EN];
@@ -115,6 +197,16 @@ __global__ __launch_bounds__(NT) void k_step2_2d(const TR* __restrict__ sr, cons
   }
 }
 
+template <typename TR, typename TM, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_step2_2d(const TR* __restrict__ sr, const TM* __restrict__ sm,
+                                                  TR* __restrict__ dr, TM* __restrict__ dm, int nx, int ny,
+                                                  int64_t stride, Coef k, NeqScale<2> sc) {
+  if constexpr (IsNeq<TM>::value)
+    step2_neq_tile<TX, TY, NT>(sr, sm, dr, dm, nx, ny, stride, k, sc);
+  else
+    step2_tile<TR, TM, TX, TY, NT>(sr, sm, dr, dm, nx, ny, stride, k);
+}
+
 // ----------------------------------------------------------------------------
 // moments: rho = ref + sum_l g_rho,l and q_j = (sum_l g_qj,l) / dx, in FP64
 // ----------------------------------------------------------------------------
@@ -124,8 +216,10 @@ __device__ __forceinline__ void cell_sums(const TR* __restrict__ r, const TM* __
 #pragma unroll
   for (int i = 0; i < D + 1; ++i) {
     double a = load_f64(r + i * stride + c);
+    if constexpr (!IsNeq<TM>::value) {  // split storage keeps the moments themselves
 #pragma unroll
-    for (int v = 0; v < 2 * D; ++v) a += load_f64(m + (i * 2 * D + v) * stride + c);
+      for (int v = 0; v < 2 * D; ++v) a += load_f64(m + (i * 2 * D + v) * stride + c);
+    }
     s[i] = a;
   }
 }
@@ -346,7 +440,7 @@ struct Impl {
     dim3 block(bx, by, 1);
     dim3 grid((g.nx + bx - 1) / bx, (g.ny + by - 1) / by, g.nz);
     hipLaunchKernelGGL((k_step<D, TR, TM>), grid, block, 0, s, a.rest, a.move, b.rest, b.move, g.nx,
-                       g.ny, g.nz, g.stride, k);
+                       g.ny, g.nz, g.stride, k, neq_scale_of<D>(r));
     return hipGetLastError();
   }
 
@@ -354,7 +448,10 @@ struct Impl {
   // measured on MI355X at 4096^2 for 4- and 2-byte planes (FP32 81 GLUPS, FP16
   // 147 GLUPS; 64x8/512: 77/127, 64x8/256: 76/119, 128x4: 78/131,
   // 256x2: 80/123, 32x8: 64/83).
-  static constexpr int kT2X = 128, kT2Y = 8, kT2N = 512;
+  // The split storage is ALU-bound (it rebuilds the upwind equilibria) and
+  // runs the same tile on 1024 threads: 91 vs 85 GLUPS (64x8/512: 72,
+  // 128x4/512: 81, 256x4/1024: 77, 64x16/1024: 82).
+  static constexpr int kT2X = 128, kT2Y = 8, kT2N = IsNeq<TM>::value ? 1024 : 512;
   // two steps per launch in 2D, for the FP32/16-bit storages (the FP64
   // reference mode would need 156 KB of LDS for this tile and runs one step
   // per launch)
@@ -369,7 +466,7 @@ struct Impl {
       const Coef k = make_coef<float>(r, D, DEV);
       dim3 grid((g.nx + kT2X - 1) / kT2X, (g.ny + kT2Y - 1) / kT2Y, 1);
       hipLaunchKernelGGL((k_step2_2d<TR, TM, kT2X, kT2Y, kT2N>), grid, dim3(kT2N), 0, s, a.rest, a.move, b.rest,
-                         b.move, g.nx, g.ny, g.stride, k);
+                         b.move, g.nx, g.ny, g.stride, k, neq_scale_of<2>(r));
       return hipGetLastError();
     }
   }
@@ -424,6 +521,7 @@ const Ops* ops_for(int dim, int storage) {
       case LBM_F16_DEV_R32: return Impl<2, float, _Float16, true>::ops();
       case LBM_BF16_DEV_R32: return Impl<2, float, bf16, true>::ops();
       case LBM_F64: return Impl<2, double, double, true>::ops();
+      case LBM_F16_NEQ: return Impl<2, float, neq16, true>::ops();
     }
   } else if (dim == 3) {
     switch (storage) {
@@ -434,6 +532,7 @@ const Ops* ops_for(int dim, int storage) {
       case LBM_F16_DEV_R32: return Impl<3, float, _Float16, true>::ops();
       case LBM_BF16_DEV_R32: return Impl<3, float, bf16, true>::ops();
       case LBM_F64: return Impl<3, double, double, true>::ops();
+      case LBM_F16_NEQ: return Impl<3, float, neq16, true>::ops();
     }
   }
   return nullptr;
@@ -446,7 +545,8 @@ bool storage_elems(int storage, size_t* rest_elem, size_t* move_elem) {
     case LBM_F16_DEV:
     case LBM_BF16_DEV: *rest_elem = 2; *move_elem = 2; return true;
     case LBM_F16_DEV_R32:
-    case LBM_BF16_DEV_R32: *rest_elem = 4; *move_elem = 2; return true;
+    case LBM_BF16_DEV_R32:
+    case LBM_F16_NEQ: *rest_elem = 4; *move_elem = 2; return true;
     case LBM_F64: *rest_elem = 8; *move_elem = 8; return true;
   }
   return false;

@@ -85,7 +85,7 @@ def test_low_frequency_warning_flag():
 
 def test_workspace_bytes_cover_both_buffers():
     for storage, per in (("f32", 4 * 15), ("f16_dev", 2 * 15), ("f16_dev_r32", 4 * 3 + 2 * 12),
-                         ("f64", 8 * 15)):
+                         ("f64", 8 * 15), ("f16_neq", 4 * 3 + 2 * 12)):
         nb = lbm.lbm_workspace_bytes(_params(storage=storage, n=(4096, 4096)))
         assert nb >= 2 * per * 4096 * 4096
         assert nb < 2 * per * 4096 * 4096 * 1.01

@@ -59,8 +59,9 @@ def _ctx_state(n=64, steps=9, seed=3, storage="f32"):
     return p, u0, eng
 
 
-def test_set_equilibrium_device_is_the_equilibrium():
-    p, u0, eng = _ctx_state()
+@pytest.mark.parametrize("storage", ["f32", "f16_neq"])
+def test_set_equilibrium_device_is_the_equilibrium(storage):
+    p, u0, eng = _ctx_state(storage=storage)
     n = 64
     rng = np.random.default_rng(2)
     rho = 1 + 1e-3 * rng.standard_normal((n, n))
@@ -78,8 +79,9 @@ def test_set_equilibrium_device_is_the_equilibrium():
     assert np.max(np.abs(r3 - r_ref)) <= 1e-6 and np.max(np.abs(q3 - q_ref)) <= 1e-5 * np.abs(q_ref).max()
 
 
-def test_correction_and_guard_match_oracle():
-    p, u0, eng = _ctx_state()
+@pytest.mark.parametrize("storage", ["f32", "f16_neq"])
+def test_correction_and_guard_match_oracle(storage):
+    p, u0, eng = _ctx_state(storage=storage)
     n = 64
     cells = n * n
     s = torch.cuda.current_stream()

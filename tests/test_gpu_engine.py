@@ -37,9 +37,9 @@ def _rel_l2(a, b):
     return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
 
 
-def _compare(p, u0, steps, rho0=None, tol=FP32_TOL):
-    print(f"[gpu parity] dim={p.dim} shape={u0.shape[1:]} steps={steps}", flush=True)
-    eng = _engine(p, u0, rho0)
+def _compare(p, u0, steps, rho0=None, tol=FP32_TOL, storage="f32"):
+    print(f"[gpu parity] dim={p.dim} shape={u0.shape[1:]} steps={steps} storage={storage}", flush=True)
+    eng = _engine(p, u0, rho0, storage=storage)
     eng.step(steps)
     rho, q = eng.moments()
     eng.close()
@@ -111,15 +111,16 @@ def test_fp64_storage_matches_oracle_to_rounding(dim):
     assert np.max(np.abs(rho - r_ref)) <= 1e-13
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16_neq"])
 @pytest.mark.parametrize("shape", [(8, 8), (75, 75), (40, 96), (3, 130), (129, 1)])
-def test_random_field_2d_ragged(shape):
+def test_random_field_2d_ragged(shape, storage):
     """Non power-of-two and ragged grids: wrap-around and partial blocks."""
     ny, nx = shape
     dx = 2 * math.pi / max(nx, ny)
     p = scheme.Params(dim=2, dx=dx, dt=dx * dx / 8, nu=0.02)
     u = inputs.random_field_box(shape, dx, seed=3, umax=0.05 / dx)
     rho0 = 1 + 1e-3 * inputs.random_field_box(shape, dx, seed=4)[0]  # smooth density bump
-    _compare(p, u, 300, rho0)
+    _compare(p, u, 300, rho0, storage=storage)
 
 
 def test_zero_steps_is_the_equilibrium():
@@ -133,15 +134,16 @@ def test_zero_steps_is_the_equilibrium():
     assert _rel_l2(q, u0) <= 1e-6
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16_neq"])
 @pytest.mark.parametrize("shape,steps", [((16, 16, 16), 200), ((10, 12, 14), 100), ((32, 32, 32), 100)])
-def test_random_field_3d(shape, steps):
+def test_random_field_3d(shape, steps, storage):
     dx = 2 * math.pi / max(shape)
     p = scheme.Params(dim=3, dx=dx, dt=dx * dx / 8, nu=0.02)
     if len(set(shape)) == 1:
         u = inputs.random_field_3d(shape[0], seed=5, umax=0.05 / dx)
     else:
         u = inputs.random_field_box(shape, dx, seed=5, umax=0.05 / dx)
-    _compare(p, u, steps)
+    _compare(p, u, steps, storage=storage)
 
 
 def test_abc_3d():
@@ -190,18 +192,21 @@ def test_mass_momentum_conserved_and_deterministic():
     assert np.array_equal(blobs[0], blobs[1])
 
 
-def test_save_load_continuation_is_bitwise():
+@pytest.mark.parametrize("storage", ["f32", "f16_neq"])
+def test_save_load_continuation_is_bitwise(storage):
+    """A snapshot continues bit for bit in a context created from another
+    initial state (for the split storage the snapshot carries its scales)."""
     n = 40
     p = scheme.params_for_grid(2, n, 0.01)
     u0 = inputs.random_field_2d(n, 6, umax=0.05 / p.dx)
-    a = _engine(p, u0)
+    a = _engine(p, u0, storage=storage)
     a.step(60)
     blob_full = None
     mid = a.save_state()
     a.step(60)
     blob_full = a.save_state()
     a.close()
-    b = _engine(p, inputs.taylor_green(n))  # different initial state, then overwritten
+    b = _engine(p, 3.0 * inputs.taylor_green(n), storage=storage)  # other initial state (and scales)
     b.load_state(mid)
     assert b.steps == 60
     b.step(60)
@@ -291,7 +296,7 @@ def test_full_size_3d_256_sampled():
 # two steps per launch (2D): bit-identical to single-step launches            #
 # --------------------------------------------------------------------------- #
 
-@pytest.mark.parametrize("storage", ["f32", "f16_dev", "bf16_dev", "f16_dev_r32", "f32_raw"])
+@pytest.mark.parametrize("storage", ["f32", "f16_dev", "bf16_dev", "f16_dev_r32", "f32_raw", "f16_neq"])
 @pytest.mark.parametrize("shape,steps", [((64, 64), 10), ((75, 75), 11), ((9, 130), 7), ((200, 3), 8),
                                          ((1, 1), 4), ((300, 257), 5)])
 def test_two_step_fusion_is_bitwise(storage, shape, steps):

@@ -25,7 +25,7 @@ from paper_2607_24059_amd import lbm  # noqa: E402
 
 STEPS = 1000
 BARS = {"f32": 1e-5, "f16_dev_r32": 2e-3, "bf16_dev_r32": 2e-3, "f32_raw": None,
-        "f16_dev": None, "bf16_dev": None, "f64": 1e-11}
+        "f16_dev": None, "bf16_dev": None, "f64": 1e-11, "f16_neq": 1e-5}
 RESULTS = {}
 
 
@@ -83,7 +83,7 @@ def test_precision_2d_512(case2d, storage):
         assert err < 0.5
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16_dev_r32", "bf16_dev_r32", "f16_dev"])
+@pytest.mark.parametrize("storage", ["f32", "f16_dev_r32", "bf16_dev_r32", "f16_dev", "f16_neq"])
 def test_precision_3d_32(case3d, storage):
     p, u0, u_ref = case3d
     u, d = _run(p, u0, storage)
