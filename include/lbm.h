@@ -64,7 +64,8 @@ typedef enum lbm_status {
  *                     rest planes, and per set and moving velocity the
  *                     non-equilibrium part n = f* - f^eq(W) in FP16, times a
  *                     power-of-two scale per set fixed by lbm_init from the
- *                     initial state (saved with the state); the rest entry's
+ *                     parameters (sized for lattice Mach numbers up to about
+ *                     0.1; saved with the state); the rest entry's
  *                     part is minus the sum of the moving ones.  Same bytes as
  *                     LBM_F16_DEV_R32 with about FP32 accuracy, since FP16 only
  *                     rounds the small non-equilibrium parts

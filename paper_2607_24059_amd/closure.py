@@ -514,6 +514,7 @@ def evaluate(cfg: Config, net, scales, log=print, seeds=None, levels=None, plain
             r = equal_error_speedup(levels, ref["u_sol"], ref["time_ms"], out["plain"][st]["u_sol"][str(n)],
                                     out["plain"][st]["time_ms"][str(n)])
             r["speedup_same_resolution"] = ref["time_ms"][str(n)] / out["plain"][st]["time_ms"][str(n)]
+            r["error_ratio_same_resolution"] = out["plain"][st]["u_sol"][str(n)] / ref["u_sol"][str(n)]
             out["speedup_equal_error"][st][str(n)] = r
     return out
 

@@ -63,36 +63,24 @@ size_t staging_bytes(const Geometry& g) { return static_cast<size_t>(g.dim + 1) 
 
 lbm_status dev(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EDEVICE; }
 
-// Power-of-two scales of the split storage, one per set: 2^13 / M_i rounded
-// down to a power of two, M_i the largest moving equilibrium deviation
-// |alpha_i W_i| + |F_ij| / (2 mu) of the initial state (FP64, on the host).
-// Non-equilibrium parts are a small fraction of M_i, so they sit well inside
-// FP16's normal range with 8x headroom below its largest finite value.
-void neq_scales(const lbm_params* p, double mu, double aq, const double* u0, const double* rho0, int64_t cells,
-                float out[4]) {
-  const int D = p->dim;
+// Power-of-two scales of the split storage, one per set, from the run's
+// parameters alone (so that any state loaded later, by lbm_load_state or
+// lbm_set_equilibrium_device, is covered): s_i = 2^13 / M_i rounded down to a
+// power of two, M_i the largest moving equilibrium deviation
+// |alpha_i W_i| + |F_ij| / (2 mu) for a reference flow with W_q = 0.1 rho_ref
+// (lattice Mach number 0.1) and |rho - rho_ref| = 0.01 rho_ref.  Non-equilibrium
+// parts are a small fraction of M_i; they stay in FP16's normal range for
+// flows from that Mach number down to about a hundredth of it, with 8x
+// headroom below FP16's largest finite value at the reference.
+void neq_scales(const lbm_params* p, double mu, double aq, float out[4]) {
   const double c = 1.0 / (2.0 * mu);
-  double M[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t x = 0; x < cells; ++x) {
-    const double rho = rho0 ? rho0[x] : p->rho_ref;
-    const double dr = rho - p->rho_ref;
-    double W[3] = {0.0, 0.0, 0.0};
-    for (int j = 0; j < D; ++j) W[j] = p->dx * rho * u0[j * cells + x];
-    for (int j = 0; j < D; ++j) {
-      M[0] = fmax(M[0], fabs(p->alpha_rho * dr) + c * fabs(W[j]));
-      for (int i = 0; i < D; ++i) {
-        const double F = W[i] * W[j] / rho + (i == j ? dr : 0.0);
-        M[1 + i] = fmax(M[1 + i], fabs(aq * W[i]) + c * fabs(F));
-      }
-    }
-  }
+  const double w = 0.1 * p->rho_ref, dr = 0.01 * p->rho_ref;
+  const double M[2] = {p->alpha_rho * dr + c * w, aq * w + c * (w * w / p->rho_ref + dr)};
   for (int i = 0; i < 4; ++i) {
-    out[i] = 1.0f;
-    if (i <= D && M[i] > 0.0 && isfinite(M[i])) {
-      int e = 13 - static_cast<int>(ceil(log2(M[i])));
-      e = e < -100 ? -100 : (e > 100 ? 100 : e);
-      out[i] = static_cast<float>(ldexp(1.0, e));
-    }
+    const double m = M[i == 0 ? 0 : 1];
+    int e = 13 - static_cast<int>(ceil(log2(m)));
+    e = e < -100 ? -100 : (e > 100 ? 100 : e);
+    out[i] = (i <= p->dim) ? static_cast<float>(ldexp(1.0, e)) : 1.0f;
   }
 }
 
@@ -144,7 +132,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const 
   c->g = g;
   c->ops = lbm::ops_for(p->dim, p->storage);
   c->coef = RunCoef{p->dx, mu, p->alpha_rho, aq, p->omega_rho, p->omega_q, p->rho_ref};
-  if (p->storage == LBM_F16_NEQ) neq_scales(p, mu, aq, u0, rho0, g.cells, c->coef.neq_s);
+  if (p->storage == LBM_F16_NEQ) neq_scales(p, mu, aq, c->coef.neq_s);
   c->ws = static_cast<char*>(workspace);
   c->ws_bytes = ws_bytes;
   c->cur = c->ws;

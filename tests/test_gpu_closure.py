@@ -108,6 +108,29 @@ def test_correction_and_guard_match_oracle(storage):
     eng.close()
 
 
+def test_split_storage_accuracy_after_state_replacement():
+    """An LBM_F16_NEQ context created from a zero field and then set to the
+    equilibrium of a real field keeps FP32-level accuracy (its FP16 scales do
+    not depend on the initial field)."""
+    n, steps = 128, 500
+    p = scheme.params_for_grid(2, n, 1e-3)
+    u0 = inputs.random_field_2d(n, 11, umax=0.05 / p.dx)
+    m = _moments_f32(np.ones((n, n)), u0)
+    prm = lbm.make_params(2, (n, n), p.dx, p.dt, p.nu, p.omega_rho, p.omega_q, p.alpha_rho, storage="f16_neq")
+    eng = lbm.Engine.create(prm, np.zeros((2, n, n)))
+    cl.lbm_set_equilibrium_device(eng.ctx, dev(m))
+    eng.step(steps)
+    rho, q = eng.moments()
+    eng.close()
+    f = scheme.equilibrium(m[0].astype(np.float64), m[1:].astype(np.float64), p)
+    for _ in range(steps):
+        f = scheme.step(f, p)
+    r_ref, q_ref = scheme.moments(f, p)
+    err = float(np.linalg.norm((q / rho - q_ref / r_ref).ravel()) / np.linalg.norm((q_ref / r_ref).ravel()))
+    print(f"[closure] f16_neq after set_equilibrium: rel-L2(u) = {err:.3e}", flush=True)
+    assert err <= 1e-5
+
+
 @pytest.mark.parametrize("guard", [1e9, 1e-3])
 def test_fused_correction_matches_modular(guard):
     """lbm_closure_correct (moments, fused network, two-launch guard, update)
