@@ -122,9 +122,17 @@ def cpu_baseline(n: int = 4096, steps: int = 10, nu: float = 1e-3) -> dict:
     for _ in range(steps):
         f = scheme.step(f, p)
     sec = time.perf_counter() - t0
+    cpu = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), cpu)
+    except OSError:
+        pass
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     return {"value": n * n * steps / sec / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
             "sample": f"numpy FP64 oracle, {n}x{n} k^-3 field, {steps} steps after 1 warm-up step "
-                      f"({sec:.1f} s); numpy element-wise kernels run on one thread"}
+                      f"({sec:.1f} s); numpy {np.__version__} element-wise kernels run on one thread "
+                      f"of {avail} available ({cpu})"}
 
 
 def traffic_entry(per_launch_algo_bytes: float):

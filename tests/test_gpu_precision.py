@@ -3,7 +3,7 @@
 Same k^-3 field as the benchmark, sampled at 512^2 (nu = 1e-3, mu = 8,
 Mach 0.05), 1000 steps.  Bars: FP32 relative L2(u) <= 1e-5; FP16 storage
 <= 2e-3 (met by FP16 deviations with FP32 rest planes); BF16 and all-16-bit
-storages are reported.  3D: 32^3, same rules.
+storages are reported.  3D: 64^3, same rules.
 """
 
 import json
@@ -41,7 +41,7 @@ def case2d():
 
 @pytest.fixture(scope="module")
 def case3d():
-    n = 32
+    n = 64
     p = scheme.params_for_grid(3, n, 1e-3)
     u0 = inputs.random_field_3d(n, 0, umax=0.05 / p.dx)
     print(f"[precision] oracle 3D {n}^3 x {STEPS} steps", flush=True)
@@ -84,12 +84,12 @@ def test_precision_2d_512(case2d, storage):
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16_dev_r32", "bf16_dev_r32", "f16_dev", "f16_neq"])
-def test_precision_3d_32(case3d, storage):
+def test_precision_3d_64(case3d, storage):
     p, u0, u_ref = case3d
     u, d = _run(p, u0, storage)
     err = float(np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref))
-    print(f"[precision] 3D 32^3 {storage}: rel-L2(u) = {err:.3e}", flush=True)
-    _record(f"3d_32_{storage}", err)
+    print(f"[precision] 3D 64^3 {storage}: rel-L2(u) = {err:.3e}", flush=True)
+    _record(f"3d_64_{storage}", err)
     assert d["nonfinite"] == 0
     if BARS[storage] is not None:
         assert err <= BARS[storage], err
