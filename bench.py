@@ -243,6 +243,8 @@ def main():
         for storage in ("f32", "f16_dev_r32"):
             log(f"[bench] batch 512 runs {storage}")
             variants[f"batch512_{storage}"] = batch_variant(storage, 1000, probe)
+        log("[bench] batch 512 runs f32, one step per launch")
+        variants["batch512_f32_one_step_per_launch"] = batch_variant("f32", 1000, probe, fuse=1)
         result["variants"] = variants
 
     if not args.no_equal_error:
@@ -288,10 +290,11 @@ def equal_error_section(n_seeds: int) -> dict:
             "plain": ev["plain"], "closure": ev["closure"], "speedup": ev["speedup_equal_error"]})
 
 
-def batch_variant(storage: str, steps: int, probe: float, n_runs: int = 512) -> dict:
+def batch_variant(storage: str, steps: int, probe: float, n_runs: int = 512, fuse: int = 2) -> dict:
     """The batch workload: n_runs independent 2D runs, sizes 64^2..1024^2,
     nu log-uniform in [1e-4, 1e-2], k^-3 fields at Mach 0.05, all advanced
-    `steps` steps by one persistent launch per step (graph replays)."""
+    `steps` steps by persistent launches replayed from graphs: two steps per
+    launch (fuse = 2, the 2D default) or one (fuse = 1)."""
     import torch
     import inputs
     from paper_2607_24059_amd import batch as B
@@ -305,6 +308,7 @@ def batch_variant(storage: str, steps: int, probe: float, n_runs: int = 512) -> 
     b = B.Batch.create(2, storage, runs, u0s)
     del u0s
     b.autotune(None)
+    b.set_fusion(fuse)
     b.step(4)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -316,10 +320,11 @@ def batch_variant(storage: str, steps: int, probe: float, n_runs: int = 512) -> 
     ms = ev0.elapsed_time(ev1) / steps
     cells, tiles, _ = b.info()
     widths = sorted({(int(r.n[0]), b.tile_width(i)) for i, r in enumerate(runs)})
-    grid = b.grid()
+    grid, grid2 = b.grid(), b.fused_grid()
     b.close()
     out = _variant(cells, ms, BYTES_PER_LUP[(storage, 2)], probe)
-    out.update({"runs": n_runs, "cells": cells, "tiles": tiles, "steps": steps, "grid": grid,
+    out.update({"runs": n_runs, "cells": cells, "tiles": tiles, "steps": steps, "steps_per_launch": fuse,
+                "grid": grid, "fused_grid": grid2,
                 "tile_width_by_n": {str(n): w for n, w in widths}})
     return out
 

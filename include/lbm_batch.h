@@ -8,9 +8,13 @@
  * batch is ONE launch of a persistent kernel whose blocks walk a list of
  * 256-cell tiles covering every run; the tile shape of each size class
  * (64x4, 128x2 or 256x1 cells in 2D) is chosen by lbm_batch_autotune.  Steps
- * are replayed from a HIP graph.  The per-cell update is the same device code
- * as lbm_step, so a run advanced in a batch is bit-identical to the same run
- * advanced alone.
+ * are replayed from a HIP graph.  In 2D the default launch advances two steps:
+ * a second persistent kernel walks 64 x 8-cell tiles, advances each tile and
+ * its one-cell border by one step into LDS and the tile by the second step
+ * (lbm_batch_set_fusion).  The per-cell update is the same device code as
+ * lbm_step, so a run advanced in a batch is bit-identical to the same run
+ * advanced alone, with either setting.  The split FP16 (LBM_F16_NEQ) and FP64
+ * storages are not available in a batch.
  *
  * Conventions are those of lbm.h: status codes only, caller-owned device
  * workspace (never allocated by the library), caller's stream, FP64 host
@@ -51,8 +55,9 @@ lbm_status lbm_batch_init(lbm_batch** out, int32_t dim, int32_t storage, int32_t
 
 /* Choose the tile shape of every size class (runs grouped by nx rounded up to
  * a power of two), then the number of blocks of the persistent launch (4, 8,
- * 16 or 32 per compute unit, or one per tile), by timing each candidate on the
- * batch's own buffers; the state is not changed.  If cache_path is non-NULL (else the environment
+ * 16 or 32 per compute unit, or one per tile), and in 2D the number of blocks
+ * of the two-step launch (1, 2, 4 or 8 per compute unit, or one per tile), by
+ * timing each candidate on the batch's own buffers; the state is not changed.  If cache_path is non-NULL (else the environment
  * variable LBM_AUTOTUNE_CACHE, if set) previously tuned shapes for this
  * device, dimension and storage are read from that text file and new ones are
  * appended.  Rebuilds the step graph.  Synchronises. */
@@ -74,6 +79,13 @@ int32_t lbm_batch_tile_width(const lbm_batch* b, int32_t run);
 /* Blocks of the persistent step launch (a grid of at least the tile count
  * means one block per tile); chosen by lbm_batch_autotune. */
 int32_t lbm_batch_grid(const lbm_batch* b);
+
+/* Blocks of the two-step launch (0 if the batch has none, i.e. in 3D). */
+int32_t lbm_batch_fused_grid(const lbm_batch* b);
+
+/* Steps per launch: 1 (one-step kernel) or 2 (two-step kernel, 2D only, the
+ * default there); LBM_EINVAL otherwise.  Either gives the same states. */
+lbm_status lbm_batch_set_fusion(lbm_batch* b, int32_t steps_per_launch);
 
 void lbm_batch_destroy(lbm_batch* b);
 

@@ -70,7 +70,90 @@ __global__ __launch_bounds__(kTileCells) void k_batch_step(const BatchRun* __res
   }
 }
 
+// Two steps per launch (2D): fused tiles of kT2X x kT2Y cells walked by a
+// persistent grid; per tile the extended tile (one-cell border, periodic wrap
+// in its run) is advanced one step into LDS in the storage types, then the
+// tile by the second step from LDS, exactly as the single-run two-step kernel
+// does, so the result equals two single steps bit for bit.
+constexpr int kT2X = 64, kT2Y = 8, kT2N = 512;
+constexpr int kFusedGraphLaunches = 24;  // fused launches per replay of the main graph (even)
+
+template <typename TR, typename TM>
+__global__ __launch_bounds__(kT2N) void k_batch_step2(const BatchRun* __restrict__ runs,
+                                                      const BatchTile* __restrict__ tiles, int64_t ntiles,
+                                                      char* __restrict__ base, int parity) {
+  constexpr int EX = kT2X + 2, EY = kT2Y + 2, EN = EX * EY;
+  __shared__ TR s_rest[3][EN];
+  __shared__ TM s_move[12][EN];
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const BatchTile tl = tiles[t];
+    const BatchRun& r = runs[tl.run];
+    const int nx = r.nx, ny = r.ny;
+    const int64_t stride = r.stride;
+    const auto a = planes_of<TR, TM>(base + r.off[parity], static_cast<size_t>(r.rest_bytes));
+    const auto b = planes_of<TR, TM>(base + r.off[parity ^ 1], static_cast<size_t>(r.rest_bytes));
+    for (int e = threadIdx.x; e < EN; e += kT2N) {
+      const int ex = e % EX, ey = e / EX;
+      int x = tl.x0 - 1 + ex, y = tl.y0 - 1 + ey;
+      x = ((x % nx) + nx) % nx;  // the border may wrap (several times on tiny runs)
+      y = ((y % ny) + ny) % ny;
+      const int64_t c = static_cast<int64_t>(y) * nx + x;
+      float g[3][5];
+      gather_cell<2, TR, TM>(a.rest, a.move, x, y, 0, nx, ny, 1, stride, c, g);
+      collide<2>(g, r.k);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        store_f32(&s_rest[i][e], g[i][0]);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) store_f32(&s_move[i * 4 + m][e], g[i][1 + m]);
+      }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < kT2X * kT2Y; q += kT2N) {
+      const int tx = q % kT2X, ty = q / kT2X;
+      const int x = tl.x0 + tx, y = tl.y0 + ty;
+      if (x >= nx || y >= ny) continue;
+      const int e = (ty + 1) * EX + (tx + 1);
+      float g[3][5];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        g[i][0] = load_f32(&s_rest[i][e]);
+        g[i][1] = load_f32(&s_move[i * 4 + 0][e - 1]);   // +x from x-1
+        g[i][2] = load_f32(&s_move[i * 4 + 1][e + 1]);   // -x from x+1
+        g[i][3] = load_f32(&s_move[i * 4 + 2][e - EX]);  // +y from y-1
+        g[i][4] = load_f32(&s_move[i * 4 + 3][e + EX]);  // -y from y+1
+      }
+      collide<2>(g, r.k);
+      const int64_t c = static_cast<int64_t>(y) * nx + x;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        store_stream(b.rest + i * stride + c, g[i][0]);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) store_stream(b.move + (i * 4 + m) * stride + c, g[i][1 + m]);
+      }
+    }
+    __syncthreads();  // the next tile overwrites the LDS tile
+  }
+}
+
 using BatchKernel = void (*)(const BatchRun*, const BatchTile*, int64_t, char*, int);
+
+BatchKernel batch_kernel2(int dim, int storage) {
+  if (dim != 2) return nullptr;
+  switch (storage) {
+    case LBM_F32: case LBM_F32_RAW: return &k_batch_step2<float, float>;
+    case LBM_F16_DEV: return &k_batch_step2<_Float16, _Float16>;
+    case LBM_BF16_DEV: return &k_batch_step2<bf16, bf16>;
+    case LBM_F16_DEV_R32: return &k_batch_step2<float, _Float16>;
+    case LBM_BF16_DEV_R32: return &k_batch_step2<float, bf16>;
+  }
+  return nullptr;
+}
+
+// fused tiles of one 2D run
+int64_t tiles2_of(const Geometry& g) {
+  return static_cast<int64_t>((g.nx + kT2X - 1) / kT2X) * ((g.ny + kT2Y - 1) / kT2Y);
+}
 
 BatchKernel batch_kernel(int dim, int storage) {
   if (dim == 2) {
@@ -132,6 +215,13 @@ struct lbm_batch {
   BatchTile* d_tiles = nullptr;
   int64_t max_tiles = 0;
   int64_t ntiles = 0;
+  BatchTile* d_tiles2 = nullptr;  // fused (two-step) tiles, 2D only
+  int64_t ntiles2 = 0;
+  int grid2 = 0;                  // persistent grid of the fused kernel
+  int fuse = 1;                   // steps per launch: 1, or 2 (fused kernel)
+  BatchKernel kernel2 = nullptr;
+  hipGraphExec_t exec_main2[2] = {nullptr, nullptr};  // kFusedGraphLaunches fused launches from parity p
+  hipGraphExec_t exec_two[2] = {nullptr, nullptr};    // one fused launch from parity p
   int64_t total_cells = 0;
   int parity = 0;  // state buffer index holding the current step
   int grid = 0;    // persistent grid size (blocks); >= ntiles means one block per tile
@@ -168,25 +258,28 @@ int default_bx(const Geometry& g) {
 }
 
 struct Layout {
-  size_t runs_off, tiles_off, bufs_off, total;
-  int64_t max_tiles;
+  size_t runs_off, tiles_off, tiles2_off, bufs_off, total;
+  int64_t max_tiles, tiles2;
   std::vector<int64_t> off0, off1;
 };
 
 Layout layout(int dim, int storage, int nruns, const lbm_run_spec* runs) {
   Layout L;
   L.max_tiles = 0;
+  L.tiles2 = 0;
   std::vector<Geometry> geo;
   for (int r = 0; r < nruns; ++r) {
     const Geometry g = make_geometry(dim, storage, runs[r].n);
     int64_t mt = 0;
     for (int bx = 64; bx <= 256; bx *= 2) mt = std::max(mt, tiles_of(g, bx));
     L.max_tiles += mt;
+    if (dim == 2) L.tiles2 += tiles2_of(g);
     geo.push_back(g);
   }
   L.runs_off = 0;
   L.tiles_off = align256(sizeof(BatchRun) * nruns);
-  L.bufs_off = align256(L.tiles_off + sizeof(BatchTile) * L.max_tiles);
+  L.tiles2_off = align256(L.tiles_off + sizeof(BatchTile) * L.max_tiles);
+  L.bufs_off = align256(L.tiles2_off + sizeof(BatchTile) * L.tiles2);
   size_t off = L.bufs_off;
   for (int r = 0; r < nruns; ++r) {
     L.off0.push_back(static_cast<int64_t>(off));
@@ -234,34 +327,47 @@ hipError_t launch_step(lbm_batch* b, int parity, int64_t ntiles, hipStream_t s) 
   return hipGetLastError();
 }
 
-void destroy_graphs(lbm_batch* b) {
-  if (b->exec_main) hipGraphExecDestroy(b->exec_main);
-  for (auto& e : b->exec_one)
-    if (e) hipGraphExecDestroy(e);
-  b->exec_main = nullptr;
-  b->exec_one[0] = b->exec_one[1] = nullptr;
+hipError_t launch_step2(lbm_batch* b, int parity, hipStream_t s) {
+  if (b->ntiles2 == 0) return hipSuccess;
+  const unsigned grid = static_cast<unsigned>(std::min<int64_t>(b->ntiles2, b->grid2));
+  hipLaunchKernelGGL(b->kernel2, dim3(grid), dim3(kT2N), 0, s, b->d_runs, b->d_tiles2, b->ntiles2, b->ws, parity);
+  return hipGetLastError();
 }
 
-// A graph of `count` consecutive steps starting at `parity`: a chain of
-// kernel nodes (no memset or copy nodes).
-hipError_t make_graph(lbm_batch* b, int parity, int count, hipGraphExec_t* out) {
+void destroy_graphs(lbm_batch* b) {
+  auto drop = [](hipGraphExec_t& e) {
+    if (e) hipGraphExecDestroy(e);
+    e = nullptr;
+  };
+  drop(b->exec_main);
+  for (int p = 0; p < 2; ++p) {
+    drop(b->exec_one[p]);
+    drop(b->exec_main2[p]);
+    drop(b->exec_two[p]);
+  }
+}
+
+// A graph of `count` consecutive launches of `kernel` starting at `parity`
+// (each launch flips the buffer parity): a chain of kernel nodes, no memset
+// or copy nodes.
+hipError_t make_graph(lbm_batch* b, BatchKernel kernel, const BatchTile* tiles, int64_t ntiles, int grid_max,
+                      int threads, int parity, int count, hipGraphExec_t* out) {
   hipGraph_t g = nullptr;
   hipError_t e = hipGraphCreate(&g, 0);
   if (e != hipSuccess) return e;
   hipGraphNode_t prev = nullptr;
-  const unsigned grid = static_cast<unsigned>(std::min<int64_t>(std::max<int64_t>(b->ntiles, 1), b->grid));
+  const unsigned grid = static_cast<unsigned>(std::min<int64_t>(std::max<int64_t>(ntiles, 1), grid_max));
   for (int s = 0; s < count && e == hipSuccess; ++s) {
     int par = (parity + s) & 1;
     const BatchRun* runs = b->d_runs;
-    const BatchTile* tiles = b->d_tiles;
-    int64_t nt = b->ntiles;
+    int64_t nt = ntiles;
     char* base = b->ws;
     void* args[] = {&runs, &tiles, &nt, &base, &par};
     hipKernelNodeParams kp;
     memset(&kp, 0, sizeof(kp));
-    kp.func = reinterpret_cast<void*>(b->kernel);
+    kp.func = reinterpret_cast<void*>(kernel);
     kp.gridDim = dim3(grid);
-    kp.blockDim = dim3(kTileCells);
+    kp.blockDim = dim3(threads);
     kp.sharedMemBytes = 0;
     kp.kernelParams = args;
     kp.extra = nullptr;
@@ -277,9 +383,33 @@ hipError_t make_graph(lbm_batch* b, int parity, int count, hipGraphExec_t* out) 
 hipError_t rebuild(lbm_batch* b) {
   destroy_graphs(b);
   hipError_t e = upload_tiles(b, build_tiles(b, {}));
-  if (e == hipSuccess) e = make_graph(b, 0, kGraphSteps, &b->exec_main);
-  if (e == hipSuccess) e = make_graph(b, 0, 1, &b->exec_one[0]);
-  if (e == hipSuccess) e = make_graph(b, 1, 1, &b->exec_one[1]);
+  const BatchTile* t1 = b->d_tiles;
+  if (e == hipSuccess) e = make_graph(b, b->kernel, t1, b->ntiles, b->grid, kTileCells, 0, kGraphSteps, &b->exec_main);
+  for (int p = 0; p < 2 && e == hipSuccess; ++p)
+    e = make_graph(b, b->kernel, t1, b->ntiles, b->grid, kTileCells, p, 1, &b->exec_one[p]);
+  if (b->kernel2) {
+    for (int p = 0; p < 2 && e == hipSuccess; ++p) {
+      e = make_graph(b, b->kernel2, b->d_tiles2, b->ntiles2, b->grid2, kT2N, p, kFusedGraphLaunches,
+                     &b->exec_main2[p]);
+      if (e == hipSuccess) e = make_graph(b, b->kernel2, b->d_tiles2, b->ntiles2, b->grid2, kT2N, p, 1, &b->exec_two[p]);
+    }
+  }
+  return e;
+}
+
+// The fused tile list (fixed: it does not depend on the tuned tile widths).
+hipError_t upload_tiles2(lbm_batch* b) {
+  std::vector<BatchTile> t;
+  for (int r = 0; r < b->nruns; ++r) {
+    const Geometry& g = b->geo[r];
+    for (int y0 = 0; y0 < g.ny; y0 += kT2Y)
+      for (int x0 = 0; x0 < g.nx; x0 += kT2X) t.push_back(BatchTile{r, x0, y0, 0, static_cast<int16_t>(log2i(kT2X))});
+  }
+  b->ntiles2 = static_cast<int64_t>(t.size());
+  if (t.empty()) return hipSuccess;
+  hipError_t e = hipMemcpyAsync(b->d_tiles2, t.data(), t.size() * sizeof(BatchTile), hipMemcpyHostToDevice,
+                                b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   return e;
 }
 
@@ -344,9 +474,12 @@ lbm_status lbm_batch_init(lbm_batch** out, int32_t dim, int32_t storage, int32_t
   b->ws_bytes = ws_bytes;
   b->d_runs = reinterpret_cast<BatchRun*>(b->ws + L.runs_off);
   b->d_tiles = reinterpret_cast<BatchTile*>(b->ws + L.tiles_off);
+  b->d_tiles2 = reinterpret_cast<BatchTile*>(b->ws + L.tiles2_off);
   b->max_tiles = L.max_tiles;
   b->stream = static_cast<hipStream_t>(hip_stream);
   b->kernel = batch_kernel(dim, storage);
+  b->kernel2 = batch_kernel2(dim, storage);
+  b->fuse = b->kernel2 ? 2 : 1;
   const Ops* ops = ops_for(dim, storage);
   const bool devn = storage_is_deviation(storage);
 
@@ -390,7 +523,9 @@ lbm_status lbm_batch_init(lbm_batch** out, int32_t dim, int32_t storage, int32_t
       cus = 256;
     b->cus = cus;
     b->grid = 8 * cus;  // 8 resident 256-thread blocks per CU at the kernel's register use
-    e = rebuild(b);
+    b->grid2 = 2 * cus;  // two resident 512-thread fused blocks per CU (LDS tile of up to 40 KB)
+    if (b->kernel2) e = upload_tiles2(b);
+    if (e == hipSuccess) e = rebuild(b);
   }
   if (e != hipSuccess) {
     destroy_graphs(b);
@@ -412,7 +547,7 @@ lbm_status lbm_batch_autotune(lbm_batch* b, const char* cache_path) {
       char arch[128];
       int d, st, cl, bx;
       while (fscanf(f, "%127s %d %d %d %d", arch, &d, &st, &cl, &bx) == 5)
-        if (key == arch && d == b->dim && st == b->storage && (cl == -1 || bx == 64 || bx == 128 || bx == 256))
+        if (key == arch && d == b->dim && st == b->storage && (cl < 0 || bx == 64 || bx == 128 || bx == 256))
           cached[cl] = bx;
       fclose(f);
     }
@@ -483,6 +618,33 @@ lbm_status lbm_batch_autotune(lbm_batch* b, const char* cache_path) {
     b->grid = best_pc > 0 ? best_pc * b->cus : static_cast<int>(std::min<int64_t>(b->ntiles, 0x7fffffff));
     fresh.emplace_back(-1, best_pc);
   }
+  // persistent grid of the fused kernel (class -2): blocks per CU, or one block per tile (0)
+  if (e == hipSuccess && b->kernel2 && cached.count(-2)) {
+    const int per_cu = cached[-2];
+    b->grid2 = per_cu > 0 ? per_cu * b->cus : static_cast<int>(std::min<int64_t>(b->ntiles2, 0x7fffffff));
+  } else if (e == hipSuccess && b->kernel2) {
+    const int cands[] = {1, 2, 4, 8, 0};
+    float best = 1e30f;
+    int best_pc = 2;
+    for (int pc : cands) {
+      if (e != hipSuccess) break;
+      b->grid2 = pc > 0 ? pc * b->cus : static_cast<int>(std::min<int64_t>(b->ntiles2, 0x7fffffff));
+      // a fused launch reads the current buffer and writes the other: the state is kept
+      for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch_step2(b, b->parity, b->stream);
+      if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+      for (int it = 0; it < 5 && e == hipSuccess; ++it) e = launch_step2(b, b->parity, b->stream);
+      if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess && ms < best) {
+        best = ms;
+        best_pc = pc;
+      }
+    }
+    b->grid2 = best_pc > 0 ? best_pc * b->cus : static_cast<int>(std::min<int64_t>(b->ntiles2, 0x7fffffff));
+    fresh.emplace_back(-2, best_pc);
+  }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (e == hipSuccess) e = rebuild(b);
@@ -500,6 +662,27 @@ lbm_status lbm_batch_autotune(lbm_batch* b, const char* cache_path) {
 lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
   if (!b || nsteps < 0) return LBM_EINVAL;
   hipError_t e = hipSuccess;
+  if (b->fuse == 2) {
+    // fused launches advance two steps and move the state to the other buffer
+    while (nsteps > 0 && e == hipSuccess) {
+      if (nsteps >= 2 * kFusedGraphLaunches) {
+        e = hipGraphLaunch(b->exec_main2[b->parity], b->stream);  // even launch count: parity kept
+        if (e == hipSuccess) {
+          nsteps -= 2 * kFusedGraphLaunches;
+          b->steps += 2 * kFusedGraphLaunches;
+        }
+      } else {
+        const int two = nsteps >= 2;
+        e = hipGraphLaunch(two ? b->exec_two[b->parity] : b->exec_one[b->parity], b->stream);
+        if (e == hipSuccess) {
+          nsteps -= two ? 2 : 1;
+          b->steps += two ? 2 : 1;
+          b->parity ^= 1;
+        }
+      }
+    }
+    return dev(e);
+  }
   while (nsteps > 0 && e == hipSuccess) {
     if (b->parity == 0 && nsteps >= kGraphSteps) {
       e = hipGraphLaunch(b->exec_main, b->stream);
@@ -542,6 +725,15 @@ lbm_status lbm_batch_info(const lbm_batch* b, int64_t* total_cells, int64_t* til
 }
 
 int32_t lbm_batch_grid(const lbm_batch* b) { return b ? b->grid : -1; }
+
+int32_t lbm_batch_fused_grid(const lbm_batch* b) { return b ? (b->kernel2 ? b->grid2 : 0) : -1; }
+
+lbm_status lbm_batch_set_fusion(lbm_batch* b, int32_t steps_per_launch) {
+  if (!b || steps_per_launch < 1 || steps_per_launch > 2) return LBM_EINVAL;
+  if (steps_per_launch == 2 && !b->kernel2) return LBM_EINVAL;
+  b->fuse = steps_per_launch;
+  return LBM_OK;
+}
 
 int32_t lbm_batch_tile_width(const lbm_batch* b, int32_t run) {
   if (!b || run < 0 || run >= b->nruns) return -1;

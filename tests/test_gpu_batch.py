@@ -47,11 +47,17 @@ def _single(dim, storage, run, u0, steps):
     return out
 
 
+@pytest.mark.parametrize("fuse", [2, 1])
 @pytest.mark.parametrize("storage,steps", [("f32", 73), ("f16_dev_r32", 120), ("bf16_dev", 51)])
-def test_batch_bitwise_equals_single_runs_2d(storage, steps):
+def test_batch_bitwise_equals_single_runs_2d(storage, steps, fuse):
+    """Either kernel (two steps per launch, the 2D default, or one) gives each
+    run's single-run state bit for bit; 73 and 51 steps end on a one-step
+    launch, 120 on the 48-step graph plus fused launches."""
     runs, u0s = _mixed_runs(2)
-    print(f"[batch] 2D {storage} {len(runs)} runs {steps} steps", flush=True)
+    print(f"[batch] 2D {storage} {len(runs)} runs {steps} steps fuse={fuse}", flush=True)
     b = B.Batch.create(2, storage, runs, u0s)
+    assert b.fused_grid() > 0
+    b.set_fusion(fuse)
     b.step(steps)
     cells, tiles, done = b.info()
     assert done == steps
@@ -66,10 +72,30 @@ def test_batch_bitwise_equals_single_runs_2d(storage, steps):
 def test_batch_bitwise_equals_single_runs_3d():
     runs, u0s = _mixed_runs(3)
     b = B.Batch.create(3, "f32", runs, u0s)
+    assert b.fused_grid() == 0
+    with pytest.raises(lbm.LbmError):
+        b.set_fusion(2)
     b.step(37)
     for r, (run, u0) in enumerate(zip(runs, u0s)):
         rho, q = b.moments(r)
         rho1, q1 = _single(3, "f32", run, u0, 37)
+        assert np.array_equal(rho, rho1) and np.array_equal(q, q1), r
+    b.close()
+
+
+def test_switching_fusion_mid_run_is_bitwise():
+    """Alternating one- and two-step launches (buffer parity changes) keeps the
+    single-run states."""
+    runs, u0s = _mixed_runs(2)
+    b = B.Batch.create(2, "f32", runs, u0s)
+    total = 0
+    for fuse, n in ((2, 5), (1, 3), (2, 50), (1, 1), (2, 2)):
+        b.set_fusion(fuse)
+        b.step(n)
+        total += n
+    for r in (0, 2, 5, 7):
+        rho, q = b.moments(r)
+        rho1, q1 = _single(2, "f32", runs[r], u0s[r], total)
         assert np.array_equal(rho, rho1) and np.array_equal(q, q1), r
     b.close()
 
@@ -102,6 +128,7 @@ def test_autotune_keeps_state_and_caches(tmp_path):
         assert w in (64, 128, 256)
     assert os.path.exists(cache) and open(cache).read().strip()
     lines_first = open(cache).read()
+    assert b.fused_grid() > 0
     b.step(25)
     for r in (0, 3, 7):
         rho, q = b.moments(r)
