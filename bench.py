@@ -209,7 +209,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic_entry(algo),
-                     "kernel": "k_step2_2d<float,float,128,8,512> (two lattice updates per cell per launch)",
+                     "kernel": "k_step2_2d<float,float,256,8,1024> (two lattice updates per cell per launch)",
                      "bytes_per_launch_algorithmic": algo, "launch_us": round(launch_ms * 1e3, 2),
                      "note": "achieved uses 120 B per lattice update; the fused kernel keeps the "
                              "intermediate step on chip, so it moves fewer bytes than two single "

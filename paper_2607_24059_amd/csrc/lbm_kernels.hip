@@ -444,30 +444,38 @@ struct Impl {
     return hipGetLastError();
   }
 
-  // Tile of the two-step kernel: 128x8 cells on 512 threads, the fastest shape
-  // measured on MI355X at 4096^2 for 4- and 2-byte planes (FP32 81 GLUPS, FP16
-  // 147 GLUPS; 64x8/512: 77/127, 64x8/256: 76/119, 128x4: 78/131,
-  // 256x2: 80/123, 32x8: 64/83).
-  // The split storage is ALU-bound (it rebuilds the upwind equilibria) and
-  // runs the same tile on 1024 threads: 91 vs 85 GLUPS (64x8/512: 72,
-  // 128x4/512: 81, 256x4/1024: 77, 64x16/1024: 82).
-  static constexpr int kT2X = 128, kT2Y = 8, kT2N = IsNeq<TM>::value ? 1024 : 512;
-  // two steps per launch in 2D, for the FP32/16-bit storages (the FP64
-  // reference mode would need 156 KB of LDS for this tile and runs one step
-  // per launch)
+  // Tile of the two-step kernel by storage and grid size, from sweeps of this
+  // kernel on MI355X (GLUPS; 128x8 on 512 threads / 256x8 on 1024 / 128x16 on
+  // 1024 / 64x8 on 512): 4096^2 FP32 81.1 / 85.8 / 83.2 / 79.6, FP16 148.3 /
+  // 137.9 / 121.0 / 128.6, BF16 132.7 / 121.4 / 113.0 / 121.8, FP16 + FP32 rest
+  // 129.2 / 122.8 / 114.0 / 115.9; 2048^2 FP32 74.2 / 69.3 / 71.4 / 73.4.  So
+  // 256x8 tiles only for 4-byte moving planes from 2^23 cells on.  Up to 256^2
+  // cells the launch is latency-bound and 64x4 on 256 threads (256 blocks)
+  // beats 128x8 (64 blocks): 20.4 vs 19.4 GLUPS FP32 at 256^2.  The split
+  // storage is ALU-bound (it rebuilds the upwind equilibria) and runs 128x8
+  // on 1024 threads: 91 vs 85 GLUPS for 128x8/512 (64x8/512: 72, 256x4/1024: 77).
   static constexpr bool kHasStep2 = D == 2 && !std::is_same<TM, double>::value;
+
+  template <int TX, int TY, int NT>
+  static hipError_t launch2(const Geometry& g, const RunCoef& r, const void* src, void* dst, hipStream_t s) {
+    auto a = planes_of<TR, TM>(const_cast<void*>(src), g.rest_bytes);
+    auto b = planes_of<TR, TM>(dst, g.rest_bytes);
+    const Coef k = make_coef<float>(r, D, DEV);
+    dim3 grid((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY, 1);
+    hipLaunchKernelGGL((k_step2_2d<TR, TM, TX, TY, NT>), grid, dim3(NT), 0, s, a.rest, a.move, b.rest, b.move, g.nx,
+                       g.ny, g.stride, k, neq_scale_of<2>(r));
+    return hipGetLastError();
+  }
 
   static hipError_t step2(const Geometry& g, const RunCoef& r, const void* src, void* dst, hipStream_t s) {
     if constexpr (!kHasStep2) {
       return hipErrorInvalidValue;
+    } else if constexpr (IsNeq<TM>::value) {
+      return launch2<128, 8, 1024>(g, r, src, dst, s);
     } else {
-      auto a = planes_of<TR, TM>(const_cast<void*>(src), g.rest_bytes);
-      auto b = planes_of<TR, TM>(dst, g.rest_bytes);
-      const Coef k = make_coef<float>(r, D, DEV);
-      dim3 grid((g.nx + kT2X - 1) / kT2X, (g.ny + kT2Y - 1) / kT2Y, 1);
-      hipLaunchKernelGGL((k_step2_2d<TR, TM, kT2X, kT2Y, kT2N>), grid, dim3(kT2N), 0, s, a.rest, a.move, b.rest,
-                         b.move, g.nx, g.ny, g.stride, k, neq_scale_of<2>(r));
-      return hipGetLastError();
+      if (sizeof(TM) == 4 && g.cells >= (int64_t(1) << 23)) return launch2<256, 8, 1024>(g, r, src, dst, s);
+      if (g.cells <= (int64_t(1) << 16)) return launch2<64, 4, 256>(g, r, src, dst, s);
+      return launch2<128, 8, 512>(g, r, src, dst, s);
     }
   }
 

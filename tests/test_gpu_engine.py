@@ -314,6 +314,25 @@ def test_two_step_fusion_is_bitwise(storage, shape, steps):
     assert np.array_equal(blobs[0], blobs[1])
 
 
+@pytest.mark.parametrize("storage", ["f32", "f32_raw"])
+def test_two_step_fusion_bitwise_large_tile(storage):
+    """From 2^23 cells on, the two-step kernel runs 256x8 tiles on 1024
+    threads for 4-byte planes: a 2900^2 grid (ragged against both tile
+    edges), 5 steps."""
+    import hashlib
+    n = 2900
+    p = scheme.params_for_grid(2, n, 1e-3)
+    u = inputs.random_field_2d(n, 2, umax=0.05 / p.dx)
+    digests = []
+    for fuse in (1, 2):
+        eng = _engine(p, u, storage=storage)
+        eng.set_fusion(fuse)
+        eng.step(5)
+        digests.append(hashlib.sha256(eng.save_state().tobytes()).hexdigest())
+        eng.close()
+    assert digests[0] == digests[1]
+
+
 def test_two_step_fusion_not_available_in_3d():
     p = scheme.params_for_grid(3, 8, 0.01)
     eng = _engine(p, inputs.abc_flow(8, 0.1, 0.1, 0.1))
