@@ -171,6 +171,34 @@ size_t lbm_state_bytes(const lbm_ctx* ctx);
 lbm_status lbm_save_state(lbm_ctx* ctx, void* host, size_t bytes);
 lbm_status lbm_load_state(lbm_ctx* ctx, const void* host, size_t bytes);
 
+/* Channel boundaries (2D; the numerical boundary conditions of the Poiseuille
+ * test, Section 5.2) in place of the periodic ones, on the box [0, nx dx] x
+ * [0, ny dx]:
+ *   inlet  x = 0:  ghost moments rho_g = 2 rho(0) - rho(1),
+ *                  q_g = 2 rho_ref u_in(y) - q(0)           (enters: +x)
+ *   outlet x = L:  rho_g = 2 rho_out - rho(nx-1),
+ *                  q_g = 2 q(nx-1) - q(nx-2)                (enters: -x)
+ *   walls  y = 0, L: rho_g = 2 rho(wall row) - rho(next row),
+ *                  q_g = (2 rho_ref u_wall - q_x, -q_y)(wall row) (enters: +y / -y)
+ * The entering post-relaxation population of every set is the equilibrium of
+ * the ghost moments; with `correction` the walls add the non-equilibrium part
+ * f* - f^eq(W) of the same population in the wall row (second order when
+ * omega_q != 1).  Moments are those of the time level the step starts from.
+ *   walls   NULL restores periodic boundaries
+ *   u_in    host FP64 [2][ny]: inlet velocity (x, then y component), copied
+ * While the walls are set every launch advances one step (lbm_set_fusion(2)
+ * returns LBM_EINVAL); diagnostics keep their periodic centred differences.
+ * LBM_EINVAL for 3D contexts, LBM_F16_NEQ storage, nx or ny < 3, a NULL u_in
+ * or non-finite values.  Synchronises (the profile copy). */
+typedef struct lbm_walls {
+  double rho_out;      /* outlet density target, rho_ref (1 + dx^2 p_out) */
+  double u_bottom;     /* tangential velocity of the wall at y = 0 */
+  double u_top;        /* tangential velocity of the wall at y = L */
+  int32_t correction;  /* 1: non-equilibrium correction on the two walls */
+} lbm_walls;
+
+lbm_status lbm_set_walls(lbm_ctx* ctx, const lbm_walls* walls, const double* u_in);
+
 /* Steps taken so far. */
 int64_t lbm_step_count(const lbm_ctx* ctx);
 

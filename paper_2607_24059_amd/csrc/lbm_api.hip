@@ -84,6 +84,16 @@ void neq_scales(const lbm_params* p, double mu, double aq, float out[4]) {
   }
 }
 
+// diagnostics partials + final slots, then 16 doubles of closure slots
+size_t scratch_bytes(const Ops* o, const Geometry& g) {
+  return align_up((static_cast<size_t>(o->diag_blocks(g) + 1) * kDiagSlots + 16) * sizeof(double));
+}
+
+// inlet velocity profile of the channel boundaries: [2][ny] doubles (2D)
+size_t profile_bytes(const lbm_params* p) {
+  return p->dim == 2 ? align_up(2 * static_cast<size_t>(p->n[1]) * sizeof(double)) : 0;
+}
+
 void default_block(const Geometry& g, int* bx, int* by) {
   int x = 256;
   while (x > 64 && x / 2 >= g.nx) x /= 2;
@@ -104,9 +114,7 @@ size_t lbm_workspace_bytes(const lbm_params* p) {
   const Geometry g = geometry(p);
   const Ops* o = lbm::ops_for(p->dim, p->storage);
   if (!o) return 0;
-  // diagnostics partials + final slots, then 16 doubles of closure slots
-  const size_t scratch = align_up((static_cast<size_t>(o->diag_blocks(g) + 1) * kDiagSlots + 16) * sizeof(double));
-  return 2 * g.buf_bytes + scratch;
+  return 2 * g.buf_bytes + scratch_bytes(o, g) + profile_bytes(p);
 }
 
 lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const double* rho0,
@@ -141,6 +149,10 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const 
   c->diag_blocks = c->ops->diag_blocks(g);
   c->result = c->partials + c->diag_blocks * kDiagSlots;
   c->closure_slots = c->result + kDiagSlots;
+  c->walls = 0;
+  c->wall = lbm::WallArgs{};
+  c->wall_profile = p->dim == 2 ? reinterpret_cast<double*>(c->ws + 2 * g.buf_bytes + scratch_bytes(c->ops, g))
+                                : nullptr;
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->steps = 0;
   default_block(g, &c->bx, &c->by);
@@ -168,9 +180,10 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const 
 lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
   if (!c || nsteps < 0) return LBM_EINVAL;
   while (nsteps > 0) {
-    const bool two = c->fuse == 2 && nsteps >= 2;
-    hipError_t e = two ? c->ops->step2(c->g, c->coef, c->cur, c->nxt, c->stream)
-                       : c->ops->step(c->g, c->coef, c->cur, c->nxt, c->bx, c->by, c->stream);
+    const bool two = c->fuse == 2 && nsteps >= 2 && !c->walls;
+    hipError_t e = c->walls ? c->ops->step_walls(c->g, c->coef, c->cur, c->nxt, c->wall, c->bx, c->by, c->stream)
+                   : two    ? c->ops->step2(c->g, c->coef, c->cur, c->nxt, c->stream)
+                            : c->ops->step(c->g, c->coef, c->cur, c->nxt, c->bx, c->by, c->stream);
     if (e != hipSuccess) return LBM_EDEVICE;
     char* t = c->cur;
     c->cur = c->nxt;
@@ -183,8 +196,28 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
 
 lbm_status lbm_set_fusion(lbm_ctx* c, int32_t steps_per_launch) {
   if (!c || steps_per_launch < 1 || steps_per_launch > 2) return LBM_EINVAL;
-  if (steps_per_launch == 2 && !c->ops->step2) return LBM_EINVAL;
+  if (steps_per_launch == 2 && (!c->ops->step2 || c->walls)) return LBM_EINVAL;
   c->fuse = steps_per_launch;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_walls(lbm_ctx* c, const lbm_walls* w, const double* u_in) {
+  if (!c) return LBM_EINVAL;
+  if (!w) {
+    c->walls = 0;
+    return LBM_OK;
+  }
+  if (!c->ops->step_walls || !u_in || c->p.n[0] < 3 || c->p.n[1] < 3) return LBM_EINVAL;
+  if (!isfinite(w->rho_out) || !(w->rho_out > 0.0) || !isfinite(w->u_bottom) || !isfinite(w->u_top))
+    return LBM_EINVAL;
+  const size_t bytes = 2 * static_cast<size_t>(c->p.n[1]) * sizeof(double);
+  hipError_t e = hipMemcpyAsync(c->wall_profile, u_in, bytes, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // the host array may go away
+  if (e != hipSuccess) return LBM_EDEVICE;
+  c->wall = lbm::WallArgs{c->wall_profile, w->rho_out, w->u_bottom, w->u_top, c->p.dx, c->p.rho_ref,
+                          w->correction ? 1 : 0};
+  c->walls = 1;
+  c->fuse = 1;
   return LBM_OK;
 }
 

@@ -285,17 +285,17 @@ __device__ __forceinline__ float recip_neq(float x) { return __builtin_amdgcn_rc
 
 // The equilibrium (deviation) of set i, moving velocity 1 + m (axis m / 2,
 // + for even m), at a cell with moments W; the arithmetic of equilibrium<D, float>.
-template <int D>
-__device__ __forceinline__ float eq_moving(const float (&W)[D + 1], float inv, const Coef& k, int i, int m) {
+template <int D, typename R>
+__device__ __forceinline__ R eq_moving(const R (&W)[D + 1], R inv, const CoefT<R>& k, int i, int m) {
   const int j = m >> 1;
-  float base, flux;
+  R base, flux;
   if (i == 0) {
     base = k.a_rho * W[0];
     flux = k.c * W[1 + j];
   } else {
-    const float wi = W[i];
+    const R wi = W[i];
     base = k.a_q * wi;
-    float F = (wi * inv) * W[1 + j];
+    R F = (wi * inv) * W[1 + j];
     if (i - 1 == j) F = F + W[0];
     flux = k.c * F;
   }
@@ -372,6 +372,89 @@ __device__ __forceinline__ void step_cell_neq(const float* __restrict__ sr, cons
     store_stream(dr + i * stride + c, W[i]);
 #pragma unroll
     for (int m = 0; m < 2 * D; ++m) store_stream(dm + (i * 2 * D + m) * stride + c, n[i][m] * sc.s[i]);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Channel boundaries (2D, Section 5.2): inlet at x = 0 with a prescribed
+// velocity profile, outlet at x = L with a prescribed density, walls at y = 0
+// and y = L.  A population entering the domain comes from a ghost cell whose
+// moments are second-order formulas in the interior moments; its value is the
+// equilibrium of those moments (the non-equilibrium part of the first interior
+// cell is added on the walls when `corr` is set).  Every moment here is that
+// of the stored post-relaxation state, i.e. of the time level the step starts
+// from (the relaxation does not change moments).
+// ----------------------------------------------------------------------------
+struct WallArgs {
+  const double* u_in;  // [2][ny] inlet velocity (physical units), device memory
+  double rho_out;      // outlet density target
+  double u_bottom, u_top;
+  double dx, rho_bar;
+  int corr;
+};
+
+// moments (deviation form for W_rho) of the stored cell c
+template <typename TR, typename TM, typename R>
+__device__ __forceinline__ void cell_moments2(const TR* __restrict__ sr, const TM* __restrict__ sm, int64_t c,
+                                              int64_t stride, R (&W)[3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    R s = load_as<R>(sr + i * stride + c);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) s = s + load_as<R>(sm + (i * 4 + m) * stride + c);
+    W[i] = s;
+  }
+}
+
+// Replace the entering populations of boundary cell (x, y) in the gathered g.
+template <typename TR, typename TM, typename R>
+__device__ __forceinline__ void wall_ghosts(const TR* __restrict__ sr, const TM* __restrict__ sm, int x, int y,
+                                            int nx, int ny, int64_t stride, const CoefT<R>& k, const WallArgs& w,
+                                            R (&g)[3][5]) {
+  const int64_t c = static_cast<int64_t>(y) * nx + x;
+  const R two = R(2);
+  if (x == 0) {  // inlet: +x populations
+    R a[3], b[3], Wg[3];
+    cell_moments2<TR, TM, R>(sr, sm, c, stride, a);
+    cell_moments2<TR, TM, R>(sr, sm, c + 1, stride, b);
+    Wg[0] = two * a[0] - b[0];
+    Wg[1] = static_cast<R>(2.0 * w.dx * w.rho_bar * w.u_in[y]) - a[1];
+    Wg[2] = static_cast<R>(2.0 * w.dx * w.rho_bar * w.u_in[ny + y]) - a[2];
+    const R inv = R(1) / (Wg[0] + k.ref);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) g[i][1] = eq_moving<2, R>(Wg, inv, k, i, 0);
+  }
+  if (x == nx - 1) {  // outlet: -x populations
+    R a[3], b[3], Wg[3];
+    cell_moments2<TR, TM, R>(sr, sm, c, stride, a);
+    cell_moments2<TR, TM, R>(sr, sm, c - 1, stride, b);
+    Wg[0] = static_cast<R>(2.0 * (w.rho_out - static_cast<double>(k.ref))) - a[0];
+    Wg[1] = two * a[1] - b[1];
+    Wg[2] = two * a[2] - b[2];
+    const R inv = R(1) / (Wg[0] + k.ref);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) g[i][2] = eq_moving<2, R>(Wg, inv, k, i, 1);
+  }
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {  // lower wall: +y populations; upper wall: -y
+    const bool on = side == 0 ? (y == 0) : (y == ny - 1);
+    if (!on) continue;
+    const int m = side == 0 ? 2 : 3;
+    const int64_t inner = side == 0 ? c + nx : c - nx;
+    R a[3], b[3], Wg[3];
+    cell_moments2<TR, TM, R>(sr, sm, c, stride, a);
+    cell_moments2<TR, TM, R>(sr, sm, inner, stride, b);
+    Wg[0] = two * a[0] - b[0];
+    Wg[1] = static_cast<R>(2.0 * w.dx * w.rho_bar * (side == 0 ? w.u_bottom : w.u_top)) - a[1];
+    Wg[2] = -a[2];
+    const R inv = R(1) / (Wg[0] + k.ref);
+    const R inv_a = R(1) / (a[0] + k.ref);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      R v = eq_moving<2, R>(Wg, inv, k, i, m);
+      if (w.corr) v = v + (load_as<R>(sm + (i * 4 + m) * stride + c) - eq_moving<2, R>(a, inv_a, k, i, m));
+      g[i][1 + m] = v;
+    }
   }
 }
 

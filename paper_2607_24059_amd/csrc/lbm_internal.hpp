@@ -52,6 +52,9 @@ struct Ops {
   hipError_t (*diag)(const Geometry&, const RunCoef&, const void* src, double* partials,
                      double* result, hipStream_t s);
   int64_t (*diag_blocks)(const Geometry&);
+  // one step with the channel boundaries (2D population storages; nullptr otherwise)
+  hipError_t (*step_walls)(const Geometry&, const RunCoef&, const void* src, void* dst, const WallArgs& w, int bx,
+                           int by, hipStream_t s);
 };
 
 // Ops for a dimension and an lbm_storage value; nullptr if unsupported.
@@ -128,4 +131,7 @@ struct lbm_ctx {
   int64_t steps;
   int bx, by;       // step kernel block shape
   int fuse;         // time steps per launch: 1, or 2 (2D two-step kernel)
+  int walls;        // 1: channel boundaries (lbm_set_walls) instead of periodic
+  lbm::WallArgs wall;
+  double* wall_profile;  // [2][ny] inlet velocity, in the workspace (2D)
 };

@@ -71,6 +71,33 @@ __global__ __launch_bounds__(256) void k_step(const TR* __restrict__ sr,
 }
 
 // ----------------------------------------------------------------------------
+// step with the channel boundaries (2D): the step of k_step, with the
+// populations entering through the domain's sides replaced by their ghost
+// values (wall_ghosts) before the relaxation
+// ----------------------------------------------------------------------------
+template <typename TR, typename TM>
+__global__ __launch_bounds__(256) void k_step_walls(const TR* __restrict__ sr, const TM* __restrict__ sm,
+                                                    TR* __restrict__ dr, TM* __restrict__ dm, int nx, int ny,
+                                                    int64_t stride, CoefT<typename ComputeOf<TM>::type> k,
+                                                    WallArgs w) {
+  using R = typename ComputeOf<TM>::type;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (x >= nx || y >= ny) return;
+  const int64_t c = static_cast<int64_t>(y) * nx + x;
+  R g[3][5];
+  gather_cell<2, TR, TM, R>(sr, sm, x, y, 0, nx, ny, 1, stride, c, g);
+  if (x == 0 || y == 0 || x == nx - 1 || y == ny - 1) wall_ghosts<TR, TM, R>(sr, sm, x, y, nx, ny, stride, k, w, g);
+  collide<2, R>(g, k);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    store_stream(dr + i * stride + c, g[i][0]);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) store_stream(dm + (i * 4 + m) * stride + c, g[i][1 + m]);
+  }
+}
+
+// ----------------------------------------------------------------------------
 // two steps in one launch (2D): the block advances its TX x TY tile plus a
 // one-cell border by one step, keeps that intermediate state in LDS in the
 // storage type (rounded exactly as a store to HBM would be), then advances the
@@ -479,6 +506,24 @@ struct Impl {
     }
   }
 
+  static constexpr bool kHasWalls = D == 2 && !IsNeq<TM>::value;
+
+  static hipError_t step_walls(const Geometry& g, const RunCoef& r, const void* src, void* dst, const WallArgs& w,
+                               int bx, int by, hipStream_t s) {
+    if constexpr (!kHasWalls) {
+      return hipErrorInvalidValue;
+    } else {
+      auto a = planes_of<TR, TM>(const_cast<void*>(src), g.rest_bytes);
+      auto b = planes_of<TR, TM>(dst, g.rest_bytes);
+      const auto k = make_coef<typename ComputeOf<TM>::type>(r, D, DEV);
+      dim3 block(bx, by, 1);
+      dim3 grid((g.nx + bx - 1) / bx, (g.ny + by - 1) / by, 1);
+      hipLaunchKernelGGL((k_step_walls<TR, TM>), grid, block, 0, s, a.rest, a.move, b.rest, b.move, g.nx, g.ny,
+                         g.stride, k, w);
+      return hipGetLastError();
+    }
+  }
+
   static hipError_t moments(const Geometry& g, const RunCoef& r, const void* src, double* out64,
                             float* out32, hipStream_t s) {
     auto a = planes_of<TR, TM>(const_cast<void*>(src), g.rest_bytes);
@@ -512,7 +557,8 @@ struct Impl {
   }
 
   static const Ops* ops() {
-    static const Ops o = {&init, &step, kHasStep2 ? &step2 : nullptr, &moments, &diag, &diag_blocks};
+    static const Ops o = {&init, &step, kHasStep2 ? &step2 : nullptr, &moments, &diag, &diag_blocks,
+                          kHasWalls ? &step_walls : nullptr};
     return &o;
   }
 };

@@ -60,6 +60,11 @@ class lbm_diag(C.Structure):
     ]
 
 
+class lbm_walls(C.Structure):
+    _fields_ = [("rho_out", C.c_double), ("u_bottom", C.c_double), ("u_top", C.c_double),
+                ("correction", C.c_int32)]
+
+
 class LbmError(RuntimeError):
     def __init__(self, status: int, where: str):
         super().__init__(f"{where}: {lbm_strerror(status)} (status {status})")
@@ -77,6 +82,7 @@ SIGNATURES = {
                            C.c_void_p, C.c_size_t, C.c_void_p]),
     "lbm_step": (C.c_int, [C.c_void_p, C.c_int64]),
     "lbm_set_fusion": (C.c_int, [C.c_void_p, C.c_int32]),
+    "lbm_set_walls": (C.c_int, [C.c_void_p, C.POINTER(lbm_walls), C.c_void_p]),
     "lbm_moments": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "lbm_moments_device": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lbm_diagnostics": (C.c_int, [C.c_void_p, C.POINTER(lbm_diag)]),
@@ -156,6 +162,14 @@ def lbm_step(ctx: int, nsteps: int) -> None:
 
 def lbm_set_fusion(ctx: int, steps_per_launch: int) -> None:
     _ok(lib().lbm_set_fusion(C.c_void_p(ctx), int(steps_per_launch)), "lbm_set_fusion")
+
+
+def lbm_set_walls(ctx: int, walls: lbm_walls | None, u_in: np.ndarray | None) -> None:
+    if walls is None:
+        _ok(lib().lbm_set_walls(C.c_void_p(ctx), None, None), "lbm_set_walls")
+        return
+    u = np.ascontiguousarray(u_in, dtype=np.float64)
+    _ok(lib().lbm_set_walls(C.c_void_p(ctx), C.byref(walls), u.ctypes.data_as(C.c_void_p)), "lbm_set_walls")
 
 
 def lbm_moments(ctx: int, rho: np.ndarray, q: np.ndarray | None) -> None:
@@ -254,6 +268,16 @@ class Engine:
 
     def step(self, n: int) -> None:
         lbm_step(self.ctx, n)
+
+    def set_walls(self, u_in, rho_out: float, u_bottom: float = 0.0, u_top: float = 0.0,
+                  correction: bool = False) -> None:
+        """Channel boundaries (inlet velocity u_in [2][ny], outlet density, walls);
+        u_in=None restores periodic boundaries."""
+        if u_in is None:
+            lbm_set_walls(self.ctx, None, None)
+        else:
+            lbm_set_walls(self.ctx, lbm_walls(float(rho_out), float(u_bottom), float(u_top), int(bool(correction))),
+                          u_in)
 
     def set_fusion(self, steps_per_launch: int) -> None:
         lbm_set_fusion(self.ctx, steps_per_launch)
