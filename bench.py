@@ -240,6 +240,10 @@ def main():
             ms_v, e = time_engine(n3, 3, storage, vs, 10, u0=u3)
             e.close()
             variants[f"3d_{n3}_{storage}"] = _variant(n3 ** 3, ms_v, BYTES_PER_LUP[(storage, 3)], probe)
+        log("[bench] variant 2D 4096^2 channel boundaries (one step per launch)")
+        variants[f"2d_{n}_f32_channel_walls"] = walls_variant(n, vs, probe)
+        log("[bench] Poiseuille 253^2 to t = 0.05 in FP64 storage (Table 2 case)")
+        variants["poiseuille_253_f64"] = poiseuille_variant()
         for storage in ("f32", "f16_dev_r32"):
             log(f"[bench] batch 512 runs {storage}")
             variants[f"batch512_{storage}"] = batch_variant(storage, 1000, probe)
@@ -288,6 +292,60 @@ def equal_error_section(n_seeds: int) -> dict:
                         f"seeds {cfg.test_seeds[0]}..{cfg.test_seeds[-1]}",
             "error_metric": "relative L2 of the divergence-free part of u",
             "plain": ev["plain"], "closure": ev["closure"], "speedup": ev["speedup_equal_error"]})
+
+
+def walls_variant(n: int, steps: int, probe: float) -> dict:
+    """The 4096^2 FP32 workload with the channel boundaries set (inlet profile,
+    outlet density, corrected walls): one step per launch with the boundary
+    cells' ghost values computed in the step kernel."""
+    import torch
+    from paper_2607_24059_amd import lbm
+    u0, dx, dt, _ = make_workload(n, 2, 1e-3)
+    eng = lbm.Engine.create(lbm.make_params(2, (n, n), dx, dt, 1e-3), u0)
+    eng.set_walls(np.stack([np.full(n, 0.05 / dx), np.zeros(n)]), 1.0, correction=True)
+    eng.step(10)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(eng.stream)
+    eng.step(steps)
+    ev1.record(eng.stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    eng.close()
+    return _variant(n * n, ms, BYTES_PER_LUP[("f32", 2)], probe)
+
+
+def poiseuille_variant(n: int = 253) -> dict:
+    """The Poiseuille test of Table 2 (omega_q = 1.15, corrected walls) at
+    n^2 to t = 0.05 in FP64 storage: wall time and the L2 error on u_x."""
+    import torch
+    from paper_2607_24059_amd import lbm
+    dx = 1.0 / n
+    dt = dx * dx / 8.0
+    nu = 0.01
+    c = (np.arange(n) + 0.5) * dx                      # cell centres along x and along y
+    u_ex = 4 * c * (1 - c)                             # u(y) = 4 U y (L - y) / L^2, U = L = 1
+    rho0 = np.broadcast_to(1.0 + dx * dx * 8 * nu * (1 - c)[None, :], (n, n)).copy()  # 1 + dx^2 p(x)
+    u0 = np.zeros((2, n, n))
+    u0[0] = u_ex[:, None]
+    eng = lbm.Engine.create(lbm.make_params(2, (n, n), dx, dt, nu, omega_q=1.15, storage="f64"), u0, rho0)
+    eng.set_walls(np.stack([u_ex, np.zeros(n)]), 1.0, correction=True)
+    steps = int(round(0.05 / dt))
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(eng.stream)
+    eng.step(steps)
+    ev1.record(eng.stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    rho, q = eng.moments()
+    eng.close()
+    e = q[0] / rho - u_ex[:, None]
+    err = float(np.sqrt(dx * dx * np.sum(e * e)))
+    return {"MLUPS": round(n * n * steps / (ms * 1e-3) / 1e6, 1), "steps": steps, "ms": round(ms, 2),
+            "l2_error_ux": err, "table2_value": 1.368e-06}
 
 
 def batch_variant(storage: str, steps: int, probe: float, n_runs: int = 512, fuse: int = 2) -> dict:
