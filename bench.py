@@ -240,6 +240,9 @@ def main():
             ms_v, e = time_engine(n3, 3, storage, vs, 10, u0=u3)
             e.close()
             variants[f"3d_{n3}_{storage}"] = _variant(n3 ** 3, ms_v, BYTES_PER_LUP[(storage, 3)], probe)
+        for dim_m, n_m in ((2, n), (3, 256)):
+            log(f"[bench] variant {dim_m}D moment-only storage, relaxation scheme omega = 1")
+            variants[f"{dim_m}d_{n_m}_f32_moments_omega1"] = moments_variant(dim_m, n_m, vs, probe)
         log("[bench] variant 2D 4096^2 channel boundaries (one step per launch)")
         variants[f"2d_{n}_f32_channel_walls"] = walls_variant(n, vs, probe)
         log("[bench] Poiseuille 253^2 to t = 0.05 in FP64 storage (Table 2 case)")
@@ -292,6 +295,29 @@ def equal_error_section(n_seeds: int) -> dict:
                         f"seeds {cfg.test_seeds[0]}..{cfg.test_seeds[-1]}",
             "error_metric": "relative L2 of the divergence-free part of u",
             "plain": ev["plain"], "closure": ev["closure"], "speedup": ev["speedup_equal_error"]})
+
+
+def moments_variant(dim: int, n: int, steps: int, probe: float) -> dict:
+    """The relaxation scheme (omega_rho = omega_q = 1) on the same k^-3 field,
+    in moment-only storage: (1 + dim) FP32 planes, 24 B (2D) / 32 B (3D) per
+    lattice update; two steps per launch in 2D."""
+    import torch
+    from paper_2607_24059_amd import lbm
+    u0, dx, dt, _ = make_workload(n, dim, 1e-3)
+    prm = lbm.make_params(dim, (n,) * dim, dx, dt, 1e-3, omega_rho=1.0, omega_q=1.0, alpha_rho=0.05,
+                          storage="f32_moments")   # (omega_rho, alpha_rho) = (1, 1/20) of Section 5.1
+    eng = lbm.Engine.create(prm, u0)
+    eng.step(10)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(eng.stream)
+    eng.step(steps)
+    ev1.record(eng.stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    eng.close()
+    return _variant(n ** dim, ms, 4 * 2 * (dim + 1), probe)
 
 
 def walls_variant(n: int, steps: int, probe: float) -> dict:

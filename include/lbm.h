@@ -69,6 +69,13 @@ typedef enum lbm_status {
  *                     part is minus the sum of the moving ones.  Same bytes as
  *                     LBM_F16_DEV_R32 with about FP32 accuracy, since FP16 only
  *                     rounds the small non-equilibrium parts
+ *   LBM_F32_MOMENTS   the relaxation scheme omega_rho = omega_q = 1 only
+ *                     (LBM_EINVAL otherwise): every post-relaxation population
+ *                     is then the equilibrium of its cell's moments, so the
+ *                     state is the moments W alone (D+1 FP32 planes, W_rho as a
+ *                     deviation) and a step is the stencil W(t+1, x) =
+ *                     sum_l f^eq_l(W(t, x - c_l)); 24 B per update in 2D, no
+ *                     channel boundaries, not in lbm_batch
  *   LBM_F64           g in FP64 with FP64 arithmetic: the reference mode for
  *                     long fine-grid runs, where FP32 rounding accumulates over
  *                     many steps; one step per launch (lbm_set_fusion(2)
@@ -81,7 +88,8 @@ typedef enum lbm_storage {
   LBM_BF16_DEV_R32 = 4,
   LBM_F32_RAW = 5,
   LBM_F64 = 6,
-  LBM_F16_NEQ = 7
+  LBM_F16_NEQ = 7,
+  LBM_F32_MOMENTS = 8
 } lbm_storage;
 
 /* Flag bits reported in lbm_diag.flags and by lbm_check_params(). */

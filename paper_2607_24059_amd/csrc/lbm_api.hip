@@ -43,6 +43,8 @@ lbm_status check(const lbm_params* p, double* mu, double* alpha_q, uint32_t* fla
   // of the checkerboard mode only for omega in [0, 2] and alpha in [0, 1/(2 dim)].
   if (!(p->omega_rho > 0.0 && p->omega_rho < 2.0)) return LBM_EUNSTABLE;
   if (!(p->omega_q > 0.0 && p->omega_q < 2.0)) return LBM_EUNSTABLE;
+  // moment-only storage represents the relaxation scheme (omega = 1) only
+  if (p->storage == LBM_F32_MOMENTS && (p->omega_rho != 1.0 || p->omega_q != 1.0)) return LBM_EINVAL;
   const double m = p->dx * p->dx / p->dt;
   const double aq = p->nu / (2.0 * m * (1.0 / p->omega_q - 0.5));
   const double amax = 1.0 / (2.0 * p->dim);
@@ -60,6 +62,13 @@ Geometry geometry(const lbm_params* p) { return lbm::make_geometry(p->dim, p->st
 
 // staging (FP64 moments or initial fields) lives in the idle buffer
 size_t staging_bytes(const Geometry& g) { return static_cast<size_t>(g.dim + 1) * g.cells * sizeof(double); }
+
+// Storages whose state buffer is smaller than the FP64 staging (the
+// moment-only storage: 12 B per cell in 2D against 24) get a staging region
+// of their own after the other regions; the others stage in the idle buffer.
+size_t extra_staging_bytes(const Geometry& g) {
+  return staging_bytes(g) > g.buf_bytes ? align_up(staging_bytes(g)) : 0;
+}
 
 lbm_status dev(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EDEVICE; }
 
@@ -94,6 +103,13 @@ size_t profile_bytes(const lbm_params* p) {
   return p->dim == 2 ? align_up(2 * static_cast<size_t>(p->n[1]) * sizeof(double)) : 0;
 }
 
+// FP64 staging for initial fields and moments: the idle state buffer, or the
+// region of its own (extra_staging_bytes) at the end of the workspace.
+char* staging(lbm_ctx* c) {
+  if (staging_bytes(c->g) <= c->g.buf_bytes) return c->nxt;
+  return c->ws + 2 * c->g.buf_bytes + scratch_bytes(c->ops, c->g) + profile_bytes(&c->p);
+}
+
 void default_block(const Geometry& g, int* bx, int* by) {
   int x = 256;
   while (x > 64 && x / 2 >= g.nx) x /= 2;
@@ -114,7 +130,7 @@ size_t lbm_workspace_bytes(const lbm_params* p) {
   const Geometry g = geometry(p);
   const Ops* o = lbm::ops_for(p->dim, p->storage);
   if (!o) return 0;
-  return 2 * g.buf_bytes + scratch_bytes(o, g) + profile_bytes(p);
+  return 2 * g.buf_bytes + scratch_bytes(o, g) + profile_bytes(p) + extra_staging_bytes(g);
 }
 
 lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const double* rho0,
@@ -129,7 +145,6 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const 
   if (ws_bytes < need) return LBM_ENOMEM;
   if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0) return LBM_EINVAL;
   const Geometry g = geometry(p);
-  if (staging_bytes(g) > g.buf_bytes) return LBM_ENOMEM;
 
   lbm_ctx* c = new (std::nothrow) lbm_ctx;
   if (!c) return LBM_ENOMEM;
@@ -159,7 +174,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const 
   c->fuse = c->ops->step2 ? 2 : 1;
 
   // stage u0 (and rho0) as FP64 in the idle buffer, then build the equilibrium
-  double* su = reinterpret_cast<double*>(c->nxt);
+  double* su = reinterpret_cast<double*>(staging(c));
   double* sr = rho0 ? su + static_cast<size_t>(g.dim) * g.cells : nullptr;
   hipError_t e = hipMemcpyAsync(su, u0, static_cast<size_t>(g.dim) * g.cells * sizeof(double),
                                 hipMemcpyHostToDevice, c->stream);
@@ -223,7 +238,7 @@ lbm_status lbm_set_walls(lbm_ctx* c, const lbm_walls* w, const double* u_in) {
 
 lbm_status lbm_moments(lbm_ctx* c, double* rho, double* q) {
   if (!c || !rho) return LBM_EINVAL;
-  double* st = reinterpret_cast<double*>(c->nxt);
+  double* st = reinterpret_cast<double*>(staging(c));
   const size_t plane = static_cast<size_t>(c->g.cells) * sizeof(double);
   hipError_t e = c->ops->moments(c->g, c->coef, c->cur, st, nullptr, c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(rho, st, plane, hipMemcpyDeviceToHost, c->stream);

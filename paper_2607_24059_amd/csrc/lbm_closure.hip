@@ -87,22 +87,24 @@ __global__ __launch_bounds__(256) void k_set_eq(const float* __restrict__ m, int
   W[0] = rho - k.ref;
 #pragma unroll
   for (int j = 0; j < D; ++j) W[1 + j] = dx * static_cast<double>(m[(1 + j) * cells + c]);
-  if constexpr (IsNeq<TM>::value) {  // split storage: the moments, no non-equilibrium part
+  if constexpr (StoresMoments<TM>::value) {  // the moments, no non-equilibrium part
 #pragma unroll
     for (int i = 0; i < D + 1; ++i) {
       store_real(rest + i * stride + c, W[i]);
+      if constexpr (IsNeq<TM>::value) {
 #pragma unroll
-      for (int v = 0; v < 2 * D; ++v) store_f32(move + (i * 2 * D + v) * stride + c, 0.0f);
+        for (int v = 0; v < 2 * D; ++v) store_f32(move + (i * 2 * D + v) * stride + c, 0.0f);
+      }
     }
-    return;
-  }
-  double eq[D + 1][2 * D + 1];
-  equilibrium<D, double>(W, 1.0 / rho, k, eq);
+  } else {
+    double eq[D + 1][2 * D + 1];
+    equilibrium<D, double>(W, 1.0 / rho, k, eq);
 #pragma unroll
-  for (int i = 0; i < D + 1; ++i) {
-    store_real(rest + i * stride + c, eq[i][0]);
+    for (int i = 0; i < D + 1; ++i) {
+      store_real(rest + i * stride + c, eq[i][0]);
 #pragma unroll
-    for (int v = 0; v < 2 * D; ++v) store_real(move + (i * 2 * D + v) * stride + c, eq[i][1 + v]);
+      for (int v = 0; v < 2 * D; ++v) store_real(move + (i * 2 * D + v) * stride + c, eq[i][1 + v]);
+    }
   }
 }
 
@@ -214,42 +216,42 @@ __global__ __launch_bounds__(256) void k_cl_apply2(const float* __restrict__ y, 
   if (!ok) return;
   const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (c >= cells) return;
-  if constexpr (IsNeq<TM>::value) {
-    // split storage: f + f^eq(W + dW) - f^eq(W) has moments W + dW and the same
-    // non-equilibrium part, so only the moment planes change
+  if constexpr (StoresMoments<TM>::value) {
+    // split and moment-only storage: f + f^eq(W + dW) - f^eq(W) has moments
+    // W + dW and the same non-equilibrium part, so only the moment planes change
     store_real(rest + c, load_f64(rest + c) + (static_cast<double>(y[c]) * s_drho - slots[kSlotMean]));
 #pragma unroll
     for (int j = 0; j < D; ++j) {
       float* pr = rest + (1 + j) * stride + c;
       store_real(pr, load_f64(pr) + dx * (static_cast<double>(y[(1 + j) * cells + c]) * s_dq - slots[kSlotMean + 1 + j]));
     }
-    return;
-  }
-  double W[D + 1];
+  } else {
+    double W[D + 1];
 #pragma unroll
-  for (int i = 0; i < D + 1; ++i) {
-    double a = load_f64(rest + i * stride + c);
+    for (int i = 0; i < D + 1; ++i) {
+      double a = load_f64(rest + i * stride + c);
 #pragma unroll
-    for (int v = 0; v < 2 * D; ++v) a += load_f64(move + (i * 2 * D + v) * stride + c);
-    W[i] = a;
-  }
-  W[0] += ref;  // full density; k.ref = 0 so both equilibria below are the plain ones
-  double W1[D + 1];
-  W1[0] = W[0] + (static_cast<double>(y[c]) * s_drho - slots[kSlotMean]);
+      for (int v = 0; v < 2 * D; ++v) a += load_f64(move + (i * 2 * D + v) * stride + c);
+      W[i] = a;
+    }
+    W[0] += ref;  // full density; k.ref = 0 so both equilibria below are the plain ones
+    double W1[D + 1];
+    W1[0] = W[0] + (static_cast<double>(y[c]) * s_drho - slots[kSlotMean]);
 #pragma unroll
-  for (int j = 0; j < D; ++j)
-    W1[1 + j] = W[1 + j] + dx * (static_cast<double>(y[(1 + j) * cells + c]) * s_dq - slots[kSlotMean + 1 + j]);
-  double e0[D + 1][2 * D + 1], e1[D + 1][2 * D + 1];
-  equilibrium<D, double>(W, 1.0 / W[0], k, e0);
-  equilibrium<D, double>(W1, 1.0 / W1[0], k, e1);
+    for (int j = 0; j < D; ++j)
+      W1[1 + j] = W[1 + j] + dx * (static_cast<double>(y[(1 + j) * cells + c]) * s_dq - slots[kSlotMean + 1 + j]);
+    double e0[D + 1][2 * D + 1], e1[D + 1][2 * D + 1];
+    equilibrium<D, double>(W, 1.0 / W[0], k, e0);
+    equilibrium<D, double>(W1, 1.0 / W1[0], k, e1);
 #pragma unroll
-  for (int i = 0; i < D + 1; ++i) {
-    TR* pr = rest + i * stride + c;
-    store_real(pr, load_f64(pr) + (e1[i][0] - e0[i][0]));
+    for (int i = 0; i < D + 1; ++i) {
+      TR* pr = rest + i * stride + c;
+      store_real(pr, load_f64(pr) + (e1[i][0] - e0[i][0]));
 #pragma unroll
-    for (int v = 0; v < 2 * D; ++v) {
-      TM* pm = move + (i * 2 * D + v) * stride + c;
-      store_real(pm, load_f64(pm) + (e1[i][1 + v] - e0[i][1 + v]));
+      for (int v = 0; v < 2 * D; ++v) {
+        TM* pm = move + (i * 2 * D + v) * stride + c;
+        store_real(pm, load_f64(pm) + (e1[i][1 + v] - e0[i][1 + v]));
+      }
     }
   }
 }
@@ -285,6 +287,7 @@ hipError_t dispatch_set_eq(lbm_ctx* c, const float* m) {
     case LBM_BF16_DEV_R32: return ClosureImpl<D, float, bf16, true>::set_eq(c, m);
     case LBM_F64: return ClosureImpl<D, double, double, true>::set_eq(c, m);
     case LBM_F16_NEQ: return ClosureImpl<D, float, neq16, true>::set_eq(c, m);
+    case LBM_F32_MOMENTS: return ClosureImpl<D, float, mom0, true>::set_eq(c, m);
   }
   return hipErrorInvalidValue;
 }
@@ -300,6 +303,7 @@ hipError_t dispatch_apply(lbm_ctx* c, const float* y, float s_drho, float s_dq, 
     case LBM_BF16_DEV_R32: return ClosureImpl<2, float, bf16, true>::apply(c, y, s_drho, s_dq, slots, div_part, n, factor);
     case LBM_F64: return ClosureImpl<2, double, double, true>::apply(c, y, s_drho, s_dq, slots, div_part, n, factor);
     case LBM_F16_NEQ: return ClosureImpl<2, float, neq16, true>::apply(c, y, s_drho, s_dq, slots, div_part, n, factor);
+    case LBM_F32_MOMENTS: return ClosureImpl<2, float, mom0, true>::apply(c, y, s_drho, s_dq, slots, div_part, n, factor);
   }
   return hipErrorInvalidValue;
 }

@@ -70,6 +70,23 @@ struct IsNeq<neq16> {
   static constexpr bool value = true;
 };
 
+// Moment-only storage (LBM_F32_MOMENTS, the relaxation scheme omega = 1 on
+// every set): no moving planes at all; a tag type for the missing planes.
+struct mom0 {};
+template <typename TM>
+struct IsMom {
+  static constexpr bool value = false;
+};
+template <>
+struct IsMom<mom0> {
+  static constexpr bool value = true;
+};
+// Storages whose rest planes hold the moments W themselves.
+template <typename TM>
+struct StoresMoments {
+  static constexpr bool value = IsNeq<TM>::value || IsMom<TM>::value;
+};
+
 // FP64 storage (the reference mode): loaded, updated and stored in FP64.
 __device__ __forceinline__ double load_f64(const double* p) { return *p; }
 template <typename T>
@@ -373,6 +390,47 @@ __device__ __forceinline__ void step_cell_neq(const float* __restrict__ sr, cons
 #pragma unroll
     for (int m = 0; m < 2 * D; ++m) store_stream(dm + (i * 2 * D + m) * stride + c, n[i][m] * sc.s[i]);
   }
+}
+
+// ----------------------------------------------------------------------------
+// Moment-only storage: with omega = 1 on every set the post-relaxation
+// populations are the equilibria of the cell's moments, so the state is W
+// alone and a step is the stencil
+//   W_i(t+1, x) = f^eq_{i,rest}(W(t, x)) + sum_moving f^eq_{i,l}(W(t, x - c_l))
+// (the relaxation scheme of Section 2; in deviation form, since the reference
+// equilibria of one set sum to the same constant in every cell).  The
+// arithmetic is that of the equilibrium routine, one moving entry at a time.
+// ----------------------------------------------------------------------------
+template <int D, typename WAt>
+__device__ __forceinline__ void step_moments(WAt w_at, const Coef& k, float (&out)[D + 1]) {
+  float W[D + 1];
+#pragma unroll
+  for (int i = 0; i < D + 1; ++i) {
+    W[i] = w_at(i, -1);
+    out[i] = W[i] - ((i == 0) ? k.d2a_rho : k.d2a_q) * W[i];
+  }
+#pragma unroll
+  for (int m = 0; m < 2 * D; ++m) {
+    float Wn[D + 1];
+#pragma unroll
+    for (int i = 0; i < D + 1; ++i) Wn[i] = w_at(i, m);
+    const float inv = 1.0f / (Wn[0] + k.ref);
+#pragma unroll
+    for (int i = 0; i < D + 1; ++i) out[i] = out[i] + eq_moving<D, float>(Wn, inv, k, i, m);
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void step_cell_mom(const float* __restrict__ sr, float* __restrict__ dr, int x, int y,
+                                              int z, int nx, int ny, int nz, int64_t stride, const Coef& k) {
+  const int64_t plane = static_cast<int64_t>(nx) * ny;
+  const int64_t c = static_cast<int64_t>(z) * plane + static_cast<int64_t>(y) * nx + x;
+  int64_t src[2 * D];
+  upwind_sources<D>(x, y, z, nx, ny, nz, c, src);
+  float out[D + 1];
+  step_moments<D>([&](int i, int nb) { return sr[i * stride + (nb < 0 ? c : src[nb])]; }, k, out);
+#pragma unroll
+  for (int i = 0; i < D + 1; ++i) store_stream(dr + i * stride + c, out[i]);
 }
 
 // ----------------------------------------------------------------------------

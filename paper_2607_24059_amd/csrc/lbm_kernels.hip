@@ -32,22 +32,24 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ u0,
   W[0] = rho - k.ref;  // deviation when k.ref = rho_ref, plain when 0
 #pragma unroll
   for (int j = 0; j < D; ++j) W[1 + j] = dx * rho * u0[j * cells + c];
-  if constexpr (IsNeq<TM>::value) {  // split storage: the moments, no non-equilibrium part
+  if constexpr (StoresMoments<TM>::value) {  // the moments, no non-equilibrium part
 #pragma unroll
     for (int i = 0; i < D + 1; ++i) {
       store_real(rest + i * stride + c, W[i]);
+      if constexpr (IsNeq<TM>::value) {
 #pragma unroll
-      for (int m = 0; m < 2 * D; ++m) store_f32(move + (i * 2 * D + m) * stride + c, 0.0f);
+        for (int m = 0; m < 2 * D; ++m) store_f32(move + (i * 2 * D + m) * stride + c, 0.0f);
+      }
     }
-    return;
-  }
-  double eq[D + 1][2 * D + 1];
-  equilibrium<D, double>(W, 1.0 / rho, k, eq);
+  } else {
+    double eq[D + 1][2 * D + 1];
+    equilibrium<D, double>(W, 1.0 / rho, k, eq);
 #pragma unroll
-  for (int i = 0; i < D + 1; ++i) {
-    store_real(rest + i * stride + c, eq[i][0]);
+    for (int i = 0; i < D + 1; ++i) {
+      store_real(rest + i * stride + c, eq[i][0]);
 #pragma unroll
-    for (int m = 0; m < 2 * D; ++m) store_real(move + (i * 2 * D + m) * stride + c, eq[i][1 + m]);
+      for (int m = 0; m < 2 * D; ++m) store_real(move + (i * 2 * D + m) * stride + c, eq[i][1 + m]);
+    }
   }
 }
 
@@ -66,6 +68,8 @@ __global__ __launch_bounds__(256) void k_step(const TR* __restrict__ sr,
   if (x >= nx || y >= ny) return;
   if constexpr (IsNeq<TM>::value)
     step_cell_neq<D>(sr, sm, dr, dm, x, y, z, nx, ny, nz, stride, k, sc);
+  else if constexpr (IsMom<TM>::value)
+    step_cell_mom<D>(sr, dr, x, y, z, nx, ny, nz, stride, k);
   else
     step_cell<D, TR, TM>(sr, sm, dr, dm, x, y, z, nx, ny, nz, stride, k);
 }
@@ -172,6 +176,42 @@ __device__ __forceinline__ void step2_neq_tile(const float* __restrict__ sr, con
   }
 }
 
+// The two-step tile in moment-only storage: the intermediate moments of the
+// extended tile (12 bytes per cell) in LDS.
+template <int TX, int TY, int NT>
+__device__ __forceinline__ void step2_mom_tile(const float* __restrict__ sr, float* __restrict__ dr, int nx, int ny,
+                                               int64_t stride, const Coef& k) {
+  constexpr int EX = TX + 2, EY = TY + 2, EN = EX * EY;
+  __shared__ float s_w[3][EN];
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  for (int e = threadIdx.x; e < EN; e += NT) {
+    const int ex = e % EX, ey = e / EX;
+    int x = x0 - 1 + ex, y = y0 - 1 + ey;
+    x = ((x % nx) + nx) % nx;  // the border may wrap (several times on tiny grids)
+    y = ((y % ny) + ny) % ny;
+    const int64_t c = static_cast<int64_t>(y) * nx + x;
+    int64_t src[4];
+    upwind_sources<2>(x, y, 0, nx, ny, 1, c, src);
+    float out[3];
+    step_moments<2>([&](int i, int nb) { return sr[i * stride + (nb < 0 ? c : src[nb])]; }, k, out);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) s_w[i][e] = out[i];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < TX * TY; t += NT) {
+    const int tx = t % TX, ty = t / TX;
+    const int x = x0 + tx, y = y0 + ty;
+    if (x >= nx || y >= ny) continue;
+    const int e = (ty + 1) * EX + (tx + 1);
+    const int off[4] = {-1, 1, -EX, EX};  // upwind neighbour of velocity +x, -x, +y, -y
+    float out[3];
+    step_moments<2>([&](int i, int nb) { return s_w[i][nb < 0 ? e : e + off[nb]]; }, k, out);
+    const int64_t c = static_cast<int64_t>(y) * nx + x;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) store_stream(dr + i * stride + c, out[i]);
+  }
+}
+
 // The two-step tile in the population storages: the intermediate state of the
 // extended tile is kept in LDS in the storage types.
 template <typename TR, typename TM, int TX, int TY, int NT>
@@ -230,6 +270,8 @@ __global__ __launch_bounds__(NT) void k_step2_2d(const TR* __restrict__ sr, cons
                                                   int64_t stride, Coef k, NeqScale<2> sc) {
   if constexpr (IsNeq<TM>::value)
     step2_neq_tile<TX, TY, NT>(sr, sm, dr, dm, nx, ny, stride, k, sc);
+  else if constexpr (IsMom<TM>::value)
+    step2_mom_tile<TX, TY, NT>(sr, dr, nx, ny, stride, k);
   else
     step2_tile<TR, TM, TX, TY, NT>(sr, sm, dr, dm, nx, ny, stride, k);
 }
@@ -243,7 +285,7 @@ __device__ __forceinline__ void cell_sums(const TR* __restrict__ r, const TM* __
 #pragma unroll
   for (int i = 0; i < D + 1; ++i) {
     double a = load_f64(r + i * stride + c);
-    if constexpr (!IsNeq<TM>::value) {  // split storage keeps the moments themselves
+    if constexpr (!StoresMoments<TM>::value) {  // these storages keep the moments themselves
 #pragma unroll
       for (int v = 0; v < 2 * D; ++v) a += load_f64(m + (i * 2 * D + v) * stride + c);
     }
@@ -499,6 +541,8 @@ struct Impl {
       return hipErrorInvalidValue;
     } else if constexpr (IsNeq<TM>::value) {
       return launch2<128, 8, 1024>(g, r, src, dst, s);
+    } else if constexpr (IsMom<TM>::value) {
+      return launch2<256, 8, 1024>(g, r, src, dst, s);
     } else {
       if (sizeof(TM) == 4 && g.cells >= (int64_t(1) << 23)) return launch2<256, 8, 1024>(g, r, src, dst, s);
       if (g.cells <= (int64_t(1) << 16)) return launch2<64, 4, 256>(g, r, src, dst, s);
@@ -506,7 +550,7 @@ struct Impl {
     }
   }
 
-  static constexpr bool kHasWalls = D == 2 && !IsNeq<TM>::value;
+  static constexpr bool kHasWalls = D == 2 && !StoresMoments<TM>::value;
 
   static hipError_t step_walls(const Geometry& g, const RunCoef& r, const void* src, void* dst, const WallArgs& w,
                                int bx, int by, hipStream_t s) {
@@ -576,6 +620,7 @@ const Ops* ops_for(int dim, int storage) {
       case LBM_BF16_DEV_R32: return Impl<2, float, bf16, true>::ops();
       case LBM_F64: return Impl<2, double, double, true>::ops();
       case LBM_F16_NEQ: return Impl<2, float, neq16, true>::ops();
+      case LBM_F32_MOMENTS: return Impl<2, float, mom0, true>::ops();
     }
   } else if (dim == 3) {
     switch (storage) {
@@ -587,6 +632,7 @@ const Ops* ops_for(int dim, int storage) {
       case LBM_BF16_DEV_R32: return Impl<3, float, bf16, true>::ops();
       case LBM_F64: return Impl<3, double, double, true>::ops();
       case LBM_F16_NEQ: return Impl<3, float, neq16, true>::ops();
+      case LBM_F32_MOMENTS: return Impl<3, float, mom0, true>::ops();
     }
   }
   return nullptr;
@@ -602,6 +648,7 @@ bool storage_elems(int storage, size_t* rest_elem, size_t* move_elem) {
     case LBM_BF16_DEV_R32:
     case LBM_F16_NEQ: *rest_elem = 4; *move_elem = 2; return true;
     case LBM_F64: *rest_elem = 8; *move_elem = 8; return true;
+    case LBM_F32_MOMENTS: *rest_elem = 4; *move_elem = 0; return true;
   }
   return false;
 }

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_EUNSTABLE, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE, LBM_ESTATE = range(7)
 STORAGE = {"f32": 0, "f16_dev": 1, "bf16_dev": 2, "f16_dev_r32": 3, "bf16_dev_r32": 4,
-           "f32_raw": 5, "f64": 6, "f16_neq": 7}
+           "f32_raw": 5, "f64": 6, "f16_neq": 7, "f32_moments": 8}
 LBM_WARN_LOWFREQ = 0x1
 
 

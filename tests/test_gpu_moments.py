@@ -1,0 +1,97 @@
+"""Moment-only storage (LBM_F32_MOMENTS): the relaxation scheme omega = 1 on
+every set, advanced as a stencil on the moments alone.
+
+Parity: against the FP64 oracle of the full scheme (15 / 28 populations) run
+with omega_rho = omega_q = 1, where every post-relaxation population is its
+cell's equilibrium, so both compute the same W(t) up to rounding (relative L2
+of u <= 1e-5 after 1000 steps in 2D); the two-step kernel is bit-identical to
+two single steps; and the population storage (LBM_F32) at omega = 1 agrees to
+FP32 rounding.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import inputs
+from oracle import scheme
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2607_24059_amd import lbm  # noqa: E402
+
+
+def _params(dim, n, nu):
+    dx = 2 * math.pi / n
+    return scheme.Params(dim=dim, dx=dx, dt=dx * dx / 8, nu=nu, omega_rho=1.0, omega_q=1.0)
+
+
+def _engine(p, u0, storage="f32_moments", rho0=None):
+    n = tuple(reversed(u0.shape[1:]))
+    prm = lbm.make_params(p.dim, n, p.dx, p.dt, p.nu, p.omega_rho, p.omega_q, p.alpha_rho, storage=storage)
+    return lbm.Engine.create(prm, u0, rho0)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+@pytest.mark.parametrize("dim,n,steps", [(2, 256, 1000), (2, 75, 300), (3, 24, 200)])
+def test_moments_match_full_oracle_at_omega_one(dim, n, steps):
+    p = _params(dim, n, 1e-3 if dim == 2 else 1e-2)
+    u0 = inputs.random_field_2d(n, 3, umax=0.05 / p.dx) if dim == 2 else inputs.random_field_3d(n, 3, umax=0.05 / p.dx)
+    shape = u0.shape[1:]
+    rho0 = 1 + 1e-3 * np.cos(np.arange(shape[-1]) * p.dx)[None] * np.ones(shape)
+    print(f"[moments] dim={dim} n={n} steps={steps}", flush=True)
+    eng = _engine(p, u0, rho0=rho0)
+    eng.step(steps)
+    rho, q = eng.moments()
+    eng.close()
+    r_ref, q_ref, _ = scheme.simulate(u0, p, steps, rho0)
+    err = _rel(q / rho, q_ref / r_ref)
+    print(f"[moments] rel-L2(u) = {err:.3e}", flush=True)
+    assert err <= 1e-5
+    assert np.max(np.abs(rho - r_ref)) <= 1e-6
+
+
+@pytest.mark.parametrize("shape,steps", [((64, 64), 10), ((75, 75), 11), ((9, 130), 7), ((1, 1), 4), ((300, 600), 5)])
+def test_moments_two_step_fusion_is_bitwise(shape, steps):
+    ny, nx = shape
+    dx = 2 * math.pi / max(shape)
+    p = scheme.Params(dim=2, dx=dx, dt=dx * dx / 8, nu=0.02, omega_rho=1.0, omega_q=1.0)
+    u = inputs.random_field_box(shape, dx, seed=12, umax=0.05 / dx)
+    blobs = []
+    for fuse in (1, 2):
+        eng = _engine(p, u)
+        eng.set_fusion(fuse)
+        eng.step(steps)
+        blobs.append(eng.save_state())
+        eng.close()
+    assert np.array_equal(blobs[0], blobs[1])
+
+
+def test_population_storage_agrees_at_omega_one():
+    n = 128
+    p = _params(2, n, 1e-3)
+    u0 = inputs.random_field_2d(n, 5, umax=0.05 / p.dx)
+    out = []
+    for storage in ("f32_moments", "f32"):
+        eng = _engine(p, u0, storage)
+        eng.step(500)
+        out.append(eng.moments())
+        eng.close()
+    err = _rel(out[0][1] / out[0][0], out[1][1] / out[1][0])
+    print(f"[moments] moments vs populations rel-L2(u) = {err:.3e}", flush=True)
+    assert err <= 5e-6
+
+
+def test_moments_storage_requires_omega_one():
+    p = scheme.params_for_grid(2, 16, 0.01)     # omega_q = 23/20
+    with pytest.raises(lbm.LbmError):
+        lbm.Engine.create(lbm.make_params(2, (16, 16), p.dx, p.dt, p.nu, storage="f32_moments"),
+                          np.zeros((2, 16, 16)))
