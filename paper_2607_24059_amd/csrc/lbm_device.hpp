@@ -295,9 +295,10 @@ struct NeqScale {
   float inv[D + 1];  // 1 / s[i]
 };
 
-// 1 / rho in the split-storage paths: the hardware reciprocal (1 ulp), used by
-// every split-storage routine alike so that a cell's equilibrium rebuilt by a
-// neighbour equals the one the cell computed itself, bit for bit.
+// 1 / rho where equilibria are rebuilt from stored moments (the split and the
+// moment-only storage): the hardware reciprocal (1 ulp), used by every such
+// routine alike so that a cell's equilibrium rebuilt by a neighbour equals the
+// one the cell computed itself, bit for bit, in every kernel.
 __device__ __forceinline__ float recip_neq(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // The equilibrium (deviation) of set i, moving velocity 1 + m (axis m / 2,
@@ -414,7 +415,7 @@ __device__ __forceinline__ void step_moments(WAt w_at, const Coef& k, float (&ou
     float Wn[D + 1];
 #pragma unroll
     for (int i = 0; i < D + 1; ++i) Wn[i] = w_at(i, m);
-    const float inv = 1.0f / (Wn[0] + k.ref);
+    const float inv = recip_neq(Wn[0] + k.ref);  // hardware reciprocal, as in the split storage
 #pragma unroll
     for (int i = 0; i < D + 1; ++i) out[i] = out[i] + eq_moving<D, float>(Wn, inv, k, i, m);
   }
