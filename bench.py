@@ -252,6 +252,8 @@ def main():
             variants[f"batch512_{storage}"] = batch_variant(storage, 1000, probe)
         log("[bench] batch 512 runs f32, one step per launch")
         variants["batch512_f32_one_step_per_launch"] = batch_variant("f32", 1000, probe, fuse=1)
+        log("[bench] Taylor-Green parameter sweep (Fig. 2 plane + Fig. 3 curves) as one batch")
+        variants["sweep_tg75_fig2_fig3"] = sweep_variant()
         result["variants"] = variants
 
     if not args.no_equal_error:
@@ -411,6 +413,26 @@ def batch_variant(storage: str, steps: int, probe: float, n_runs: int = 512, fus
                 "grid": grid, "fused_grid": grid2,
                 "tile_width_by_n": {str(n): w for n, w in widths}})
     return out
+
+
+def sweep_variant() -> dict:
+    """The parameter sweeps of Section 5.1 at 75 cells to t = 1: the Fig. 2
+    plane (omega_rho in 1..1.95, alpha_rho in 0.01..0.25, omega_q = 1) and
+    the Fig. 3 curves (omega_q in 1..1.6 for the three isoline pairs), one
+    batch, FP32, tiles autotuned; wall time of the time stepping."""
+    from paper_2607_24059_amd import sweep
+    tg = sweep.TaylorGreen()
+    pts2, pts3 = sweep.figure2_points(), sweep.figure3_points()
+    res = sweep.run(pts2 + pts3, tg, autotune=True)
+    e2 = res.errors[:len(pts2)]
+    i = int(np.argmin(e2))
+    iso = {f"{wr:g},{ar:g}": float(res.errors[len(pts2) + pts3.index((wr, ar, 1.15))])
+           for wr, ar in sweep.PAIRS}
+    return _finite({"runs": len(res.points), "cells_per_run": tg.n ** 2, "steps": res.steps,
+                    "ms": round(res.seconds * 1e3, 2), "MLUPS": round(res.glups * 1e3, 1),
+                    "fig2_min_error": float(e2[i]), "fig2_min_at": list(pts2[i][:2]),
+                    "fig2_unstable_runs": int(np.sum(~np.isfinite(e2) | (e2 > 10 * e2[i]))),
+                    "isoline_errors_omega_q_1.15": iso, "nu": tg.nu})
 
 
 def _variant(cells, ms, bytes_per_lup, probe):
