@@ -254,6 +254,9 @@ def main():
         variants["batch512_f32_one_step_per_launch"] = batch_variant("f32", 1000, probe, fuse=1)
         log("[bench] Taylor-Green parameter sweep (Fig. 2 plane + Fig. 3 curves) as one batch")
         variants["sweep_tg75_fig2_fig3"] = sweep_variant()
+        for dim_s in (2, 3):
+            log(f"[bench] batched linear spectra, {dim_s}D")
+            variants[f"spectrum_{dim_s}d"] = spectrum_variant(dim_s)
         result["variants"] = variants
 
     if not args.no_equal_error:
@@ -431,8 +434,68 @@ def sweep_variant() -> dict:
     return _finite({"runs": len(res.points), "cells_per_run": tg.n ** 2, "steps": res.steps,
                     "ms": round(res.seconds * 1e3, 2), "MLUPS": round(res.glups * 1e3, 1),
                     "fig2_min_error": float(e2[i]), "fig2_min_at": list(pts2[i][:2]),
-                    "fig2_unstable_runs": int(np.sum(~np.isfinite(e2) | (e2 > 10 * e2[i]))),
+                    "fig2_nonfinite_runs": int(np.sum(~np.isfinite(e2))),
                     "isoline_errors_omega_q_1.15": iso, "nu": tg.nu})
+
+
+def spectrum_variant(dim: int, reps: int = 3, cpu_points: int = 1000) -> dict:
+    """Eigenvalues of E(theta) (Section 4) for a map of points: in 2D the
+    Fig. 1 setting (omega = 1, alpha_rho = 1/4, nu = pi/50, alpha_q = nu/mu,
+    reference (1, 1, 1), dx = 1e-6) for 64 values of mu in [0.5, 16] x 4096
+    frequencies on the diagonal; in 3D 16 general-omega states x 4096 random
+    frequencies.  Time: HIP events around the launch on its stream; work:
+    the flops the kernel counts (reflections and rotations).  CPU: LAPACK
+    (numpy) on the oracle's matrices for a sample of the points, one core."""
+    import time
+    import torch
+    from paper_2607_24059_amd import spectrum as S
+    from oracle import spectrum as O
+    nth = 4096
+    if dim == 2:
+        nu = math.pi / 50
+        mus = np.linspace(0.5, 16.0, 64)
+        states = [S.make_state(mu, 1e-6, 1.0, 1.0, 0.25, nu / mu, 1.0, (1.0, 1.0)) for mu in mus]
+        prm = [(1e-6, mu, 1.0, 1.0, 0.25, nu / mu, 1.0, np.array([1.0, 1.0])) for mu in mus]
+        taus = np.linspace(-math.pi, math.pi, nth)
+        th = np.tile(np.stack([taus, taus], axis=1), (len(mus), 1))
+    else:
+        rng = np.random.default_rng(3)
+        states, prm = [], []
+        for _ in range(16):
+            w = rng.uniform(1.0, 1.9, 2)
+            a = rng.uniform(0.0, 1.0 / 6.0, 2)
+            mu = rng.uniform(4.0, 12.0)
+            qb = rng.uniform(-1, 1, 3)
+            states.append(S.make_state(mu, 1e-3, w[0], w[1], a[0], a[1], 1.0, qb))
+            prm.append((1e-3, mu, w[0], w[1], a[0], a[1], 1.0, qb))
+        th = rng.uniform(-math.pi, math.pi, (16 * nth, 3))
+    idx = np.repeat(np.arange(len(states), dtype=np.int32), nth)
+    pb = S.Problem(dim, states, th, idx)
+    stream = torch.cuda.current_stream()
+    pb.launch(stream)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(reps):
+        pb.launch(stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    res = pb.results()
+    flops = float(np.sum(res["flops"]))
+    gflops = flops / (ms * 1e-3) / 1e9
+    sample = np.linspace(0, len(idx) - 1, cpu_points).astype(int)
+    t0 = time.perf_counter()
+    for p in sample:
+        dx, mu, wr, wq, ar, aq, rb, qb = prm[idx[p]]
+        np.linalg.eigvals(O.amplification_matrix(th[p], dim, dx, mu, wr, wq, ar, aq, rb, qb))
+    cpu_s = time.perf_counter() - t0
+    return {"points": int(len(idx)), "order": S.lbm_spectrum_order(dim), "ms": round(ms, 3),
+            "points_per_s": round(len(idx) / (ms * 1e-3), 1), "mean_qr_sweeps": round(float(res["info"].mean()), 2),
+            "unconverged": int(np.sum(res["info"] < 0)), "counted_gflops": round(gflops, 2),
+            "frac_fp64_vector_peak": round(gflops / 78600.0, 5),
+            "cpu_lapack_points_per_s": round(cpu_points / cpu_s, 1), "cpu_sample_points": cpu_points}
 
 
 def _variant(cells, ms, bytes_per_lup, probe):

@@ -97,9 +97,10 @@ class SweepResult:
     def glups(self) -> float:
         return self.cells * self.steps / self.seconds / 1e9
 
-    def grid(self, nw: int, na: int) -> np.ndarray:
-        """Errors of a figure2_points sweep as [alpha index][omega index]."""
-        return self.errors.reshape(na, nw)
+    def grid(self, nw: int, na: int, start: int = 0) -> np.ndarray:
+        """Errors of a figure2_points sweep of nw x na runs placed at run
+        `start` of the batch, as [alpha index][omega index]."""
+        return self.errors[start:start + nw * na].reshape(na, nw)
 
 
 def run(points, tg: TaylorGreen = TaylorGreen(), storage: str = "f32", fuse: int = 2,

@@ -1,6 +1,7 @@
 """Host-only checks of the C ABI: the library loads, exports every symbol the
 headers declare, and validates parameters without touching a GPU."""
 
+import ctypes as C
 import glob
 import math
 import os
@@ -35,7 +36,7 @@ def test_binding_wraps_every_declared_symbol():
     """The Python binding carries one signature per declared entry point."""
     import paper_2607_24059_amd.lbm as B
     sigs = set(B.SIGNATURES)
-    for extra in ("batch", "closure", "cnn"):
+    for extra in ("batch", "closure", "cnn", "spectrum"):
         mod = getattr(__import__("paper_2607_24059_amd", fromlist=[extra]), extra, None)
         if mod is not None and hasattr(mod, "SIGNATURES"):
             sigs |= set(mod.SIGNATURES)
@@ -114,3 +115,24 @@ def test_moment_storage_only_for_the_relaxation_scheme():
 def test_strerror():
     assert lbm.lbm_strerror(lbm.LBM_OK) == "ok"
     assert "workspace" in lbm.lbm_strerror(lbm.LBM_ENOMEM)
+
+
+def test_spectrum_host_validation():
+    """lbm_spectrum_* reject bad arguments on the host, before any launch."""
+    from paper_2607_24059_amd import spectrum as S
+    L = S.slib()
+    assert S.lbm_spectrum_order(2) == 15 and S.lbm_spectrum_order(3) == 28
+    assert S.lbm_spectrum_order(1) == 0 and S.lbm_spectrum_order(4) == 0
+    fake = 0x1000                                   # never dereferenced: every call fails validation
+    assert L.lbm_spectrum_eigs(4, 1, fake, 1, None, fake, fake, None, None, None, None) == lbm.LBM_EINVAL
+    assert L.lbm_spectrum_eigs(2, -1, fake, 1, None, fake, fake, None, None, None, None) == lbm.LBM_EINVAL
+    assert L.lbm_spectrum_eigs(2, 1, fake, 0, None, fake, fake, None, None, None, None) == lbm.LBM_EINVAL
+    assert L.lbm_spectrum_eigs(2, 1, None, 1, None, fake, fake, None, None, None, None) == lbm.LBM_EINVAL
+    assert L.lbm_spectrum_eigs(2, 1, fake, 1, None, None, fake, None, None, None, None) == lbm.LBM_EINVAL
+    assert L.lbm_spectrum_eigs(2, 1, fake, 1, None, fake, None, None, None, None, None) == lbm.LBM_EINVAL
+    assert L.lbm_spectrum_matrix(3, 1, fake, 1, None, fake, None, None) == lbm.LBM_EINVAL
+    assert L.lbm_spectrum_matrix(2, 1, fake, 1, None, None, fake, None) == lbm.LBM_EINVAL
+    # no points: nothing to launch
+    assert L.lbm_spectrum_eigs(2, 0, fake, 1, None, fake, fake, None, None, None, None) == lbm.LBM_OK
+    assert L.lbm_spectrum_matrix(3, 0, fake, 1, None, fake, fake, None) == lbm.LBM_OK
+    assert C.sizeof(S.lbm_lin_state) == 11 * 8

@@ -125,3 +125,47 @@ def test_oracle_follows_the_amplification_matrix():
     vn = np.linalg.matrix_power(E, steps) @ v
     pred = base + eps * np.real(vn.reshape(3, 5, 1, 1) * wave)
     assert np.max(np.abs(f - pred)) <= 1e-5 * eps * np.max(np.abs(vn))
+
+
+def _fig1_matrix(theta, mu, q_bar=(1.0, 1.0)):
+    """The setting of Fig. 1: relaxation scheme (omega = 1), alpha_rho = 1/4,
+    nu = pi/50, alpha_q = nu/mu, reference (1, 1, 1), dx = 1e-6."""
+    nu = math.pi / 50
+    return spectrum.amplification_matrix(np.asarray(theta, float), 2, 1e-6, mu, 1.0, 1.0, 0.25, nu / mu,
+                                         1.0, np.array(q_bar))
+
+
+@pytest.mark.parametrize("mu", [2.0, 8.0])
+def test_low_frequency_acoustic_pair_on_the_diagonal(mu):
+    """Lemma 2's expansion along theta = (tau, tau): the acoustic pair is
+    1 +- i sqrt(2) tau/mu - c2 tau^2 + O(tau^3).  The 2x2 acoustic block of the
+    omega = 1 map, [[1 - 2 a_rho c, -i sqrt(2) s/mu], [-i sqrt(2) s/mu, 1 - 2 a_q c]]
+    with c = 2 (1 - cos tau), s = sin tau, gives c2 = a_rho + a_q: the damping of
+    the longitudinal momentum (q_x + q_y)/sqrt(2) enters once (reading: the
+    printed lemma sums a_rho + a_qx + a_qy)."""
+    a_rho, a_q = 0.25, math.pi / 50 / mu
+    for tau in (2e-3, 1e-3):
+        ev = np.linalg.eigvals(_fig1_matrix([tau, tau], mu))
+        z = ev[np.argmin(np.abs(ev - (1 + 1j * math.sqrt(2) * tau / mu)))]
+        assert z.imag / tau == pytest.approx(math.sqrt(2) / mu, rel=1e-5)
+        assert (1 - z.real) / tau ** 2 == pytest.approx(a_rho + a_q, rel=1e-4)
+        assert abs((1 - z.real) / tau ** 2 - (a_rho + 2 * a_q)) > 0.5 * a_q
+
+
+def test_stability_threshold_in_mu_on_the_diagonal():
+    """|z|^2 = 1 - 2 (a_rho + a_q - 1/mu^2) tau^2 + O(tau^4) for the acoustic
+    pair, so the low frequencies along the diagonal need mu^2 (a_rho + a_q) >= 1;
+    with a_rho = 1/4 and a_q = nu/mu that is mu >= -2 nu + sqrt(4 nu^2 + 4)
+    = 1.8783 (nu = pi/50).  The whole diagonal is stable just above it and
+    unstable just below it; at mu = 1.80, above the printed bound's 1.7644, it
+    is unstable, so that bound is necessary but not sufficient here."""
+    nu = math.pi / 50
+    mu_star = -2 * nu + math.sqrt(4 * nu * nu + 4)
+    assert mu_star == pytest.approx(1.8782802469, rel=1e-9)
+    ts = np.concatenate([np.linspace(-math.pi, math.pi, 401), np.geomspace(1e-4, 0.5, 60)])
+
+    def radius(mu):
+        return max(np.max(np.abs(np.linalg.eigvals(_fig1_matrix([t, t], mu)))) for t in ts)
+    assert radius(1.87) > 1 + 1e-5
+    assert radius(1.89) <= 1 + 1e-12
+    assert radius(1.80) > 1 + 1e-3
