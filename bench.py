@@ -159,6 +159,8 @@ def main():
     ap.add_argument("--variant-steps", type=int, default=200)
     ap.add_argument("--no-equal-error", action="store_true")
     ap.add_argument("--equal-error-seeds", type=int, default=2)
+    ap.add_argument("--only", choices=sorted(ONLY),
+                    help="run one secondary workload alone and print its JSON (for profiling)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -171,6 +173,10 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+
+    if args.only:
+        print(json.dumps({"only": args.only, **ONLY[args.only](args)}), flush=True)
+        return
 
     n = args.n
     log(f"[bench] generating {n}^2 workload")
@@ -504,6 +510,15 @@ def _variant(cells, ms, bytes_per_lup, probe):
             "GBs": round(gbs, 1), "frac_peak": round(gbs / PEAK_HBM_GBS, 4),
             "frac_probe": round(gbs / probe, 4)}
 
+
+# secondary workloads that `--only` runs alone (each as in the variants section)
+ONLY = {
+    "spectrum_2d": lambda a: spectrum_variant(2, cpu_points=10),
+    "spectrum_3d": lambda a: spectrum_variant(3, cpu_points=10),
+    "moments_2d": lambda a: moments_variant(2, a.n, a.variant_steps, copy_probe_gbs()),
+    "moments_3d": lambda a: moments_variant(3, 256, a.variant_steps, copy_probe_gbs()),
+    "sweep": lambda a: sweep_variant(),
+}
 
 if __name__ == "__main__":
     main()
