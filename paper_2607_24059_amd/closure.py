@@ -508,15 +508,32 @@ def evaluate(cfg: Config, net, scales, log=print, seeds=None, levels=None, plain
     out["speedup_equal_error"] = {
         "closure": equal_error_speedup(levels, ref["u_sol"], ref["time_ms"], out["closure"]["u_sol"],
                                        out["closure"]["time_ms"])}
+    last_dec = last_decreasing_level(levels, ref["u_sol"])
     for st in plain_storages[1:]:
         out["speedup_equal_error"][st] = {}
         for n in levels:
-            r = equal_error_speedup(levels, ref["u_sol"], ref["time_ms"], out["plain"][st]["u_sol"][str(n)],
-                                    out["plain"][st]["time_ms"][str(n)])
+            if int(n) > last_dec:
+                # the plain FP32 curve is rounding-limited here: no resolution
+                # has the same error on its resolution-limited part
+                r = {"N_star": float("nan"), "speedup": float("nan"),
+                     "note": "plain FP32 error rounding-limited at this level (above the previous level's): "
+                             "compare at the same resolution"}
+            else:
+                r = equal_error_speedup(levels, ref["u_sol"], ref["time_ms"], out["plain"][st]["u_sol"][str(n)],
+                                        out["plain"][st]["time_ms"][str(n)])
             r["speedup_same_resolution"] = ref["time_ms"][str(n)] / out["plain"][st]["time_ms"][str(n)]
             r["error_ratio_same_resolution"] = out["plain"][st]["u_sol"][str(n)] / ref["u_sol"][str(n)]
             out["speedup_equal_error"][st][str(n)] = r
     return out
+
+
+def last_decreasing_level(levels, err) -> int:
+    """The finest level up to which err(N) decreases from level to level."""
+    lv = sorted(int(n) for n in levels)
+    k = 1
+    while k < len(lv) and float(err[str(lv[k])]) < float(err[str(lv[k - 1])]):
+        k += 1
+    return lv[k - 1]
 
 
 def equal_error_speedup(levels, err, time_ms, e_target, t_target):

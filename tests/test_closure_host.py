@@ -30,3 +30,9 @@ def test_extrapolated_past_the_rounding_floor():
 def test_no_equal_error_point():
     r = cl.equal_error_speedup(LEVELS, ERR, TIME, 5e-5, 3.0)
     assert math.isnan(r["N_star"]) and math.isnan(r["speedup"])
+
+
+def test_last_decreasing_level():
+    assert cl.last_decreasing_level(LEVELS, ERR) == 512
+    assert cl.last_decreasing_level(LEVELS, {"256": 4e-5, "512": 1e-5, "1024": 3e-6}) == 1024
+    assert cl.last_decreasing_level(LEVELS, {"256": 4e-5, "512": 5e-5, "1024": 3e-6}) == 256
