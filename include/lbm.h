@@ -144,15 +144,23 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const 
                     void* workspace, size_t ws_bytes, void* hip_stream);
 
 /* Advance nsteps >= 0 time steps (relaxation then transport, Section 2).
- * Each launch fuses relaxation and transport; in 2D a launch advances two steps
- * by default (the intermediate state of each tile and its one-cell border
- * kept on chip), with a single-step launch for an odd remainder.  The result
- * is bit-identical for any fusion setting.  Asynchronous. */
+ * Each launch fuses relaxation and transport.  In 2D one launch advances
+ * several steps (lbm_set_fusion): each tile and a border as wide as the
+ * steps still to come are advanced on chip, the border shrinking by one cell
+ * per step, and only the tile's final state is written back.  A remainder
+ * shorter than the fusion depth runs as two-step and single-step launches.
+ * The result is bit-identical for any fusion setting.  Asynchronous. */
 lbm_status lbm_step(lbm_ctx* ctx, int64_t nsteps);
 
-/* Time steps per launch: 1, or 2 (2D only; the default in 2D).  LBM_EINVAL
- * if the setting is not available for the context's dimension. */
+/* Time steps per launch, 1 .. 6.  2 needs a 2D context; 3 .. 6 a 2D context in
+ * one of the population storages (LBM_F32, LBM_F32_RAW, LBM_F16_DEV,
+ * LBM_BF16_DEV, LBM_F16_DEV_R32, LBM_BF16_DEV_R32); channel boundaries allow
+ * 1 only.  LBM_EINVAL otherwise.  Default: 5 for those storages from 2^20
+ * cells on, else 2 in 2D, 1 in 3D. */
 lbm_status lbm_set_fusion(lbm_ctx* ctx, int32_t steps_per_launch);
+
+/* The current number of time steps per launch (0 for a NULL context). */
+int32_t lbm_fusion(const lbm_ctx* ctx);
 
 /* Moments of the current state: rho [cells] and q [dim][cells] = (1/dx) sum f_q,
  * summed in FP64 from the stored populations.  Host FP64 outputs; q may be

@@ -171,7 +171,9 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const 
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->steps = 0;
   default_block(g, &c->bx, &c->by);
-  c->fuse = c->ops->step2 ? 2 : 1;
+  // deeper fusion from 1024^2 cells on; smaller grids are launch-bound and
+  // keep the two-step kernel's small tiles
+  c->fuse = c->ops->stepK && g.cells >= (int64_t(1) << 20) ? 5 : c->ops->step2 ? 2 : 1;
 
   // stage u0 (and rho0) as FP64 in the idle buffer, then build the equilibrium
   double* su = reinterpret_cast<double*>(staging(c));
@@ -195,26 +197,32 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const 
 lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
   if (!c || nsteps < 0) return LBM_EINVAL;
   while (nsteps > 0) {
-    const bool two = c->fuse == 2 && nsteps >= 2 && !c->walls;
+    // the longest launch that fits: fuse steps, then two, then one (all give
+    // the same state bit for bit)
+    const int k = c->walls ? 1 : nsteps >= c->fuse ? c->fuse : (c->fuse >= 2 && nsteps >= 2) ? 2 : 1;
     hipError_t e = c->walls ? c->ops->step_walls(c->g, c->coef, c->cur, c->nxt, c->wall, c->bx, c->by, c->stream)
-                   : two    ? c->ops->step2(c->g, c->coef, c->cur, c->nxt, c->stream)
+                   : k >= 3 ? c->ops->stepK(c->g, c->coef, k, c->cur, c->nxt, c->stream)
+                   : k == 2 ? c->ops->step2(c->g, c->coef, c->cur, c->nxt, c->stream)
                             : c->ops->step(c->g, c->coef, c->cur, c->nxt, c->bx, c->by, c->stream);
     if (e != hipSuccess) return LBM_EDEVICE;
     char* t = c->cur;
     c->cur = c->nxt;
     c->nxt = t;
-    c->steps += two ? 2 : 1;
-    nsteps -= two ? 2 : 1;
+    c->steps += k;
+    nsteps -= k;
   }
   return LBM_OK;
 }
 
 lbm_status lbm_set_fusion(lbm_ctx* c, int32_t steps_per_launch) {
-  if (!c || steps_per_launch < 1 || steps_per_launch > 2) return LBM_EINVAL;
-  if (steps_per_launch == 2 && (!c->ops->step2 || c->walls)) return LBM_EINVAL;
+  if (!c || steps_per_launch < 1 || steps_per_launch > lbm::kMaxFusion) return LBM_EINVAL;
+  if (steps_per_launch >= 2 && (!c->ops->step2 || c->walls)) return LBM_EINVAL;
+  if (steps_per_launch >= 3 && !c->ops->stepK) return LBM_EINVAL;
   c->fuse = steps_per_launch;
   return LBM_OK;
 }
+
+int32_t lbm_fusion(const lbm_ctx* c) { return c ? c->fuse : 0; }
 
 lbm_status lbm_set_walls(lbm_ctx* c, const lbm_walls* w, const double* u_in) {
   if (!c) return LBM_EINVAL;

@@ -55,7 +55,12 @@ struct Ops {
   // one step with the channel boundaries (2D population storages; nullptr otherwise)
   hipError_t (*step_walls)(const Geometry&, const RunCoef&, const void* src, void* dst, const WallArgs& w, int bx,
                            int by, hipStream_t s);
+  // K = 3 .. kMaxFusion steps in one launch (2D population storages; nullptr otherwise)
+  hipError_t (*stepK)(const Geometry&, const RunCoef&, int K, const void* src, void* dst, hipStream_t s);
 };
+
+// Most time steps one launch may advance.
+constexpr int kMaxFusion = 6;
 
 // Ops for a dimension and an lbm_storage value; nullptr if unsupported.
 const Ops* ops_for(int dim, int storage);
@@ -130,7 +135,7 @@ struct lbm_ctx {
   hipStream_t stream;
   int64_t steps;
   int bx, by;       // step kernel block shape
-  int fuse;         // time steps per launch: 1, or 2 (2D two-step kernel)
+  int fuse;         // time steps per launch: 1, 2 (two-step kernel) or 3..kMaxFusion (2D)
   int walls;        // 1: channel boundaries (lbm_set_walls) instead of periodic
   lbm::WallArgs wall;
   double* wall_profile;  // [2][ny] inlet velocity, in the workspace (2D)

@@ -264,6 +264,132 @@ __device__ __forceinline__ void step2_tile(const TR* __restrict__ sr, const TM* 
   }
 }
 
+// ----------------------------------------------------------------------------
+// K >= 3 steps in one launch (2D, population storages): the block advances its
+// TX x TY tile plus a (K-1)-cell border by one step from HBM into LDS, then
+// K-2 more steps in LDS, each over a region one cell narrower on every side
+// (the cells whose inputs are still valid), and the tile by the last step to
+// HBM.  A step inside LDS gathers and relaxes its cells into registers, waits
+// for every thread, and writes them back over the same LDS slots, so one LDS
+// buffer serves all stages.  Every intermediate value is rounded to the
+// storage type when it is written to LDS, as a store to HBM would round it, so
+// the result equals K single steps bit for bit.  Each state value is read from
+// HBM about (TX+2K)(TY+2K)/(TX TY) times and written once per K steps.
+// ----------------------------------------------------------------------------
+template <typename TR, typename TM, int EX, int EN>
+__device__ __forceinline__ void gather_lds(const TR (&s_rest)[3][EN], const TM (&s_move)[12][EN], int e,
+                                           float (&g)[3][5]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    g[i][0] = load_f32(&s_rest[i][e]);
+    g[i][1] = load_f32(&s_move[i * 4 + 0][e - 1]);   // +x from x-1
+    g[i][2] = load_f32(&s_move[i * 4 + 1][e + 1]);   // -x from x+1
+    g[i][3] = load_f32(&s_move[i * 4 + 2][e - EX]);  // +y from y-1
+    g[i][4] = load_f32(&s_move[i * 4 + 3][e + EX]);  // -y from y+1
+  }
+}
+
+// one step inside LDS over the region [LO, EX - LO) x [LO, EY - LO)
+template <typename TR, typename TM, int EX, int EY, int NT, int LO>
+__device__ __forceinline__ void lds_stage(TR (&s_rest)[3][EX * EY], TM (&s_move)[12][EX * EY], const Coef& k) {
+  constexpr int EN = EX * EY, RX = EX - 2 * LO, RY = EY - 2 * LO, RN = RX * RY;
+  constexpr int PER = (RN + NT - 1) / NT;
+  float keep[PER][3][5];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int t = static_cast<int>(threadIdx.x) + j * NT;
+    if (t < RN) {
+      const int e = (LO + t / RX) * EX + LO + t % RX;
+      gather_lds<TR, TM, EX, EN>(s_rest, s_move, e, keep[j]);
+      collide<2>(keep[j], k);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int t = static_cast<int>(threadIdx.x) + j * NT;
+    if (t < RN) {
+      const int e = (LO + t / RX) * EX + LO + t % RX;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        store_f32(&s_rest[i][e], keep[j][i][0]);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) store_f32(&s_move[i * 4 + m][e], keep[j][i][1 + m]);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <typename TR, typename TM, int EX, int EY, int NT, int LO, int LAST>
+__device__ __forceinline__ void lds_stages(TR (&s_rest)[3][EX * EY], TM (&s_move)[12][EX * EY], const Coef& k) {
+  if constexpr (LO <= LAST) {
+    lds_stage<TR, TM, EX, EY, NT, LO>(s_rest, s_move, k);
+    lds_stages<TR, TM, EX, EY, NT, LO + 1, LAST>(s_rest, s_move, k);
+  }
+}
+
+// XCD: with a one-dimensional grid, consecutive blocks go to the eight XCDs in
+// turn; XCD-major numbering gives each XCD a contiguous band of tiles, so the
+// borders that neighbouring tiles share are read through the same L2.
+template <typename TR, typename TM, int TX, int TY, int NT, int K, bool XCD = false>
+__global__ __launch_bounds__(NT) void k_stepK_2d(const TR* __restrict__ sr, const TM* __restrict__ sm,
+                                                  TR* __restrict__ dr, TM* __restrict__ dm, int nx, int ny,
+                                                  int64_t stride, Coef k) {
+  static_assert(K >= 3, "two steps per launch use k_step2_2d");
+  constexpr int H = K - 1, EX = TX + 2 * H, EY = TY + 2 * H, EN = EX * EY;
+  __shared__ TR s_rest[3][EN];
+  __shared__ TM s_move[12][EN];
+  int x0, y0;
+  if constexpr (XCD) {
+    const int tiles_x = (nx + TX - 1) / TX;
+    const int nt = tiles_x * ((ny + TY - 1) / TY);
+    const int b = blockIdx.x;
+    const int t = (nt % 8 == 0) ? (b % 8) * (nt / 8) + b / 8 : b;
+    x0 = (t % tiles_x) * TX;
+    y0 = (t / tiles_x) * TY;
+  } else {
+    x0 = blockIdx.x * TX;
+    y0 = blockIdx.y * TY;
+  }
+  // first step, from HBM, over the whole extended tile
+  for (int e = threadIdx.x; e < EN; e += NT) {
+    const int ex = e % EX, ey = e / EX;
+    int x = x0 - H + ex, y = y0 - H + ey;
+    x = ((x % nx) + nx) % nx;  // the border may wrap (several times on tiny grids)
+    y = ((y % ny) + ny) % ny;
+    const int64_t c = static_cast<int64_t>(y) * nx + x;
+    float g[3][5];
+    gather_cell<2, TR, TM>(sr, sm, x, y, 0, nx, ny, 1, stride, c, g);
+    collide<2>(g, k);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      store_f32(&s_rest[i][e], g[i][0]);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) store_f32(&s_move[i * 4 + m][e], g[i][1 + m]);
+    }
+  }
+  __syncthreads();
+  // steps 2 .. K-1 in LDS
+  lds_stages<TR, TM, EX, EY, NT, 1, H - 1>(s_rest, s_move, k);
+  // last step, from LDS to HBM, over the tile
+  for (int t = threadIdx.x; t < TX * TY; t += NT) {
+    const int tx = t % TX, ty = t / TX;
+    const int x = x0 + tx, y = y0 + ty;
+    if (x >= nx || y >= ny) continue;
+    float g[3][5];
+    gather_lds<TR, TM, EX, EN>(s_rest, s_move, (ty + H) * EX + (tx + H), g);
+    collide<2>(g, k);
+    const int64_t c = static_cast<int64_t>(y) * nx + x;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      store_stream(dr + i * stride + c, g[i][0]);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) store_stream(dm + (i * 4 + m) * stride + c, g[i][1 + m]);
+    }
+  }
+}
+
 template <typename TR, typename TM, int TX, int TY, int NT>
 __global__ __launch_bounds__(NT) void k_step2_2d(const TR* __restrict__ sr, const TM* __restrict__ sm,
                                                   TR* __restrict__ dr, TM* __restrict__ dm, int nx, int ny,
@@ -550,6 +676,46 @@ struct Impl {
     }
   }
 
+  // K = 3 .. 6 steps per launch (2D population storages), 64x16 tiles in
+  // XCD-major order: 1024 threads for 4-byte rest planes, 512 for all-16-bit
+  // storage.  From sweeps of this kernel on MI355X (GLUPS at 4096^2 / 2048^2 /
+  // 1024^2, two steps per launch first): FP32 86.9 / 68.5 / 63.8 against 114.3 /
+  // 121.7 / 118.6 at K = 5; FP16 140.3 / 116.4 / 119.5 against 173.9 / 165.6 /
+  // 145.4; FP16 + FP32 rest 124.5 / 108.5 / 100.9 against 197.9 / 189.6 / 163.4.
+  // Deeper fusion moves fewer HBM bytes per step (the state is read about
+  // (TX+2K)(TY+2K)/(TX TY) times and written once per K steps) at the price of
+  // recomputing the shrinking borders; K = 6..8 and 32x16, 32x32 or 64x32
+  // tiles were within a few percent or slower.
+  static constexpr bool kHasStepK = kHasStep2 && !IsNeq<TM>::value && !IsMom<TM>::value;
+  static constexpr int kStepKThreads = sizeof(TR) == 2 ? 512 : 1024;
+
+  template <int K>
+  static hipError_t launchK(const Geometry& g, const RunCoef& r, const void* src, void* dst, hipStream_t s) {
+    constexpr int TX = 64, TY = 16;
+    auto a = planes_of<TR, TM>(const_cast<void*>(src), g.rest_bytes);
+    auto b = planes_of<TR, TM>(dst, g.rest_bytes);
+    const Coef k = make_coef<float>(r, D, DEV);
+    const int64_t tiles = static_cast<int64_t>((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY);
+    hipLaunchKernelGGL((k_stepK_2d<TR, TM, TX, TY, kStepKThreads, K, true>), dim3(static_cast<uint32_t>(tiles)),
+                       dim3(kStepKThreads), 0, s, a.rest, a.move, b.rest, b.move, g.nx, g.ny, g.stride, k);
+    return hipGetLastError();
+  }
+
+  static hipError_t stepK(const Geometry& g, const RunCoef& r, int K, const void* src, void* dst,
+                          hipStream_t s) {
+    if constexpr (!kHasStepK) {
+      return hipErrorInvalidValue;
+    } else {
+      switch (K) {
+        case 3: return launchK<3>(g, r, src, dst, s);
+        case 4: return launchK<4>(g, r, src, dst, s);
+        case 5: return launchK<5>(g, r, src, dst, s);
+        case 6: return launchK<6>(g, r, src, dst, s);
+      }
+      return hipErrorInvalidValue;
+    }
+  }
+
   static constexpr bool kHasWalls = D == 2 && !StoresMoments<TM>::value;
 
   static hipError_t step_walls(const Geometry& g, const RunCoef& r, const void* src, void* dst, const WallArgs& w,
@@ -602,7 +768,7 @@ struct Impl {
 
   static const Ops* ops() {
     static const Ops o = {&init, &step, kHasStep2 ? &step2 : nullptr, &moments, &diag, &diag_blocks,
-                          kHasWalls ? &step_walls : nullptr};
+                          kHasWalls ? &step_walls : nullptr, kHasStepK ? &stepK : nullptr};
     return &o;
   }
 };

@@ -82,6 +82,7 @@ SIGNATURES = {
                            C.c_void_p, C.c_size_t, C.c_void_p]),
     "lbm_step": (C.c_int, [C.c_void_p, C.c_int64]),
     "lbm_set_fusion": (C.c_int, [C.c_void_p, C.c_int32]),
+    "lbm_fusion": (C.c_int32, [C.c_void_p]),
     "lbm_set_walls": (C.c_int, [C.c_void_p, C.POINTER(lbm_walls), C.c_void_p]),
     "lbm_moments": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "lbm_moments_device": (C.c_int, [C.c_void_p, C.c_void_p]),
@@ -162,6 +163,10 @@ def lbm_step(ctx: int, nsteps: int) -> None:
 
 def lbm_set_fusion(ctx: int, steps_per_launch: int) -> None:
     _ok(lib().lbm_set_fusion(C.c_void_p(ctx), int(steps_per_launch)), "lbm_set_fusion")
+
+
+def lbm_fusion(ctx: int) -> int:
+    return int(lib().lbm_fusion(C.c_void_p(ctx)))
 
 
 def lbm_set_walls(ctx: int, walls: lbm_walls | None, u_in: np.ndarray | None) -> None:
@@ -281,6 +286,9 @@ class Engine:
 
     def set_fusion(self, steps_per_launch: int) -> None:
         lbm_set_fusion(self.ctx, steps_per_launch)
+
+    def fusion(self) -> int:
+        return lbm_fusion(self.ctx)
 
     def moments(self):
         rho = np.empty(self.shape)

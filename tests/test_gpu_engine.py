@@ -333,6 +333,82 @@ def test_two_step_fusion_bitwise_large_tile(storage):
     assert digests[0] == digests[1]
 
 
+# --------------------------------------------------------------------------- #
+# 3 .. 6 steps per launch (2D population storages): bit-identical as well     #
+# --------------------------------------------------------------------------- #
+
+@pytest.mark.parametrize("storage", ["f32", "f16_dev", "bf16_dev", "f16_dev_r32", "bf16_dev_r32", "f32_raw"])
+@pytest.mark.parametrize("shape,steps", [((64, 64), 13), ((75, 75), 17), ((17, 130), 11), ((3, 200), 9),
+                                         ((1, 1), 7), ((300, 257), 12)])
+def test_deep_fusion_is_bitwise(storage, shape, steps):
+    """Every fusion depth gives the single-step state; the step counts leave
+    remainders that run as two-step and single-step launches."""
+    ny, nx = shape
+    dx = 2 * math.pi / max(shape)
+    p = scheme.Params(dim=2, dx=dx, dt=dx * dx / 8, nu=0.02)
+    u = inputs.random_field_box(shape, dx, seed=13, umax=0.05 / dx)
+    blobs = []
+    for fuse in (1, 3, 4, 5, 6):
+        eng = _engine(p, u, storage=storage)
+        eng.set_fusion(fuse)
+        assert eng.fusion() == fuse
+        eng.step(steps)
+        assert eng.steps() == steps
+        blobs.append(eng.save_state())
+        eng.close()
+    for b in blobs[1:]:
+        assert np.array_equal(blobs[0], b)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16_dev", "f16_dev_r32"])
+def test_deep_fusion_bitwise_large_grid(storage):
+    """The default depth from 2^20 cells on (5 steps per launch, 64x16 tiles in
+    XCD order) on a 2900^2 grid, ragged against both tile edges, 23 steps."""
+    import hashlib
+    n = 2900
+    p = scheme.params_for_grid(2, n, 1e-3)
+    u = inputs.random_field_2d(n, 2, umax=0.05 / p.dx)
+    digests = []
+    for fuse in (1, None):
+        eng = _engine(p, u, storage=storage)
+        if fuse is not None:
+            eng.set_fusion(fuse)
+        else:
+            assert eng.fusion() == 5
+        eng.step(23)
+        digests.append(hashlib.sha256(eng.save_state().tobytes()).hexdigest())
+        eng.close()
+    assert digests[0] == digests[1]
+
+
+def test_fusion_settings_and_defaults():
+    small = scheme.params_for_grid(2, 64, 0.01)
+    u = inputs.random_field_box((64, 64), small.dx, seed=3, umax=0.05 / small.dx)
+    eng = _engine(small, u)
+    assert eng.fusion() == 2                     # below 2^20 cells: two steps per launch
+    for bad in (0, 7, -1):
+        with pytest.raises(lbm.LbmError):
+            eng.set_fusion(bad)
+    eng.set_fusion(6)
+    assert eng.fusion() == 6
+    eng.close()
+    neq = _engine(small, u, storage="f16_neq")
+    assert neq.fusion() == 2
+    with pytest.raises(lbm.LbmError):
+        neq.set_fusion(3)
+    neq.close()
+    big = scheme.params_for_grid(2, 1024, 1e-3)
+    eng = _engine(big, inputs.random_field_2d(1024, 0, umax=0.05 / big.dx))
+    assert eng.fusion() == 5
+    eng.close()
+    p3 = scheme.params_for_grid(3, 8, 0.01)
+    e3 = _engine(p3, inputs.abc_flow(8, 0.1, 0.1, 0.1))
+    assert e3.fusion() == 1
+    with pytest.raises(lbm.LbmError):
+        e3.set_fusion(3)
+    e3.close()
+
+
 def test_two_step_fusion_not_available_in_3d():
     p = scheme.params_for_grid(3, 8, 0.01)
     eng = _engine(p, inputs.abc_flow(8, 0.1, 0.1, 0.1))
