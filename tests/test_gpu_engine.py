@@ -353,7 +353,7 @@ def test_deep_fusion_is_bitwise(storage, shape, steps):
         eng.set_fusion(fuse)
         assert eng.fusion() == fuse
         eng.step(steps)
-        assert eng.steps() == steps
+        assert eng.steps == steps
         blobs.append(eng.save_state())
         eng.close()
     for b in blobs[1:]:
