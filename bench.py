@@ -216,7 +216,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic_entry(algo),
-                     "kernel": (f"k_stepK_2d<float,float,64,16,1024,{fuse},true> ({fuse} lattice updates "
+                     "kernel": (f"k_stepKr_2d<float,float,32,16,256,{fuse},true> ({fuse} lattice updates "
                                 "per cell per launch)" if fuse >= 3 else
                                 "k_step2_2d<float,float,256,8,1024> (two lattice updates per cell per launch)"),
                      "bytes_per_launch_algorithmic": algo, "launch_us": round(launch_ms * 1e3, 2),

@@ -390,6 +390,120 @@ __global__ __launch_bounds__(NT) void k_stepK_2d(const TR* __restrict__ sr, cons
   }
 }
 
+// Variant for 4-byte planes with the rest populations in registers: every
+// thread owns the same cells of the extended tile in all K steps (cell e =
+// threadIdx + j NT), so a cell's rest populations, which only that cell reads,
+// never go through LDS; LDS holds the 12 moving planes only (48 B per cell in
+// FP32, against 60 B).  Not used for 16-bit planes: there the compiler turns
+// the last relaxation FMA and the rounding to FP16 into one fused instruction
+// (one rounding) in some kernels and not in others (two roundings), and this
+// kernel's register round trip of the rest values takes the two-rounding form,
+// which differs from the single-step kernel in one FP16 ulp now and then.
+template <typename TR, typename TM, int TX, int TY, int NT, int K, bool XCD = false>
+__global__ __launch_bounds__(NT) void k_stepKr_2d(const TR* __restrict__ sr, const TM* __restrict__ sm,
+                                                   TR* __restrict__ dr, TM* __restrict__ dm, int nx, int ny,
+                                                   int64_t stride, Coef k) {
+  static_assert(K >= 2, "at least two steps");
+  constexpr int H = K - 1, EX = TX + 2 * H, EY = TY + 2 * H, EN = EX * EY;
+  constexpr int PER = (EN + NT - 1) / NT;
+  __shared__ TM s_move[12][EN];
+  int x0, y0;
+  if constexpr (XCD) {
+    const int tiles_x = (nx + TX - 1) / TX;
+    const int nt = tiles_x * ((ny + TY - 1) / TY);
+    const int b = blockIdx.x;
+    const int t = (nt % 8 == 0) ? (b % 8) * (nt / 8) + b / 8 : b;
+    x0 = (t % tiles_x) * TX;
+    y0 = (t / tiles_x) * TY;
+  } else {
+    x0 = blockIdx.x * TX;
+    y0 = blockIdx.y * TY;
+  }
+  float rest[PER][3];   // this thread's cells' rest populations (storage-rounded)
+  float mv[PER][12];    // moving populations computed in the current step
+  // step 1 from HBM over the whole extended tile
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int e = static_cast<int>(threadIdx.x) + j * NT;
+    if (e < EN) {
+      const int ex = e % EX, ey = e / EX;
+      int x = x0 - H + ex, y = y0 - H + ey;
+      x = ((x % nx) + nx) % nx;
+      y = ((y % ny) + ny) % ny;
+      const int64_t c = static_cast<int64_t>(y) * nx + x;
+      float g[3][5];
+      gather_cell<2, TR, TM>(sr, sm, x, y, 0, nx, ny, 1, stride, c, g);
+      collide<2>(g, k);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        TR rr;
+        store_f32(&rr, g[i][0]);
+        rest[j][i] = load_f32(&rr);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) store_f32(&s_move[i * 4 + m][e], g[i][1 + m]);
+      }
+    }
+  }
+  __syncthreads();
+  // steps 2 .. K-1 in LDS over shrinking regions, then step K to HBM
+#pragma unroll
+  for (int st = 2; st <= K; ++st) {
+    const int lo = st - 1;   // region [lo, EX - lo) x [lo, EY - lo)
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int e = static_cast<int>(threadIdx.x) + j * NT;
+      const int ex = e % EX, ey = e / EX;
+      const bool in = e < EN && ex >= lo && ex < EX - lo && ey >= lo && ey < EY - lo;
+      if (in) {
+        float g[3][5];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          g[i][0] = rest[j][i];
+          g[i][1] = load_f32(&s_move[i * 4 + 0][e - 1]);
+          g[i][2] = load_f32(&s_move[i * 4 + 1][e + 1]);
+          g[i][3] = load_f32(&s_move[i * 4 + 2][e - EX]);
+          g[i][4] = load_f32(&s_move[i * 4 + 3][e + EX]);
+        }
+        collide<2>(g, k);
+        if (st < K) {
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            TR rr;
+            store_f32(&rr, g[i][0]);
+            rest[j][i] = load_f32(&rr);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) mv[j][i * 4 + m] = g[i][1 + m];
+          }
+        } else {
+          const int x = x0 + ex - H, y = y0 + ey - H;
+          if (x < nx && y < ny) {
+            const int64_t c = static_cast<int64_t>(y) * nx + x;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+              store_stream(dr + i * stride + c, g[i][0]);
+#pragma unroll
+              for (int m = 0; m < 4; ++m) store_stream(dm + (i * 4 + m) * stride + c, g[i][1 + m]);
+            }
+          }
+        }
+      }
+    }
+    if (st < K) {
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        const int e = static_cast<int>(threadIdx.x) + j * NT;
+        const int ex = e % EX, ey = e / EX;
+        if (e < EN && ex >= lo && ex < EX - lo && ey >= lo && ey < EY - lo) {
+#pragma unroll
+          for (int q = 0; q < 12; ++q) store_f32(&s_move[q][e], mv[j][q]);
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 template <typename TR, typename TM, int TX, int TY, int NT>
 __global__ __launch_bounds__(NT) void k_step2_2d(const TR* __restrict__ sr, const TM* __restrict__ sm,
                                                   TR* __restrict__ dr, TM* __restrict__ dm, int nx, int ny,
@@ -676,12 +790,15 @@ struct Impl {
     }
   }
 
-  // K = 3 .. 6 steps per launch (2D population storages), 64x16 tiles in
-  // XCD-major order: 1024 threads for 4-byte rest planes, 512 for all-16-bit
-  // storage.  From sweeps of this kernel on MI355X (GLUPS at 4096^2 / 2048^2 /
+  // K = 3 .. 6 steps per launch (2D population storages) in XCD-major tile
+  // order.  4-byte planes: k_stepKr_2d (rest populations in registers), 32x16
+  // tiles on 256 threads; 16-bit moving planes: k_stepK_2d, 64x16 tiles on
+  // 1024 threads with FP32 rest planes, 512 for all-16-bit storage.  From
+  // sweeps of the engine's instantiations on MI355X (GLUPS at 4096^2 / 2048^2 /
   // 1024^2, two steps per launch first): FP32 86.9 / 68.5 / 63.8 against 114.3 /
-  // 121.7 / 118.6 at K = 5; FP16 140.3 / 116.4 / 119.5 against 173.9 / 165.6 /
-  // 145.4; FP16 + FP32 rest 124.5 / 108.5 / 100.9 against 197.9 / 189.6 / 163.4.
+  // 121.7 / 118.6 for k_stepK_2d at K = 5 and 130.2 / 132.8 for k_stepKr_2d;
+  // FP16 140.3 / 116.4 / 119.5 against 173.9 / 165.6 / 145.4; FP16 + FP32 rest
+  // 124.5 / 108.5 / 100.9 against 197.9 / 189.6 / 163.4.
   // Deeper fusion moves fewer HBM bytes per step (the state is read about
   // (TX+2K)(TY+2K)/(TX TY) times and written once per K steps) at the price of
   // recomputing the shrinking borders; K = 6..8 and 32x16, 32x32 or 64x32
@@ -689,15 +806,24 @@ struct Impl {
   static constexpr bool kHasStepK = kHasStep2 && !IsNeq<TM>::value && !IsMom<TM>::value;
   static constexpr int kStepKThreads = sizeof(TR) == 2 ? 512 : 1024;
 
+  static constexpr bool kRestInRegisters = sizeof(TR) == 4 && sizeof(TM) == 4;
+
   template <int K>
   static hipError_t launchK(const Geometry& g, const RunCoef& r, const void* src, void* dst, hipStream_t s) {
-    constexpr int TX = 64, TY = 16;
     auto a = planes_of<TR, TM>(const_cast<void*>(src), g.rest_bytes);
     auto b = planes_of<TR, TM>(dst, g.rest_bytes);
     const Coef k = make_coef<float>(r, D, DEV);
-    const int64_t tiles = static_cast<int64_t>((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY);
-    hipLaunchKernelGGL((k_stepK_2d<TR, TM, TX, TY, kStepKThreads, K, true>), dim3(static_cast<uint32_t>(tiles)),
-                       dim3(kStepKThreads), 0, s, a.rest, a.move, b.rest, b.move, g.nx, g.ny, g.stride, k);
+    if constexpr (kRestInRegisters) {
+      constexpr int TX = 32, TY = 16, NT = 256;
+      const int64_t tiles = static_cast<int64_t>((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY);
+      hipLaunchKernelGGL((k_stepKr_2d<TR, TM, TX, TY, NT, K, true>), dim3(static_cast<uint32_t>(tiles)), dim3(NT), 0,
+                         s, a.rest, a.move, b.rest, b.move, g.nx, g.ny, g.stride, k);
+    } else {
+      constexpr int TX = 64, TY = 16;
+      const int64_t tiles = static_cast<int64_t>((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY);
+      hipLaunchKernelGGL((k_stepK_2d<TR, TM, TX, TY, kStepKThreads, K, true>), dim3(static_cast<uint32_t>(tiles)),
+                         dim3(kStepKThreads), 0, s, a.rest, a.move, b.rest, b.move, g.nx, g.ny, g.stride, k);
+    }
     return hipGetLastError();
   }
 
