@@ -264,8 +264,9 @@ def main():
         for storage in ("f32", "f16_dev_r32"):
             log(f"[bench] batch 512 runs {storage}")
             variants[f"batch512_{storage}"] = batch_variant(storage, 1000, probe)
-        log("[bench] batch 512 runs f32, one step per launch")
+        log("[bench] batch 512 runs f32, one and two steps per launch")
         variants["batch512_f32_one_step_per_launch"] = batch_variant("f32", 1000, probe, fuse=1)
+        variants["batch512_f32_two_steps_per_launch"] = batch_variant("f32", 1000, probe, fuse=2)
         log("[bench] Taylor-Green parameter sweep (Fig. 2 plane + Fig. 3 curves) as one batch")
         variants["sweep_tg75_fig2_fig3"] = sweep_variant()
         for dim_s in (2, 3):
@@ -393,11 +394,11 @@ def poiseuille_variant(n: int = 253) -> dict:
             "l2_error_ux": err, "table2_value": 1.368e-06}
 
 
-def batch_variant(storage: str, steps: int, probe: float, n_runs: int = 512, fuse: int = 2) -> dict:
+def batch_variant(storage: str, steps: int, probe: float, n_runs: int = 512, fuse: int | None = None) -> dict:
     """The batch workload: n_runs independent 2D runs, sizes 64^2..1024^2,
     nu log-uniform in [1e-4, 1e-2], k^-3 fields at Mach 0.05, all advanced
-    `steps` steps by persistent launches replayed from graphs: two steps per
-    launch (fuse = 2, the 2D default) or one (fuse = 1)."""
+    `steps` steps by persistent launches replayed from graphs: five steps per
+    launch (the 2D default, fuse = None), two or one."""
     import torch
     import inputs
     from paper_2607_24059_amd import batch as B
@@ -411,8 +412,10 @@ def batch_variant(storage: str, steps: int, probe: float, n_runs: int = 512, fus
     b = B.Batch.create(2, storage, runs, u0s)
     del u0s
     b.autotune(None)
-    b.set_fusion(fuse)
-    b.step(4)
+    if fuse is not None:
+        b.set_fusion(fuse)
+    fuse = b.fusion()
+    b.step(10)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)

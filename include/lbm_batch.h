@@ -8,12 +8,15 @@
  * batch is ONE launch of a persistent kernel whose blocks walk a list of
  * 256-cell tiles covering every run; the tile shape of each size class
  * (64x4, 128x2 or 256x1 cells in 2D) is chosen by lbm_batch_autotune.  Steps
- * are replayed from a HIP graph.  In 2D the default launch advances two steps:
- * a second persistent kernel walks 64 x 8-cell tiles, advances each tile and
- * its one-cell border by one step into LDS and the tile by the second step
- * (lbm_batch_set_fusion).  The per-cell update is the same device code as
- * lbm_step, so a run advanced in a batch is bit-identical to the same run
- * advanced alone, with either setting.  The split FP16 (LBM_F16_NEQ) and FP64
+ * are replayed from a HIP graph.  In 2D two more persistent kernels advance
+ * several steps per launch (lbm_batch_set_fusion): one walks 64 x 8-cell tiles
+ * and advances two steps (each tile and its one-cell border by one step into
+ * LDS, the tile by the second); the default one walks the single-run engine's
+ * multi-step tiles and advances five (the tile and a four-cell border by one
+ * step into LDS, three more steps inside LDS on shrinking regions, the tile by
+ * the fifth).  The per-cell update is the same device code as lbm_step, so a
+ * run advanced in a batch is bit-identical to the same run advanced alone,
+ * with any setting.  The split FP16 (LBM_F16_NEQ) and FP64
  * storages are not available in a batch.
  *
  * Conventions are those of lbm.h: status codes only, caller-owned device
@@ -80,12 +83,19 @@ int32_t lbm_batch_tile_width(const lbm_batch* b, int32_t run);
  * means one block per tile); chosen by lbm_batch_autotune. */
 int32_t lbm_batch_grid(const lbm_batch* b);
 
-/* Blocks of the two-step launch (0 if the batch has none, i.e. in 3D). */
+/* Blocks of the current multi-step launch: the five-step kernel's when the
+ * fusion is 5, else the two-step kernel's (0 if the batch has none, i.e. in
+ * 3D).  Chosen by lbm_batch_autotune. */
 int32_t lbm_batch_fused_grid(const lbm_batch* b);
 
-/* Steps per launch: 1 (one-step kernel) or 2 (two-step kernel, 2D only, the
- * default there); LBM_EINVAL otherwise.  Either gives the same states. */
+/* Steps per launch: 1 (one-step kernel), 2 (two-step kernel) or 5 (five-step
+ * kernel, the default); 2 and 5 in 2D only; LBM_EINVAL otherwise.  Every
+ * setting gives the same states.  A remainder shorter than the setting runs
+ * as shorter launches. */
 lbm_status lbm_batch_set_fusion(lbm_batch* b, int32_t steps_per_launch);
+
+/* The current number of steps per launch (0 for NULL). */
+int32_t lbm_batch_fusion(const lbm_batch* b);
 
 void lbm_batch_destroy(lbm_batch* b);
 

@@ -42,6 +42,7 @@ SIGNATURES = {
     "lbm_batch_grid": (C.c_int32, [C.c_void_p]),
     "lbm_batch_fused_grid": (C.c_int32, [C.c_void_p]),
     "lbm_batch_set_fusion": (C.c_int, [C.c_void_p, C.c_int32]),
+    "lbm_batch_fusion": (C.c_int32, [C.c_void_p]),
     "lbm_batch_destroy": (None, [C.c_void_p]),
 }
 
@@ -134,6 +135,10 @@ def lbm_batch_set_fusion(h: int, steps_per_launch: int) -> None:
     _ok(blib().lbm_batch_set_fusion(C.c_void_p(h), steps_per_launch), "lbm_batch_set_fusion")
 
 
+def lbm_batch_fusion(h: int) -> int:
+    return int(blib().lbm_batch_fusion(C.c_void_p(h)))
+
+
 def lbm_batch_destroy(h: int) -> None:
     blib().lbm_batch_destroy(C.c_void_p(h))
 
@@ -193,6 +198,9 @@ class Batch:
 
     def set_fusion(self, steps_per_launch: int) -> None:
         lbm_batch_set_fusion(self.handle, steps_per_launch)
+
+    def fusion(self) -> int:
+        return lbm_batch_fusion(self.handle)
 
     def tile_width(self, r: int) -> int:
         return lbm_batch_tile_width(self.handle, r)

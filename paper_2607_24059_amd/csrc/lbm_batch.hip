@@ -25,6 +25,7 @@
 #include "lbm.h"
 #include "lbm_batch.h"
 #include "lbm_device.hpp"
+#include "lbm_fused.hpp"
 #include "lbm_internal.hpp"
 
 namespace lbm {
@@ -136,7 +137,76 @@ __global__ __launch_bounds__(kT2N) void k_batch_step2(const BatchRun* __restrict
   }
 }
 
+// kBatchK steps per launch (2D): the single-run engine's multi-step tiles
+// (lbm_fused.hpp) walked by a persistent grid, each tile wrapping periodically
+// in its own run; the same tile shapes as the single-run engine (32x16 cells
+// on 256 threads with the rest populations in registers for 4-byte planes,
+// 64x16 on 1024 / 512 threads otherwise), so again bit-identical to single
+// steps.
+constexpr int kBatchK = 5;
+
+template <typename TR, typename TM>
+struct BatchKShape {
+  static constexpr bool kRegs = sizeof(TR) == 4 && sizeof(TM) == 4;
+  static constexpr int TX = kRegs ? 32 : 64, TY = 16;
+  static constexpr int NT = kRegs ? 256 : (sizeof(TR) == 2 ? 512 : 1024);
+};
+constexpr int kTKXmin = 32, kTKY = 16;  // smallest tile width (sizes the tile list)
+
+template <typename TR, typename TM>
+__global__ __launch_bounds__((BatchKShape<TR, TM>::NT)) void k_batch_stepK(const BatchRun* __restrict__ runs,
+                                                                         const BatchTile* __restrict__ tiles,
+                                                                         int64_t ntiles, char* __restrict__ base,
+                                                                         int parity) {
+  using S = BatchKShape<TR, TM>;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const BatchTile tl = tiles[t];
+    const BatchRun& r = runs[tl.run];
+    const auto a = planes_of<TR, TM>(base + r.off[parity], static_cast<size_t>(r.rest_bytes));
+    const auto b = planes_of<TR, TM>(base + r.off[parity ^ 1], static_cast<size_t>(r.rest_bytes));
+    if constexpr (S::kRegs) {
+      using T = TileKr<TR, TM, S::TX, S::TY, S::NT, kBatchK>;
+      __shared__ TM s_move[12][T::EN];
+      T::run(a.rest, a.move, b.rest, b.move, tl.x0, tl.y0, r.nx, r.ny, r.stride, r.k, s_move);
+    } else {
+      using T = TileK<TR, TM, S::TX, S::TY, S::NT, kBatchK>;
+      __shared__ TR s_rest[3][T::EN];
+      __shared__ TM s_move[12][T::EN];
+      T::run(a.rest, a.move, b.rest, b.move, tl.x0, tl.y0, r.nx, r.ny, r.stride, r.k, s_rest, s_move);
+    }
+    __syncthreads();  // the next tile overwrites the LDS tile
+  }
+}
+
 using BatchKernel = void (*)(const BatchRun*, const BatchTile*, int64_t, char*, int);
+
+struct BatchKKernel {
+  BatchKernel fn = nullptr;
+  int tx = 0, threads = 0;
+};
+
+template <typename TR, typename TM>
+BatchKKernel batch_k_of() {
+  using S = BatchKShape<TR, TM>;
+  return BatchKKernel{&k_batch_stepK<TR, TM>, S::TX, S::NT};
+}
+
+BatchKKernel batch_kernelK(int dim, int storage) {
+  if (dim != 2) return {};
+  switch (storage) {
+    case LBM_F32: case LBM_F32_RAW: return batch_k_of<float, float>();
+    case LBM_F16_DEV: return batch_k_of<_Float16, _Float16>();
+    case LBM_BF16_DEV: return batch_k_of<bf16, bf16>();
+    case LBM_F16_DEV_R32: return batch_k_of<float, _Float16>();
+    case LBM_BF16_DEV_R32: return batch_k_of<float, bf16>();
+  }
+  return {};
+}
+
+// multi-step tiles of one 2D run for tile width tx (at most this many for any width >= kTKXmin)
+int64_t tilesK_of(const Geometry& g, int tx) {
+  return static_cast<int64_t>((g.nx + tx - 1) / tx) * ((g.ny + kTKY - 1) / kTKY);
+}
 
 BatchKernel batch_kernel2(int dim, int storage) {
   if (dim != 2) return nullptr;
@@ -218,8 +288,14 @@ struct lbm_batch {
   BatchTile* d_tiles2 = nullptr;  // fused (two-step) tiles, 2D only
   int64_t ntiles2 = 0;
   int grid2 = 0;                  // persistent grid of the fused kernel
-  int fuse = 1;                   // steps per launch: 1, or 2 (fused kernel)
+  int fuse = 1;                   // steps per launch: 1, 2 (two-step kernel) or kBatchK
   BatchKernel kernel2 = nullptr;
+  BatchKKernel kernelK;           // kBatchK steps per launch (2D population storages)
+  BatchTile* d_tilesK = nullptr;
+  int64_t ntilesK = 0;
+  int gridK = 0;
+  hipGraphExec_t exec_mainK[2] = {nullptr, nullptr};  // kFusedGraphLaunches K-step launches from parity p
+  hipGraphExec_t exec_oneK[2] = {nullptr, nullptr};   // one K-step launch from parity p
   hipGraphExec_t exec_main2[2] = {nullptr, nullptr};  // kFusedGraphLaunches fused launches from parity p
   hipGraphExec_t exec_two[2] = {nullptr, nullptr};    // one fused launch from parity p
   int64_t total_cells = 0;
@@ -258,8 +334,8 @@ int default_bx(const Geometry& g) {
 }
 
 struct Layout {
-  size_t runs_off, tiles_off, tiles2_off, bufs_off, total;
-  int64_t max_tiles, tiles2;
+  size_t runs_off, tiles_off, tiles2_off, tilesK_off, bufs_off, total;
+  int64_t max_tiles, tiles2, tilesK;
   std::vector<int64_t> off0, off1;
 };
 
@@ -267,19 +343,24 @@ Layout layout(int dim, int storage, int nruns, const lbm_run_spec* runs) {
   Layout L;
   L.max_tiles = 0;
   L.tiles2 = 0;
+  L.tilesK = 0;
   std::vector<Geometry> geo;
   for (int r = 0; r < nruns; ++r) {
     const Geometry g = make_geometry(dim, storage, runs[r].n);
     int64_t mt = 0;
     for (int bx = 64; bx <= 256; bx *= 2) mt = std::max(mt, tiles_of(g, bx));
     L.max_tiles += mt;
-    if (dim == 2) L.tiles2 += tiles2_of(g);
+    if (dim == 2) {
+      L.tiles2 += tiles2_of(g);
+      L.tilesK += tilesK_of(g, kTKXmin);
+    }
     geo.push_back(g);
   }
   L.runs_off = 0;
   L.tiles_off = align256(sizeof(BatchRun) * nruns);
   L.tiles2_off = align256(L.tiles_off + sizeof(BatchTile) * L.max_tiles);
-  L.bufs_off = align256(L.tiles2_off + sizeof(BatchTile) * L.tiles2);
+  L.tilesK_off = align256(L.tiles2_off + sizeof(BatchTile) * L.tiles2);
+  L.bufs_off = align256(L.tilesK_off + sizeof(BatchTile) * L.tilesK);
   size_t off = L.bufs_off;
   for (int r = 0; r < nruns; ++r) {
     L.off0.push_back(static_cast<int64_t>(off));
@@ -334,6 +415,14 @@ hipError_t launch_step2(lbm_batch* b, int parity, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_stepK(lbm_batch* b, int parity, hipStream_t s) {
+  if (b->ntilesK == 0) return hipSuccess;
+  const unsigned grid = static_cast<unsigned>(std::min<int64_t>(b->ntilesK, b->gridK));
+  hipLaunchKernelGGL(b->kernelK.fn, dim3(grid), dim3(b->kernelK.threads), 0, s, b->d_runs, b->d_tilesK, b->ntilesK,
+                     b->ws, parity);
+  return hipGetLastError();
+}
+
 void destroy_graphs(lbm_batch* b) {
   auto drop = [](hipGraphExec_t& e) {
     if (e) hipGraphExecDestroy(e);
@@ -344,6 +433,8 @@ void destroy_graphs(lbm_batch* b) {
     drop(b->exec_one[p]);
     drop(b->exec_main2[p]);
     drop(b->exec_two[p]);
+    drop(b->exec_mainK[p]);
+    drop(b->exec_oneK[p]);
   }
 }
 
@@ -394,6 +485,32 @@ hipError_t rebuild(lbm_batch* b) {
       if (e == hipSuccess) e = make_graph(b, b->kernel2, b->d_tiles2, b->ntiles2, b->grid2, kT2N, p, 1, &b->exec_two[p]);
     }
   }
+  if (b->kernelK.fn) {
+    for (int p = 0; p < 2 && e == hipSuccess; ++p) {
+      e = make_graph(b, b->kernelK.fn, b->d_tilesK, b->ntilesK, b->gridK, b->kernelK.threads, p,
+                     kFusedGraphLaunches, &b->exec_mainK[p]);
+      if (e == hipSuccess)
+        e = make_graph(b, b->kernelK.fn, b->d_tilesK, b->ntilesK, b->gridK, b->kernelK.threads, p, 1,
+                       &b->exec_oneK[p]);
+    }
+  }
+  return e;
+}
+
+// The multi-step tile list (fixed, like the two-step one).
+hipError_t upload_tilesK(lbm_batch* b) {
+  std::vector<BatchTile> t;
+  const int tx = b->kernelK.tx;
+  for (int r = 0; r < b->nruns; ++r) {
+    const Geometry& g = b->geo[r];
+    for (int y0 = 0; y0 < g.ny; y0 += kTKY)
+      for (int x0 = 0; x0 < g.nx; x0 += tx) t.push_back(BatchTile{r, x0, y0, 0, static_cast<int16_t>(log2i(tx))});
+  }
+  b->ntilesK = static_cast<int64_t>(t.size());
+  if (t.empty()) return hipSuccess;
+  hipError_t e = hipMemcpyAsync(b->d_tilesK, t.data(), t.size() * sizeof(BatchTile), hipMemcpyHostToDevice,
+                                b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   return e;
 }
 
@@ -475,11 +592,13 @@ lbm_status lbm_batch_init(lbm_batch** out, int32_t dim, int32_t storage, int32_t
   b->d_runs = reinterpret_cast<BatchRun*>(b->ws + L.runs_off);
   b->d_tiles = reinterpret_cast<BatchTile*>(b->ws + L.tiles_off);
   b->d_tiles2 = reinterpret_cast<BatchTile*>(b->ws + L.tiles2_off);
+  b->d_tilesK = reinterpret_cast<BatchTile*>(b->ws + L.tilesK_off);
   b->max_tiles = L.max_tiles;
   b->stream = static_cast<hipStream_t>(hip_stream);
   b->kernel = batch_kernel(dim, storage);
   b->kernel2 = batch_kernel2(dim, storage);
-  b->fuse = b->kernel2 ? 2 : 1;
+  b->kernelK = batch_kernelK(dim, storage);
+  b->fuse = b->kernelK.fn ? kBatchK : b->kernel2 ? 2 : 1;
   const Ops* ops = ops_for(dim, storage);
   const bool devn = storage_is_deviation(storage);
 
@@ -524,7 +643,9 @@ lbm_status lbm_batch_init(lbm_batch** out, int32_t dim, int32_t storage, int32_t
     b->cus = cus;
     b->grid = 8 * cus;  // 8 resident 256-thread blocks per CU at the kernel's register use
     b->grid2 = 2 * cus;  // two resident 512-thread fused blocks per CU (LDS tile of up to 40 KB)
+    b->gridK = 4 * cus;
     if (b->kernel2) e = upload_tiles2(b);
+    if (e == hipSuccess && b->kernelK.fn) e = upload_tilesK(b);
     if (e == hipSuccess) e = rebuild(b);
   }
   if (e != hipSuccess) {
@@ -645,6 +766,33 @@ lbm_status lbm_batch_autotune(lbm_batch* b, const char* cache_path) {
     b->grid2 = best_pc > 0 ? best_pc * b->cus : static_cast<int>(std::min<int64_t>(b->ntiles2, 0x7fffffff));
     fresh.emplace_back(-2, best_pc);
   }
+  // persistent grid of the multi-step kernel (class -3), as for the two-step one
+  if (e == hipSuccess && b->kernelK.fn && cached.count(-3)) {
+    const int per_cu = cached[-3];
+    b->gridK = per_cu > 0 ? per_cu * b->cus : static_cast<int>(std::min<int64_t>(b->ntilesK, 0x7fffffff));
+  } else if (e == hipSuccess && b->kernelK.fn) {
+    const int cands[] = {1, 2, 4, 8, 0};
+    float best = 1e30f;
+    int best_pc = 4;
+    for (int pc : cands) {
+      if (e != hipSuccess) break;
+      b->gridK = pc > 0 ? pc * b->cus : static_cast<int>(std::min<int64_t>(b->ntilesK, 0x7fffffff));
+      // a launch reads the current buffer and writes the other: the state is kept
+      for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch_stepK(b, b->parity, b->stream);
+      if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+      for (int it = 0; it < 5 && e == hipSuccess; ++it) e = launch_stepK(b, b->parity, b->stream);
+      if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess && ms < best) {
+        best = ms;
+        best_pc = pc;
+      }
+    }
+    b->gridK = best_pc > 0 ? best_pc * b->cus : static_cast<int>(std::min<int64_t>(b->ntilesK, 0x7fffffff));
+    fresh.emplace_back(-3, best_pc);
+  }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (e == hipSuccess) e = rebuild(b);
@@ -662,6 +810,31 @@ lbm_status lbm_batch_autotune(lbm_batch* b, const char* cache_path) {
 lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
   if (!b || nsteps < 0) return LBM_EINVAL;
   hipError_t e = hipSuccess;
+  if (b->fuse == kBatchK) {
+    // multi-step launches, then two-step and single-step ones for the remainder
+    while (nsteps > 0 && e == hipSuccess) {
+      int adv = 1, flip = 1;
+      if (nsteps >= kBatchK * kFusedGraphLaunches) {
+        e = hipGraphLaunch(b->exec_mainK[b->parity], b->stream);  // even launch count: parity kept
+        adv = kBatchK * kFusedGraphLaunches;
+        flip = 0;
+      } else if (nsteps >= kBatchK) {
+        e = hipGraphLaunch(b->exec_oneK[b->parity], b->stream);
+        adv = kBatchK;
+      } else if (nsteps >= 2) {
+        e = hipGraphLaunch(b->exec_two[b->parity], b->stream);
+        adv = 2;
+      } else {
+        e = hipGraphLaunch(b->exec_one[b->parity], b->stream);
+      }
+      if (e == hipSuccess) {
+        nsteps -= adv;
+        b->steps += adv;
+        b->parity ^= flip;
+      }
+    }
+    return dev(e);
+  }
   if (b->fuse == 2) {
     // fused launches advance two steps and move the state to the other buffer
     while (nsteps > 0 && e == hipSuccess) {
@@ -726,14 +899,22 @@ lbm_status lbm_batch_info(const lbm_batch* b, int64_t* total_cells, int64_t* til
 
 int32_t lbm_batch_grid(const lbm_batch* b) { return b ? b->grid : -1; }
 
-int32_t lbm_batch_fused_grid(const lbm_batch* b) { return b ? (b->kernel2 ? b->grid2 : 0) : -1; }
+int32_t lbm_batch_fused_grid(const lbm_batch* b) {
+  if (!b) return -1;
+  if (b->fuse == kBatchK) return b->gridK;
+  return b->kernel2 ? b->grid2 : 0;
+}
 
 lbm_status lbm_batch_set_fusion(lbm_batch* b, int32_t steps_per_launch) {
-  if (!b || steps_per_launch < 1 || steps_per_launch > 2) return LBM_EINVAL;
+  if (!b) return LBM_EINVAL;
   if (steps_per_launch == 2 && !b->kernel2) return LBM_EINVAL;
+  if (steps_per_launch == kBatchK && !b->kernelK.fn) return LBM_EINVAL;
+  if (steps_per_launch != 1 && steps_per_launch != 2 && steps_per_launch != kBatchK) return LBM_EINVAL;
   b->fuse = steps_per_launch;
   return LBM_OK;
 }
+
+int32_t lbm_batch_fusion(const lbm_batch* b) { return b ? b->fuse : 0; }
 
 int32_t lbm_batch_tile_width(const lbm_batch* b, int32_t run) {
   if (!b || run < 0 || run >= b->nruns) return -1;

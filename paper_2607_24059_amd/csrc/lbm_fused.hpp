@@ -1,0 +1,242 @@
+// Tiles of the fused multi-step update (2D population storages), shared by
+// the single-run kernels (lbm_kernels.hip) and the batch engine
+// (lbm_batch.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_device.hpp"
+
+namespace lbm {
+
+// ----------------------------------------------------------------------------
+// K >= 3 steps in one launch (2D, population storages): the block advances its
+// TX x TY tile plus a (K-1)-cell border by one step from HBM into LDS, then
+// K-2 more steps in LDS, each over a region one cell narrower on every side
+// (the cells whose inputs are still valid), and the tile by the last step to
+// HBM.  A step inside LDS gathers and relaxes its cells into registers, waits
+// for every thread, and writes them back over the same LDS slots, so one LDS
+// buffer serves all stages.  Every intermediate value is rounded to the
+// storage type when it is written to LDS, as a store to HBM would round it, so
+// the result equals K single steps bit for bit.  Each state value is read from
+// HBM about (TX+2K)(TY+2K)/(TX TY) times and written once per K steps.
+// ----------------------------------------------------------------------------
+template <typename TR, typename TM, int EX, int EN>
+__device__ __forceinline__ void gather_lds(const TR (&s_rest)[3][EN], const TM (&s_move)[12][EN], int e,
+                                           float (&g)[3][5]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    g[i][0] = load_f32(&s_rest[i][e]);
+    g[i][1] = load_f32(&s_move[i * 4 + 0][e - 1]);   // +x from x-1
+    g[i][2] = load_f32(&s_move[i * 4 + 1][e + 1]);   // -x from x+1
+    g[i][3] = load_f32(&s_move[i * 4 + 2][e - EX]);  // +y from y-1
+    g[i][4] = load_f32(&s_move[i * 4 + 3][e + EX]);  // -y from y+1
+  }
+}
+
+// one step inside LDS over the region [LO, EX - LO) x [LO, EY - LO)
+template <typename TR, typename TM, int EX, int EY, int NT, int LO>
+__device__ __forceinline__ void lds_stage(TR (&s_rest)[3][EX * EY], TM (&s_move)[12][EX * EY], const Coef& k) {
+  constexpr int EN = EX * EY, RX = EX - 2 * LO, RY = EY - 2 * LO, RN = RX * RY;
+  constexpr int PER = (RN + NT - 1) / NT;
+  float keep[PER][3][5];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int t = static_cast<int>(threadIdx.x) + j * NT;
+    if (t < RN) {
+      const int e = (LO + t / RX) * EX + LO + t % RX;
+      gather_lds<TR, TM, EX, EN>(s_rest, s_move, e, keep[j]);
+      collide<2>(keep[j], k);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int t = static_cast<int>(threadIdx.x) + j * NT;
+    if (t < RN) {
+      const int e = (LO + t / RX) * EX + LO + t % RX;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        store_f32(&s_rest[i][e], keep[j][i][0]);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) store_f32(&s_move[i * 4 + m][e], keep[j][i][1 + m]);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <typename TR, typename TM, int EX, int EY, int NT, int LO, int LAST>
+__device__ __forceinline__ void lds_stages(TR (&s_rest)[3][EX * EY], TM (&s_move)[12][EX * EY], const Coef& k) {
+  if constexpr (LO <= LAST) {
+    lds_stage<TR, TM, EX, EY, NT, LO>(s_rest, s_move, k);
+    lds_stages<TR, TM, EX, EY, NT, LO + 1, LAST>(s_rest, s_move, k);
+  }
+}
+
+// XCD: with a one-dimensional grid, consecutive blocks go to the eight XCDs in
+// turn; XCD-major numbering gives each XCD a contiguous band of tiles, so the
+// borders that neighbouring tiles share are read through the same L2.
+__device__ __forceinline__ void xcd_tile_origin(int b, int nx, int ny, int TX, int TY, int* x0, int* y0) {
+  const int tiles_x = (nx + TX - 1) / TX;
+  const int nt = tiles_x * ((ny + TY - 1) / TY);
+  const int t = (nt % 8 == 0) ? (b % 8) * (nt / 8) + b / 8 : b;
+  *x0 = (t % tiles_x) * TX;
+  *y0 = (t / tiles_x) * TY;
+}
+
+// The K-step tile with its origin (x0, y0); s_rest and s_move are the block's
+// LDS tile (TileK<..>::EN cells).
+template <typename TR, typename TM, int TX, int TY, int NT, int K>
+struct TileK {
+  static_assert(K >= 3, "two steps per launch use the two-step tile");
+  static constexpr int H = K - 1, EX = TX + 2 * H, EY = TY + 2 * H, EN = EX * EY;
+
+  __device__ static void run(const TR* __restrict__ sr, const TM* __restrict__ sm, TR* __restrict__ dr,
+                             TM* __restrict__ dm, int x0, int y0, int nx, int ny, int64_t stride, const Coef& k,
+                             TR (&s_rest)[3][EN], TM (&s_move)[12][EN]) {
+    // first step, from HBM, over the whole extended tile
+    for (int e = threadIdx.x; e < EN; e += NT) {
+      const int ex = e % EX, ey = e / EX;
+      int x = x0 - H + ex, y = y0 - H + ey;
+      x = ((x % nx) + nx) % nx;  // the border may wrap (several times on tiny grids)
+      y = ((y % ny) + ny) % ny;
+      const int64_t c = static_cast<int64_t>(y) * nx + x;
+      float g[3][5];
+      gather_cell<2, TR, TM>(sr, sm, x, y, 0, nx, ny, 1, stride, c, g);
+      collide<2>(g, k);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        store_f32(&s_rest[i][e], g[i][0]);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) store_f32(&s_move[i * 4 + m][e], g[i][1 + m]);
+      }
+    }
+    __syncthreads();
+    // steps 2 .. K-1 in LDS
+    lds_stages<TR, TM, EX, EY, NT, 1, H - 1>(s_rest, s_move, k);
+    // last step, from LDS to HBM, over the tile
+    for (int t = threadIdx.x; t < TX * TY; t += NT) {
+      const int tx = t % TX, ty = t / TX;
+      const int x = x0 + tx, y = y0 + ty;
+      if (x >= nx || y >= ny) continue;
+      float g[3][5];
+      gather_lds<TR, TM, EX, EN>(s_rest, s_move, (ty + H) * EX + (tx + H), g);
+      collide<2>(g, k);
+      const int64_t c = static_cast<int64_t>(y) * nx + x;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        store_stream(dr + i * stride + c, g[i][0]);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) store_stream(dm + (i * 4 + m) * stride + c, g[i][1 + m]);
+      }
+    }
+  }
+};
+
+// Variant for 4-byte planes with the rest populations in registers: every
+// thread owns the same cells of the extended tile in all K steps (cell e =
+// threadIdx + j NT), so a cell's rest populations, which only that cell reads,
+// never go through LDS; LDS holds the 12 moving planes only (48 B per cell in
+// FP32, against 60 B).  Not used for 16-bit planes: there the compiler turns
+// the last relaxation FMA and the rounding to FP16 into one fused instruction
+// (one rounding) in some kernels and not in others (two roundings), and this
+// kernel's register round trip of the rest values takes the two-rounding form,
+// which differs from the single-step kernel in one FP16 ulp now and then.
+template <typename TR, typename TM, int TX, int TY, int NT, int K>
+struct TileKr {
+  static_assert(K >= 2, "at least two steps");
+  static constexpr int H = K - 1, EX = TX + 2 * H, EY = TY + 2 * H, EN = EX * EY;
+  static constexpr int PER = (EN + NT - 1) / NT;
+
+  __device__ static void run(const TR* __restrict__ sr, const TM* __restrict__ sm, TR* __restrict__ dr,
+                             TM* __restrict__ dm, int x0, int y0, int nx, int ny, int64_t stride, const Coef& k,
+                             TM (&s_move)[12][EN]) {
+    float rest[PER][3];   // this thread's cells' rest populations (storage-rounded)
+    float mv[PER][12];    // moving populations computed in the current step
+    // step 1 from HBM over the whole extended tile
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int e = static_cast<int>(threadIdx.x) + j * NT;
+      if (e < EN) {
+        const int ex = e % EX, ey = e / EX;
+        int x = x0 - H + ex, y = y0 - H + ey;
+        x = ((x % nx) + nx) % nx;
+        y = ((y % ny) + ny) % ny;
+        const int64_t c = static_cast<int64_t>(y) * nx + x;
+        float g[3][5];
+        gather_cell<2, TR, TM>(sr, sm, x, y, 0, nx, ny, 1, stride, c, g);
+        collide<2>(g, k);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          TR rr;
+          store_f32(&rr, g[i][0]);
+          rest[j][i] = load_f32(&rr);
+#pragma unroll
+          for (int m = 0; m < 4; ++m) store_f32(&s_move[i * 4 + m][e], g[i][1 + m]);
+        }
+      }
+    }
+    __syncthreads();
+    // steps 2 .. K-1 in LDS over shrinking regions, then step K to HBM
+#pragma unroll
+    for (int st = 2; st <= K; ++st) {
+      const int lo = st - 1;   // region [lo, EX - lo) x [lo, EY - lo)
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        const int e = static_cast<int>(threadIdx.x) + j * NT;
+        const int ex = e % EX, ey = e / EX;
+        const bool in = e < EN && ex >= lo && ex < EX - lo && ey >= lo && ey < EY - lo;
+        if (in) {
+          float g[3][5];
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            g[i][0] = rest[j][i];
+            g[i][1] = load_f32(&s_move[i * 4 + 0][e - 1]);
+            g[i][2] = load_f32(&s_move[i * 4 + 1][e + 1]);
+            g[i][3] = load_f32(&s_move[i * 4 + 2][e - EX]);
+            g[i][4] = load_f32(&s_move[i * 4 + 3][e + EX]);
+          }
+          collide<2>(g, k);
+          if (st < K) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+              TR rr;
+              store_f32(&rr, g[i][0]);
+              rest[j][i] = load_f32(&rr);
+#pragma unroll
+              for (int m = 0; m < 4; ++m) mv[j][i * 4 + m] = g[i][1 + m];
+            }
+          } else {
+            const int x = x0 + ex - H, y = y0 + ey - H;
+            if (x < nx && y < ny) {
+              const int64_t c = static_cast<int64_t>(y) * nx + x;
+#pragma unroll
+              for (int i = 0; i < 3; ++i) {
+                store_stream(dr + i * stride + c, g[i][0]);
+#pragma unroll
+                for (int m = 0; m < 4; ++m) store_stream(dm + (i * 4 + m) * stride + c, g[i][1 + m]);
+              }
+            }
+          }
+        }
+      }
+      if (st < K) {
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+          const int e = static_cast<int>(threadIdx.x) + j * NT;
+          const int ex = e % EX, ey = e / EX;
+          if (e < EN && ex >= lo && ex < EX - lo && ey >= lo && ey < EY - lo) {
+#pragma unroll
+            for (int q = 0; q < 12; ++q) store_f32(&s_move[q][e], mv[j][q]);
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+};
+
+}  // namespace lbm

@@ -16,7 +16,7 @@ is used.
   the density diffusivity of the modified equations (Section 3).
 
 Every run advances in one batch (include/lbm_batch.h): one persistent launch
-per two time steps for all runs together.  The error of each run is evaluated
+per five time steps for all runs together.  The error of each run is evaluated
 from its FP64 moments.
 """
 
@@ -103,7 +103,7 @@ class SweepResult:
         return self.errors[start:start + nw * na].reshape(na, nw)
 
 
-def run(points, tg: TaylorGreen = TaylorGreen(), storage: str = "f32", fuse: int = 2,
+def run(points, tg: TaylorGreen = TaylorGreen(), storage: str = "f32", fuse: int | None = None,
         autotune: bool = False, keep_moments: bool = False):
     """Advance one run per (omega_rho, alpha_rho, omega_q) point in one batch
     to t_final and return the errors on u_x (and, with keep_moments, the
@@ -117,7 +117,8 @@ def run(points, tg: TaylorGreen = TaylorGreen(), storage: str = "f32", fuse: int
     try:
         if autotune:
             b.autotune()
-        b.set_fusion(fuse)
+        if fuse is not None:
+            b.set_fusion(fuse)
         steps = tg.steps()
         torch.cuda.synchronize()
         t0 = time.perf_counter()

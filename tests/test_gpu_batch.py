@@ -47,17 +47,20 @@ def _single(dim, storage, run, u0, steps):
     return out
 
 
-@pytest.mark.parametrize("fuse", [2, 1])
-@pytest.mark.parametrize("storage,steps", [("f32", 73), ("f16_dev_r32", 120), ("bf16_dev", 51)])
+@pytest.mark.parametrize("fuse", [5, 2, 1])
+@pytest.mark.parametrize("storage,steps", [("f32", 73), ("f16_dev_r32", 120), ("bf16_dev", 51), ("f16_dev", 8),
+                                           ("bf16_dev_r32", 17), ("f32_raw", 126)])
 def test_batch_bitwise_equals_single_runs_2d(storage, steps, fuse):
-    """Either kernel (two steps per launch, the 2D default, or one) gives each
-    run's single-run state bit for bit; 73 and 51 steps end on a one-step
-    launch, 120 on the 48-step graph plus fused launches."""
+    """Every kernel (five steps per launch, the 2D default, two or one) gives
+    each run's single-run state bit for bit; the step counts end on shorter
+    launches (73 = 14 x 5 + 2 + 1) or use the graphs of 24 launches (120, 126)."""
     runs, u0s = _mixed_runs(2)
     print(f"[batch] 2D {storage} {len(runs)} runs {steps} steps fuse={fuse}", flush=True)
     b = B.Batch.create(2, storage, runs, u0s)
+    assert b.fusion() == 5
     assert b.fused_grid() > 0
     b.set_fusion(fuse)
+    assert b.fusion() == fuse
     b.step(steps)
     cells, tiles, done = b.info()
     assert done == steps
@@ -72,9 +75,10 @@ def test_batch_bitwise_equals_single_runs_2d(storage, steps, fuse):
 def test_batch_bitwise_equals_single_runs_3d():
     runs, u0s = _mixed_runs(3)
     b = B.Batch.create(3, "f32", runs, u0s)
-    assert b.fused_grid() == 0
-    with pytest.raises(lbm.LbmError):
-        b.set_fusion(2)
+    assert b.fused_grid() == 0 and b.fusion() == 1
+    for bad in (2, 5, 3, 0):
+        with pytest.raises(lbm.LbmError):
+            b.set_fusion(bad)
     b.step(37)
     for r, (run, u0) in enumerate(zip(runs, u0s)):
         rho, q = b.moments(r)
@@ -84,12 +88,15 @@ def test_batch_bitwise_equals_single_runs_3d():
 
 
 def test_switching_fusion_mid_run_is_bitwise():
-    """Alternating one- and two-step launches (buffer parity changes) keeps the
-    single-run states."""
+    """Alternating one-, two- and five-step launches (buffer parity changes)
+    keeps the single-run states."""
     runs, u0s = _mixed_runs(2)
     b = B.Batch.create(2, "f32", runs, u0s)
+    for bad in (3, 4, 6):
+        with pytest.raises(lbm.LbmError):
+            b.set_fusion(bad)
     total = 0
-    for fuse, n in ((2, 5), (1, 3), (2, 50), (1, 1), (2, 2)):
+    for fuse, n in ((2, 5), (5, 7), (1, 3), (2, 50), (5, 121), (1, 1), (5, 10), (2, 2)):
         b.set_fusion(fuse)
         b.step(n)
         total += n
@@ -162,9 +169,9 @@ def test_full_batch_workload_sampled():
         u0s.append(inputs.random_field_2d(n, s["seed"], umax=0.05 / dx))
     b = B.Batch.create(2, "f32", runs, u0s)
     b.autotune(None)
-    b.step(20)
+    b.step(23)
     for r in (0, 1, 255, 511) + tuple(i for i, s in enumerate(specs) if s["n"] == 1024)[:1]:
         rho, q = b.moments(r)
-        rho1, q1 = _single(2, "f32", runs[r], u0s[r], 20)
+        rho1, q1 = _single(2, "f32", runs[r], u0s[r], 23)
         assert np.array_equal(rho, rho1) and np.array_equal(q, q1), r
     b.close()
