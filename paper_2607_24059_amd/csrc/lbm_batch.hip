@@ -508,7 +508,18 @@ hipError_t upload_tilesK(lbm_batch* b) {
   }
   b->ntilesK = static_cast<int64_t>(t.size());
   if (t.empty()) return hipSuccess;
-  hipError_t e = hipMemcpyAsync(b->d_tilesK, t.data(), t.size() * sizeof(BatchTile), hipMemcpyHostToDevice,
+  // XCD-major order: list slot s is taken by a block on XCD s % 8 (one block
+  // per tile, or a persistent grid that is a multiple of 8), so the slots of
+  // XCD j get the j-th eighth of the tiles in raster order and neighbouring
+  // tiles share their border reads through one L2
+  const size_t n = t.size();
+  std::vector<BatchTile> perm(n);
+  if (n % 8 == 0) {
+    for (size_t s = 0; s < n; ++s) perm[s] = t[(s % 8) * (n / 8) + s / 8];
+  } else {
+    perm = t;
+  }
+  hipError_t e = hipMemcpyAsync(b->d_tilesK, perm.data(), n * sizeof(BatchTile), hipMemcpyHostToDevice,
                                 b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   return e;
