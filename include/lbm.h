@@ -154,9 +154,10 @@ lbm_status lbm_step(lbm_ctx* ctx, int64_t nsteps);
 
 /* Time steps per launch, 1 .. 6.  2 needs a 2D context; 3 .. 6 a 2D context in
  * one of the population storages (LBM_F32, LBM_F32_RAW, LBM_F16_DEV,
- * LBM_BF16_DEV, LBM_F16_DEV_R32, LBM_BF16_DEV_R32); channel boundaries allow
- * 1 only.  LBM_EINVAL otherwise.  Default: 5 for those storages from 2^20
- * cells on, else 2 in 2D, 1 in 3D. */
+ * LBM_BF16_DEV, LBM_F16_DEV_R32, LBM_BF16_DEV_R32) or in LBM_F32_MOMENTS;
+ * channel boundaries allow 1 only.  LBM_EINVAL otherwise.  Default from 2^20
+ * cells on: 5 for those population storages, 4 for LBM_F32_MOMENTS; else 2 in
+ * 2D, 1 in 3D. */
 lbm_status lbm_set_fusion(lbm_ctx* ctx, int32_t steps_per_launch);
 
 /* The current number of time steps per launch (0 for a NULL context). */

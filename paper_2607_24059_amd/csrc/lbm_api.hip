@@ -173,7 +173,9 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const 
   default_block(g, &c->bx, &c->by);
   // deeper fusion from 1024^2 cells on; smaller grids are launch-bound and
   // keep the two-step kernel's small tiles
-  c->fuse = c->ops->stepK && g.cells >= (int64_t(1) << 20) ? 5 : c->ops->step2 ? 2 : 1;
+  c->fuse = c->ops->stepK && g.cells >= (int64_t(1) << 20) ? (p->storage == LBM_F32_MOMENTS ? 4 : 5)
+            : c->ops->step2                                  ? 2
+                                                             : 1;
 
   // stage u0 (and rho0) as FP64 in the idle buffer, then build the equilibrium
   double* su = reinterpret_cast<double*>(staging(c));

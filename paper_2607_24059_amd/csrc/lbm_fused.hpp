@@ -239,4 +239,77 @@ struct TileKr {
   }
 };
 
+// K >= 3 steps of the moment-only storage (relaxation scheme, omega = 1) in
+// one tile: the state is W (3 FP32 planes); the first step runs the stencil
+// W(t+1, x) = sum_l f^eq_l(W(t, x - c_l)) from HBM over the tile plus a
+// (K-1)-cell border into LDS (12 B per cell), the next K-2 steps run it inside
+// LDS on regions one cell narrower per side (results staged in registers
+// across a barrier, then written back over the same slots), and the last step
+// writes the tile to HBM.  Every stage evaluates the same step_moments as the
+// one- and two-step kernels, so the result equals K single steps bit for bit.
+template <int TX, int TY, int NT, int K>
+struct TileMomK {
+  static_assert(K >= 3, "two steps per launch use the two-step tile");
+  static constexpr int H = K - 1, EX = TX + 2 * H, EY = TY + 2 * H, EN = EX * EY;
+
+  template <int LO>
+  __device__ static void lds_stage(float (&s_w)[3][EN], const Coef& k) {
+    constexpr int RX = EX - 2 * LO, RY = EY - 2 * LO, RN = RX * RY;
+    constexpr int PER = (RN + NT - 1) / NT;
+    float keep[PER][3];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int t = static_cast<int>(threadIdx.x) + j * NT;
+      if (t < RN) {
+        const int e = (LO + t / RX) * EX + LO + t % RX;
+        const int off[4] = {-1, 1, -EX, EX};  // upwind neighbour of velocity +x, -x, +y, -y
+        step_moments<2>([&](int i, int nb) { return s_w[i][nb < 0 ? e : e + off[nb]]; }, k, keep[j]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int t = static_cast<int>(threadIdx.x) + j * NT;
+      if (t < RN) {
+        const int e = (LO + t / RX) * EX + LO + t % RX;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) s_w[i][e] = keep[j][i];
+      }
+    }
+    __syncthreads();
+    if constexpr (LO + 1 <= H - 1) lds_stage<LO + 1>(s_w, k);
+  }
+
+  __device__ static void run(const float* __restrict__ sr, float* __restrict__ dr, int x0, int y0, int nx, int ny,
+                             int64_t stride, const Coef& k, float (&s_w)[3][EN]) {
+    for (int e = threadIdx.x; e < EN; e += NT) {
+      const int ex = e % EX, ey = e / EX;
+      int x = x0 - H + ex, y = y0 - H + ey;
+      x = ((x % nx) + nx) % nx;  // the border may wrap (several times on tiny grids)
+      y = ((y % ny) + ny) % ny;
+      const int64_t c = static_cast<int64_t>(y) * nx + x;
+      int64_t src[4];
+      upwind_sources<2>(x, y, 0, nx, ny, 1, c, src);
+      float out[3];
+      step_moments<2>([&](int i, int nb) { return sr[i * stride + (nb < 0 ? c : src[nb])]; }, k, out);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) s_w[i][e] = out[i];
+    }
+    __syncthreads();
+    lds_stage<1>(s_w, k);
+    for (int t = threadIdx.x; t < TX * TY; t += NT) {
+      const int tx = t % TX, ty = t / TX;
+      const int x = x0 + tx, y = y0 + ty;
+      if (x >= nx || y >= ny) continue;
+      const int e = (ty + H) * EX + (tx + H);
+      const int off[4] = {-1, 1, -EX, EX};
+      float out[3];
+      step_moments<2>([&](int i, int nb) { return s_w[i][nb < 0 ? e : e + off[nb]]; }, k, out);
+      const int64_t c = static_cast<int64_t>(y) * nx + x;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) store_stream(dr + i * stride + c, out[i]);
+    }
+  }
+};
+
 }  // namespace lbm

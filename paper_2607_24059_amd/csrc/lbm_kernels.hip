@@ -289,6 +289,16 @@ __global__ __launch_bounds__(NT) void k_stepKr_2d(const TR* __restrict__ sr, con
   T::run(sr, sm, dr, dm, x0, y0, nx, ny, stride, k, s_move);
 }
 
+template <int TX, int TY, int NT, int K, bool XCD = false>
+__global__ __launch_bounds__(NT) void k_stepK_mom_2d(const float* __restrict__ sr, float* __restrict__ dr, int nx,
+                                                      int ny, int64_t stride, Coef k) {
+  using T = TileMomK<TX, TY, NT, K>;
+  __shared__ float s_w[3][T::EN];
+  int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  if constexpr (XCD) xcd_tile_origin(blockIdx.x, nx, ny, TX, TY, &x0, &y0);
+  T::run(sr, dr, x0, y0, nx, ny, stride, k, s_w);
+}
+
 template <typename TR, typename TM, int TX, int TY, int NT>
 __global__ __launch_bounds__(NT) void k_step2_2d(const TR* __restrict__ sr, const TM* __restrict__ sm,
                                                   TR* __restrict__ dr, TM* __restrict__ dm, int nx, int ny,
@@ -588,7 +598,7 @@ struct Impl {
   // (TX+2K)(TY+2K)/(TX TY) times and written once per K steps) at the price of
   // recomputing the shrinking borders; K = 6..8 and 32x16, 32x32 or 64x32
   // tiles were within a few percent or slower.
-  static constexpr bool kHasStepK = kHasStep2 && !IsNeq<TM>::value && !IsMom<TM>::value;
+  static constexpr bool kHasStepK = kHasStep2 && !IsNeq<TM>::value;
   static constexpr int kStepKThreads = sizeof(TR) == 2 ? 512 : 1024;
 
   static constexpr bool kRestInRegisters = sizeof(TR) == 4 && sizeof(TM) == 4;
@@ -598,7 +608,16 @@ struct Impl {
     auto a = planes_of<TR, TM>(const_cast<void*>(src), g.rest_bytes);
     auto b = planes_of<TR, TM>(dst, g.rest_bytes);
     const Coef k = make_coef<float>(r, D, DEV);
-    if constexpr (kRestInRegisters) {
+    if constexpr (IsMom<TM>::value) {
+      // moment-only storage: 64x32 tiles on 512 threads in raster order (sweep
+      // at 4096^2 / 2048^2, GLUPS: two steps 264.9 / 223.8; four steps 363.2 /
+      // 332.4; five steps with 64x16 tiles on 256 threads 352.3 / 314.3; XCD
+      // order was a few percent slower here)
+      constexpr int TX = 64, TY = 32, NT = 512;
+      dim3 grid((g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY, 1);
+      hipLaunchKernelGGL((k_stepK_mom_2d<TX, TY, NT, K, false>), grid, dim3(NT), 0, s, a.rest,
+                         reinterpret_cast<float*>(b.rest), g.nx, g.ny, g.stride, k);
+    } else if constexpr (kRestInRegisters) {
       constexpr int TX = 32, TY = 16, NT = 256;
       const int64_t tiles = static_cast<int64_t>((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY);
       hipLaunchKernelGGL((k_stepKr_2d<TR, TM, TX, TY, NT, K, true>), dim3(static_cast<uint32_t>(tiles)), dim3(NT), 0,

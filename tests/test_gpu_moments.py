@@ -59,20 +59,42 @@ def test_moments_match_full_oracle_at_omega_one(dim, n, steps):
     assert np.max(np.abs(rho - r_ref)) <= 1e-6
 
 
-@pytest.mark.parametrize("shape,steps", [((64, 64), 10), ((75, 75), 11), ((9, 130), 7), ((1, 1), 4), ((300, 600), 5)])
-def test_moments_two_step_fusion_is_bitwise(shape, steps):
+@pytest.mark.parametrize("shape,steps", [((64, 64), 10), ((75, 75), 11), ((9, 130), 7), ((1, 1), 4), ((300, 600), 5),
+                                         ((70, 33), 13), ((129, 257), 23)])
+def test_moments_fusion_is_bitwise(shape, steps):
+    """Every fusion depth (1 .. 6 steps per launch) gives the single-step state."""
     ny, nx = shape
     dx = 2 * math.pi / max(shape)
     p = scheme.Params(dim=2, dx=dx, dt=dx * dx / 8, nu=0.02, omega_rho=1.0, omega_q=1.0)
     u = inputs.random_field_box(shape, dx, seed=12, umax=0.05 / dx)
     blobs = []
-    for fuse in (1, 2):
+    for fuse in (1, 2, 3, 4, 5, 6):
         eng = _engine(p, u)
         eng.set_fusion(fuse)
         eng.step(steps)
         blobs.append(eng.save_state())
         eng.close()
     assert np.array_equal(blobs[0], blobs[1])
+
+
+def test_moments_default_fusion_large_grid_bitwise():
+    """From 2^20 cells the moment-only storage runs four steps per launch by
+    default: a 1100 x 1000 grid (ragged against the 64 x 32 tiles), 19 steps."""
+    import hashlib
+    p = scheme.Params(dim=2, dx=2 * math.pi / 1100, dt=(2 * math.pi / 1100) ** 2 / 8, nu=1e-3,
+                      omega_rho=1.0, omega_q=1.0)
+    u = inputs.random_field_box((1000, 1100), p.dx, seed=4, umax=0.05 / p.dx)
+    digests = []
+    for fuse in (1, None):
+        eng = _engine(p, u)
+        if fuse is None:
+            assert eng.fusion() == 4
+        else:
+            eng.set_fusion(fuse)
+        eng.step(19)
+        digests.append(hashlib.sha256(eng.save_state().tobytes()).hexdigest())
+        eng.close()
+    assert digests[0] == digests[1]
 
 
 def test_population_storage_agrees_at_omega_one():
