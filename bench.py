@@ -35,7 +35,8 @@ METRIC = "MLUPS & % HBM peak; fp16-store / learned closure vs plain fp32 at fixe
 BYTES_PER_LUP = {("f32", 2): 120, ("f16_dev", 2): 60, ("bf16_dev", 2): 60, ("f16_dev_r32", 2): 72,
                  ("bf16_dev_r32", 2): 72, ("f32_raw", 2): 120, ("f32", 3): 224, ("f16_dev", 3): 112, ("bf16_dev", 3): 112,
                  ("f16_dev_r32", 3): 128, ("bf16_dev_r32", 3): 128, ("f16_neq", 2): 72, ("f16_neq", 3): 128}
-KERNEL_SOURCES = ("paper_2607_24059_amd/csrc/lbm_kernels.hip", "paper_2607_24059_amd/csrc/lbm_device.hpp")
+KERNEL_SOURCES = ("paper_2607_24059_amd/csrc/lbm_kernels.hip", "paper_2607_24059_amd/csrc/lbm_device.hpp",
+                  "paper_2607_24059_amd/csrc/lbm_fused.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stepK_2d_f32_4096_traffic.json")
 
 
