@@ -588,7 +588,8 @@ struct Impl {
   // K = 3 .. 6 steps per launch (2D population storages) in XCD-major tile
   // order.  4-byte planes: k_stepKr_2d (rest populations in registers), 32x16
   // tiles on 256 threads; 16-bit moving planes: k_stepK_2d, 64x16 tiles on
-  // 1024 threads with FP32 rest planes, 512 for all-16-bit storage.  From
+  // 512 threads (1024 threads ran FP16 + FP32 rest at 124 against 154 GLUPS
+  // at 4096^2 in this library's build).  From
   // sweeps of the engine's instantiations on MI355X (GLUPS at 4096^2 / 2048^2 /
   // 1024^2, two steps per launch first): FP32 86.9 / 68.5 / 63.8 against 114.3 /
   // 121.7 / 118.6 for k_stepK_2d at K = 5 and 130.2 / 132.8 for k_stepKr_2d;
@@ -599,7 +600,7 @@ struct Impl {
   // recomputing the shrinking borders; K = 6..8 and 32x16, 32x32 or 64x32
   // tiles were within a few percent or slower.
   static constexpr bool kHasStepK = kHasStep2 && !IsNeq<TM>::value;
-  static constexpr int kStepKThreads = sizeof(TR) == 2 ? 512 : 1024;
+  static constexpr int kStepKThreads = 512;
 
   static constexpr bool kRestInRegisters = sizeof(TR) == 4 && sizeof(TM) == 4;
 
