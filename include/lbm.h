@@ -152,12 +152,10 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const 
  * The result is bit-identical for any fusion setting.  Asynchronous. */
 lbm_status lbm_step(lbm_ctx* ctx, int64_t nsteps);
 
-/* Time steps per launch, 1 .. 6.  2 needs a 2D context; 3 .. 6 a 2D context in
- * one of the population storages (LBM_F32, LBM_F32_RAW, LBM_F16_DEV,
- * LBM_BF16_DEV, LBM_F16_DEV_R32, LBM_BF16_DEV_R32) or in LBM_F32_MOMENTS;
- * channel boundaries allow 1 only.  LBM_EINVAL otherwise.  Default from 2^20
- * cells on: 5 for those population storages, 4 for LBM_F32_MOMENTS; else 2 in
- * 2D, 1 in 3D. */
+/* Time steps per launch, 1 .. 6.  2 .. 6 need a 2D context in any storage but
+ * LBM_F64; channel boundaries allow 1 only.  LBM_EINVAL otherwise.  Default
+ * from 2^20 cells on: 4 for LBM_F32_MOMENTS, 5 otherwise; else 2 in 2D, 1 in
+ * 3D and for LBM_F64. */
 lbm_status lbm_set_fusion(lbm_ctx* ctx, int32_t steps_per_launch);
 
 /* The current number of time steps per launch (0 for a NULL context). */

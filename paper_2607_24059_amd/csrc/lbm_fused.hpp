@@ -312,4 +312,120 @@ struct TileMomK {
   }
 };
 
+// K >= 3 steps of the split FP16 storage (W in FP32, scaled non-equilibrium
+// parts n in FP16) in one tile.  The first step runs from HBM over the tile
+// plus a (K-1)-cell border (rebuilding the upwind neighbours' equilibria) and
+// keeps in LDS, as FP32, the populations that the stored values would stand
+// for, f* = f^eq(W) + n / s with n rounded to FP16 (rest: f^eq_rest(W) -
+// sum_m n_m / s): exactly what the next step's gather would rebuild from HBM.
+// Each step inside LDS gathers those populations, relaxes, and rounds its
+// result the same way before writing it back (staged in registers across a
+// barrier), on regions one cell narrower per side; the last step writes W and
+// the scaled FP16 parts of the tile to HBM.  The result equals K single steps
+// bit for bit, and the upwind equilibria are rebuilt once per launch instead
+// of once per step.
+template <int TX, int TY, int NT, int K>
+struct TileNeqK {
+  static_assert(K >= 3, "two steps per launch use the two-step tile");
+  static constexpr int H = K - 1, EX = TX + 2 * H, EY = TY + 2 * H, EN = EX * EY;
+
+  // the populations a store of (W, n) and a reload would give
+  __device__ static void stored_populations(const float (&W)[3], const float (&n)[3][4], const float (&eq)[3][5],
+                                            const Coef& k, const NeqScale<2>& sc, float (&f)[15]) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      float nr[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) nr[m] = static_cast<float>(static_cast<_Float16>(n[i][m] * sc.s[i]));
+      const float s = ((nr[0] + nr[1]) + nr[2]) + nr[3];
+      f[i * 5] = (W[i] - ((i == 0) ? k.d2a_rho : k.d2a_q) * W[i]) - s * sc.inv[i];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) f[i * 5 + 1 + m] = eq[i][1 + m] + nr[m] * sc.inv[i];
+    }
+  }
+
+  __device__ static void gather(const float (&s_f)[15][EN], int e, float (&g)[3][5]) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      g[i][0] = s_f[i * 5][e];
+      g[i][1] = s_f[i * 5 + 1][e - 1];   // +x from x-1
+      g[i][2] = s_f[i * 5 + 2][e + 1];   // -x from x+1
+      g[i][3] = s_f[i * 5 + 3][e - EX];  // +y from y-1
+      g[i][4] = s_f[i * 5 + 4][e + EX];  // -y from y+1
+    }
+  }
+
+  template <int LO>
+  __device__ static void lds_stage(float (&s_f)[15][EN], const Coef& k, const NeqScale<2>& sc) {
+    constexpr int RX = EX - 2 * LO, RY = EY - 2 * LO, RN = RX * RY;
+    constexpr int PER = (RN + NT - 1) / NT;
+    float keep[PER][15];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int t = static_cast<int>(threadIdx.x) + j * NT;
+      if (t < RN) {
+        const int e = (LO + t / RX) * EX + LO + t % RX;
+        float g[3][5];
+        gather(s_f, e, g);
+        float W[3], n[3][4], eq[3][5];
+        collide_neq<2>(g, k, W, n, eq);
+        stored_populations(W, n, eq, k, sc, keep[j]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int t = static_cast<int>(threadIdx.x) + j * NT;
+      if (t < RN) {
+        const int e = (LO + t / RX) * EX + LO + t % RX;
+#pragma unroll
+        for (int q = 0; q < 15; ++q) s_f[q][e] = keep[j][q];
+      }
+    }
+    __syncthreads();
+    if constexpr (LO + 1 <= H - 1) lds_stage<LO + 1>(s_f, k, sc);
+  }
+
+  __device__ static void run(const float* __restrict__ sr, const neq16* __restrict__ sm, float* __restrict__ dr,
+                             neq16* __restrict__ dm, int x0, int y0, int nx, int ny, int64_t stride, const Coef& k,
+                             const NeqScale<2>& sc, float (&s_f)[15][EN]) {
+    for (int e = threadIdx.x; e < EN; e += NT) {
+      const int ex = e % EX, ey = e / EX;
+      int x = x0 - H + ex, y = y0 - H + ey;
+      x = ((x % nx) + nx) % nx;  // the border may wrap (several times on tiny grids)
+      y = ((y % ny) + ny) % ny;
+      const int64_t c = static_cast<int64_t>(y) * nx + x;
+      int64_t src[4];
+      upwind_sources<2>(x, y, 0, nx, ny, 1, c, src);
+      auto w_at = [&](int i, int nb) { return sr[i * stride + (nb < 0 ? c : src[nb])]; };
+      auto n_at = [&](int i, int m, int nb) { return load_f32(sm + (i * 4 + m) * stride + (nb < 0 ? c : src[nb])); };
+      float g[3][5];
+      gather_neq<2>(w_at, n_at, k, sc, g);
+      float W[3], n[3][4], eq[3][5], f[15];
+      collide_neq<2>(g, k, W, n, eq);
+      stored_populations(W, n, eq, k, sc, f);
+#pragma unroll
+      for (int q = 0; q < 15; ++q) s_f[q][e] = f[q];
+    }
+    __syncthreads();
+    lds_stage<1>(s_f, k, sc);
+    for (int t = threadIdx.x; t < TX * TY; t += NT) {
+      const int tx = t % TX, ty = t / TX;
+      const int x = x0 + tx, y = y0 + ty;
+      if (x >= nx || y >= ny) continue;
+      float g[3][5];
+      gather(s_f, (ty + H) * EX + (tx + H), g);
+      float W[3], n[3][4], eq[3][5];
+      collide_neq<2>(g, k, W, n, eq);
+      const int64_t c = static_cast<int64_t>(y) * nx + x;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        store_stream(dr + i * stride + c, W[i]);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) store_stream(dm + (i * 4 + m) * stride + c, n[i][m] * sc.s[i]);
+      }
+    }
+  }
+};
+
 }  // namespace lbm

@@ -290,6 +290,17 @@ __global__ __launch_bounds__(NT) void k_stepKr_2d(const TR* __restrict__ sr, con
 }
 
 template <int TX, int TY, int NT, int K, bool XCD = false>
+__global__ __launch_bounds__(NT) void k_stepK_neq_2d(const float* __restrict__ sr, const neq16* __restrict__ sm,
+                                                      float* __restrict__ dr, neq16* __restrict__ dm, int nx, int ny,
+                                                      int64_t stride, Coef k, NeqScale<2> sc) {
+  using T = TileNeqK<TX, TY, NT, K>;
+  __shared__ float s_f[15][T::EN];
+  int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  if constexpr (XCD) xcd_tile_origin(blockIdx.x, nx, ny, TX, TY, &x0, &y0);
+  T::run(sr, sm, dr, dm, x0, y0, nx, ny, stride, k, sc, s_f);
+}
+
+template <int TX, int TY, int NT, int K, bool XCD = false>
 __global__ __launch_bounds__(NT) void k_stepK_mom_2d(const float* __restrict__ sr, float* __restrict__ dr, int nx,
                                                       int ny, int64_t stride, Coef k) {
   using T = TileMomK<TX, TY, NT, K>;
@@ -599,17 +610,29 @@ struct Impl {
   // (TX+2K)(TY+2K)/(TX TY) times and written once per K steps) at the price of
   // recomputing the shrinking borders; K = 6..8 and 32x16, 32x32 or 64x32
   // tiles were within a few percent or slower.
-  static constexpr bool kHasStepK = kHasStep2 && !IsNeq<TM>::value;
+  static constexpr bool kHasStepK = kHasStep2;
   static constexpr int kStepKThreads = 512;
 
   static constexpr bool kRestInRegisters = sizeof(TR) == 4 && sizeof(TM) == 4;
+  // split FP16 storage: 64x8 tiles on 512 threads (GLUPS at 4096^2, K = 2 /
+  // 3 / 4 / 5 / 6: 88.0 / 97.6 / 96.1 / 98.3 / 90.3; 64x16 on 512, 32x16 on
+  // 256 and 32x32 on 512 threads peaked at 94.9, 96.5 and 85.1): every stage
+  // rebuilds the storage rounding, so the kernel stays ALU-bound
+  struct NeqKTile {
+    static constexpr int TX = 64, TY = 8, NT = 512;
+  };
 
   template <int K>
   static hipError_t launchK(const Geometry& g, const RunCoef& r, const void* src, void* dst, hipStream_t s) {
     auto a = planes_of<TR, TM>(const_cast<void*>(src), g.rest_bytes);
     auto b = planes_of<TR, TM>(dst, g.rest_bytes);
     const Coef k = make_coef<float>(r, D, DEV);
-    if constexpr (IsMom<TM>::value) {
+    if constexpr (IsNeq<TM>::value) {
+      constexpr int TX = NeqKTile::TX, TY = NeqKTile::TY, NT = NeqKTile::NT;
+      const int64_t tiles = static_cast<int64_t>((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY);
+      hipLaunchKernelGGL((k_stepK_neq_2d<TX, TY, NT, K, true>), dim3(static_cast<uint32_t>(tiles)), dim3(NT), 0, s,
+                         a.rest, a.move, b.rest, b.move, g.nx, g.ny, g.stride, k, neq_scale_of<2>(r));
+    } else if constexpr (IsMom<TM>::value) {
       // moment-only storage: 64x32 tiles on 512 threads in raster order (sweep
       // at 4096^2 / 2048^2, GLUPS: two steps 264.9 / 223.8; four steps 363.2 /
       // 332.4; five steps with 64x16 tiles on 256 threads 352.3 / 314.3; XCD

@@ -337,7 +337,8 @@ def test_two_step_fusion_bitwise_large_tile(storage):
 # 3 .. 6 steps per launch (2D population storages): bit-identical as well     #
 # --------------------------------------------------------------------------- #
 
-@pytest.mark.parametrize("storage", ["f32", "f16_dev", "bf16_dev", "f16_dev_r32", "bf16_dev_r32", "f32_raw"])
+@pytest.mark.parametrize("storage", ["f32", "f16_dev", "bf16_dev", "f16_dev_r32", "bf16_dev_r32", "f32_raw",
+                                     "f16_neq"])
 @pytest.mark.parametrize("shape,steps", [((64, 64), 13), ((75, 75), 17), ((17, 130), 11), ((3, 200), 9),
                                          ((1, 1), 7), ((300, 257), 12)])
 def test_deep_fusion_is_bitwise(storage, shape, steps):
@@ -360,7 +361,7 @@ def test_deep_fusion_is_bitwise(storage, shape, steps):
         assert np.array_equal(blobs[0], b)
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16_dev", "f16_dev_r32"])
+@pytest.mark.parametrize("storage", ["f32", "f16_dev", "f16_dev_r32", "f16_neq"])
 def test_deep_fusion_bitwise_large_grid(storage):
     """The default depth from 2^20 cells on (5 steps per launch, 64x16 tiles in
     XCD order) on a 2900^2 grid, ragged against both tile edges, 23 steps."""
@@ -394,9 +395,16 @@ def test_fusion_settings_and_defaults():
     eng.close()
     neq = _engine(small, u, storage="f16_neq")
     assert neq.fusion() == 2
+    neq.set_fusion(3)
     with pytest.raises(lbm.LbmError):
-        neq.set_fusion(3)
+        neq.set_fusion(7)
     neq.close()
+    f64 = _engine(small, u, storage="f64")
+    assert f64.fusion() == 1
+    for bad in (2, 3):
+        with pytest.raises(lbm.LbmError):
+            f64.set_fusion(bad)
+    f64.close()
     big = scheme.params_for_grid(2, 1024, 1e-3)
     eng = _engine(big, inputs.random_field_2d(1024, 0, umax=0.05 / big.dx))
     assert eng.fusion() == 5
