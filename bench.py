@@ -136,15 +136,16 @@ def cpu_baseline(n: int = 4096, steps: int = 10, nu: float = 1e-3) -> dict:
                       f"of {avail} available ({cpu})"}
 
 
-def traffic_entry(per_launch_algo_bytes: float):
+def traffic_entry(kernel: str):
     """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was
-    taken on the current kernel source; else None."""
+    taken on the current kernel source and on this kernel instantiation; else
+    None."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_hash") != kernel_hash():
+    if t.get("kernel_hash") != kernel_hash() or t.get("kernel") != kernel:
         return None
     return t.get("bytes_per_launch")
 
@@ -197,6 +198,8 @@ def main():
     algo = lup_bytes * fuse * cells          # per launch: 120 B per lattice update x fuse updates per cell
     achieved = algo / (launch_ms * 1e-3) / 1e9
     min_bytes = lup_bytes * cells            # the fused kernel's own minimum: state read once + written once
+    kname = (f"k_stepKr_2d<float,float,32,16,256,{fuse},true>" if fuse >= 3 else
+             "k_step2_2d<float,float,256,8,1024>" if fuse == 2 else "k_step<2,float,float>")
     result = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -216,10 +219,8 @@ def main():
                    "omega_rho": 1.2, "omega_q": 1.15, "alpha_rho": 0.075, "steps_per_launch": fuse},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": traffic_entry(algo),
-                     "kernel": (f"k_stepKr_2d<float,float,32,16,256,{fuse},true> ({fuse} lattice updates "
-                                "per cell per launch)" if fuse >= 3 else
-                                "k_step2_2d<float,float,256,8,1024> (two lattice updates per cell per launch)"),
+                     "traffic": traffic_entry(kname),
+                     "kernel": f"{kname} ({fuse} lattice updates per cell per launch)",
                      "bytes_per_launch_algorithmic": algo, "launch_us": round(launch_ms * 1e3, 2),
                      "note": "achieved uses 120 B per lattice update; the fused kernel keeps the "
                              "intermediate steps on chip, so it moves fewer bytes than single "
