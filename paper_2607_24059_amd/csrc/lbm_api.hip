@@ -119,6 +119,18 @@ void default_block(const Geometry& g, int* bx, int* by) {
 
 }  // namespace
 
+// Default steps per launch of the multi-step kernels, from sweeps at 4096^2 /
+// 2048^2: FP32 populations (rest in registers, 32x16 tiles) 130.4 / 125.4
+// GLUPS at 5 and 136.6 / 130.4 at 6; the 16-bit and split storages peak at 5;
+// the moment-only storage at 4.
+static int default_depth(int storage) {
+  switch (storage) {
+    case LBM_F32: case LBM_F32_RAW: return 6;
+    case LBM_F32_MOMENTS: return 4;
+    default: return 5;
+  }
+}
+
 extern "C" {
 
 lbm_status lbm_check_params(const lbm_params* p, double* mu, double* alpha_q, uint32_t* flags) {
@@ -194,18 +206,6 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const 
   }
   *out = c;
   return LBM_OK;
-}
-
-// Default steps per launch of the multi-step kernels, from sweeps at 4096^2 /
-// 2048^2: FP32 populations (rest in registers, 32x16 tiles) 130.4 / 125.4
-// GLUPS at 5 and 136.6 / 130.4 at 6; the 16-bit and split storages peak at 5;
-// the moment-only storage at 4.
-static int default_depth(int storage) {
-  switch (storage) {
-    case LBM_F32: case LBM_F32_RAW: return 6;
-    case LBM_F32_MOMENTS: return 4;
-    default: return 5;
-  }
 }
 
 lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
