@@ -277,7 +277,7 @@ def main():
         result["variants"] = variants
 
     if not args.no_equal_error:
-        log("[bench] equal-error comparison (FP64 2048^2 judge, plain FP32 / FP16 levels, learned closure)")
+        log("[bench] equal-error comparison (FP64 2048^2 reference, plain FP32 / FP16 levels, learned closure)")
         result["equal_error"] = equal_error_section(args.equal_error_seeds)
 
     if not args.no_cpu:
@@ -299,8 +299,8 @@ def _finite(v):
 
 def equal_error_section(n_seeds: int) -> dict:
     """Speedups over the plain FP32 scheme at equal error against the fine-grid
-    judge, on the closure workload: k^-3 fields (held-out seeds 1000...),
-    nu = 5e-4, coarse 256^2, judge = the plain scheme at 2048^2 in FP64
+    reference, on the closure workload: k^-3 fields (held-out seeds 1000...),
+    nu = 5e-4, coarse 256^2, reference = the plain scheme at 2048^2 in FP64
     storage restricted to 256^2, 256 coarse steps.  Plain levels 256^2, 512^2,
     1024^2 in FP32 and in FP16 + FP32-rest storage; the corrected 256^2 run
     uses the committed trained network.  Errors: relative L2 of the
@@ -312,7 +312,7 @@ def equal_error_section(n_seeds: int) -> dict:
     cfg.test_seeds = list(range(1000, 1000 + n_seeds))
     net = cnn.Net(params=params)
     ev = closure.evaluate(cfg, net, meta["scales"], log=log)
-    return _finite({"workload": f"k^-3 field, nu={cfg.nu}, coarse {cfg.coarse_n}^2, judge FP64 "
+    return _finite({"workload": f"k^-3 field, nu={cfg.nu}, coarse {cfg.coarse_n}^2, reference FP64 "
                         f"{cfg.fine_n}^2 restricted, {cfg.horizon} coarse steps, "
                         f"seeds {cfg.test_seeds[0]}..{cfg.test_seeds[-1]}",
             "error_metric": "relative L2 of the divergence-free part of u",

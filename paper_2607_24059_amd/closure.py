@@ -5,7 +5,7 @@ Workload (defaults): coarse 256^2 runs of the D2Q5 scheme corrected every 4
 coarse steps by the four-layer 3x3 network of `cnn`; training data from 2048^2
 fine runs of the same scheme (nu = 5e-4, k^-3 random fields at coarse Mach
 0.05, mu = 8 on both grids so one coarse step is 64 fine steps), restricted
-8x to the coarse grid; judged against held-out fine runs; the guard falls back
+8x to the coarse grid; compared with held-out fine runs; the guard falls back
 to the plain coarse step when the correction would more than double the
 discrete divergence norm.
 
@@ -420,7 +420,7 @@ def rel_u_sol(m, ref):
 
 def evaluate(cfg: Config, net, scales, log=print, seeds=None, levels=None, plain_storages=("f32", "f16_neq", "f16_dev_r32"),
              use_graph=True):
-    """Errors against the restricted fine judge after `horizon` coarse steps,
+    """Errors against the restricted fine reference after `horizon` coarse steps,
     for the plain scheme at each level in each storage and for the corrected
     coarse run (FP32 storage), with the wall time of each run (HIP events
     around the steps only).  Every run starts from the restriction of the fine
@@ -449,10 +449,10 @@ def evaluate(cfg: Config, net, scales, log=print, seeds=None, levels=None, plain
             starts[n] = torch.empty((3, n, n), dtype=torch.float32, device="cuda")
             fine.restricted(n, starts[n])
         fine.advance(cfg.horizon)
-        judge = torch.empty((3, nc, nc), dtype=torch.float32, device="cuda")
-        fine.restricted(nc, judge)
+        ref_c = torch.empty((3, nc, nc), dtype=torch.float32, device="cuda")
+        fine.restricted(nc, ref_c)
         fine.close()
-        judge_h = _host(judge)
+        ref_h = _host(ref_c)
         for st in plain_storages:
             for n in levels:
                 eng = _engine(cfg, n, storage=st)
@@ -467,8 +467,8 @@ def evaluate(cfg: Config, net, scales, log=print, seeds=None, levels=None, plain
                 torch.cuda.synchronize()
                 tim[st][n].append(ev0.elapsed_time(ev1))
                 mh = _host(mbuf)
-                err[st][n]["u_sol"].append(rel_u_sol(mh, judge_h))
-                err[st][n]["u"].append(rel_u(mh, judge_h))
+                err[st][n]["u_sol"].append(rel_u_sol(mh, ref_h))
+                err[st][n]["u"].append(rel_u(mh, ref_h))
                 eng.close()
         run = CorrectedRun(cfg, net, scales, starts[nc], use_graph=use_graph)
         if use_graph:
@@ -485,8 +485,8 @@ def evaluate(cfg: Config, net, scales, log=print, seeds=None, levels=None, plain
         run.moments(mbuf)
         torch.cuda.synchronize()
         mh = _host(mbuf)
-        cerr["u_sol"].append(rel_u_sol(mh, judge_h))
-        cerr["u"].append(rel_u(mh, judge_h))
+        cerr["u_sol"].append(rel_u_sol(mh, ref_h))
+        cerr["u"].append(rel_u(mh, ref_h))
         run.close()
         st0 = plain_storages[0]
         log(f"[closure] seed {seed}: u_sol plain {st0} " +

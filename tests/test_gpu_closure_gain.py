@@ -2,7 +2,7 @@
 
 The network shipped in paper_2607_24059_amd/closure_weights.npz (trained on
 seeds 0..95 by `python -m paper_2607_24059_amd.closure`) corrects a 256^2 run
-every 4 steps; the judge is the plain scheme at 2048^2 in FP64 storage,
+every 4 steps; the reference is the plain scheme at 2048^2 in FP64 storage,
 restricted to 256^2.  On held-out seeds the corrected run must beat the plain
 256^2 run by at least 2x on the divergence-free velocity error after 256
 coarse steps, and must not be worse on the full velocity error.
@@ -30,7 +30,7 @@ def test_trained_network_beats_plain_coarse():
                        if k in ("coarse_n", "factor", "nu", "mach", "mu", "every", "guard", "horizon")})
     assert not set(HELD_OUT) & set(meta["config"]["train_seeds"])
     net = cnn.Net(params=params)
-    print(f"[gain] seeds {HELD_OUT}, coarse {cfg.coarse_n}^2, judge FP64 {cfg.fine_n}^2", flush=True)
+    print(f"[gain] seeds {HELD_OUT}, coarse {cfg.coarse_n}^2, reference FP64 {cfg.fine_n}^2", flush=True)
     ev = cl.evaluate(cfg, net, meta["scales"], seeds=HELD_OUT, levels=(256, 512), plain_storages=("f32",),
                      log=lambda *a: print(*a, flush=True))
     ps = ev["per_seed"]

@@ -63,8 +63,8 @@ def _run(p, u0, storage):
 
 def _record(key, err):
     RESULTS[key] = err
-    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
-    if os.path.isdir(out):
+    out = os.environ.get("LBM_RESULTS_DIR")  # optional: where to write the measured errors
+    if out and os.path.isdir(out):
         with open(os.path.join(out, "precision.json"), "w") as fh:
             json.dump(RESULTS, fh, indent=1)
 
