@@ -265,6 +265,99 @@ __device__ __forceinline__ void step2_tile(const TR* __restrict__ sr, const TM* 
   }
 }
 
+// ----------------------------------------------------------------------------
+// two steps per launch in 3D, marching along z.  Each thread owns one (x, y)
+// column of a (TX+2) x (TY+2) extended tile and walks the planes of one z
+// segment [z0, z0 + ZS) plus one plane on each side.  At plane p it advances
+// its column cell by the first step from HBM (the single-step gather); the
+// in-plane moving populations (+-x, +-y of the four sets) of that result go to
+// one of two LDS planes, the rest and +-z populations stay in the thread's
+// registers.  The second step of plane p - 1 then gathers +-x, +-y from the
+// neighbouring columns' LDS values of plane p - 1, the rest from its own
+// registers, +z from its result of plane p - 2 and -z from that of plane p,
+// and writes the tile's cells to HBM.  One barrier per plane.  Every first-step
+// value is rounded to the storage type as a store to HBM would round it, so the
+// result equals two single steps bit for bit; each state value is read about
+// (TX+2)(TY+2)(ZS+2)/(TX TY ZS) times and written once per two steps.
+// ----------------------------------------------------------------------------
+template <typename TR, typename TM, int TX, int TY, int ZS, int NT>
+__global__ __launch_bounds__(NT) void k_step2_3d(const TR* __restrict__ sr, const TM* __restrict__ sm,
+                                                  TR* __restrict__ dr, TM* __restrict__ dm, int nx, int ny, int nz,
+                                                  int64_t stride, Coef k) {
+  constexpr int EX = TX + 2, EY = TY + 2, EN = EX * EY;
+  static_assert(NT >= EN, "one thread per column of the extended tile");
+  __shared__ TM s_in[2][16][EN];  // +-x, +-y populations of the four sets, two planes
+  const int t = threadIdx.x;
+  const bool col = t < EN;
+  const int ex = t % EX, ey = t / EX;
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * ZS;
+  int x = x0 - 1 + ex, y = y0 - 1 + ey;
+  x = ((x % nx) + nx) % nx;  // the border may wrap (several times on tiny grids)
+  y = ((y % ny) + ny) % ny;
+  const bool inner = col && ex >= 1 && ex <= TX && ey >= 1 && ey <= TY && x0 + ex - 1 < nx && y0 + ey - 1 < ny;
+  const int64_t plane = static_cast<int64_t>(nx) * ny;
+  const int64_t cxy = static_cast<int64_t>(y) * nx + x;
+  const int zend = min(z0 + ZS, nz);
+  float rest1[4], zp1[4], zp2[4];  // first-step results of planes p - 1 (rest, +z) and p - 2 (+z)
+#pragma unroll
+  for (int i = 0; i < 4; ++i) rest1[i] = zp1[i] = zp2[i] = 0.0f;
+  for (int p = z0 - 1; p <= zend; ++p) {
+    const int slot = (p - z0 + 1) & 1;
+    float rest0[4], zp0[4], zm0[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) rest0[i] = zp0[i] = zm0[i] = 0.0f;
+    if (col) {
+      const int pz = ((p % nz) + nz) % nz;
+      const int64_t c = static_cast<int64_t>(pz) * plane + cxy;
+      float g[4][7];
+      gather_cell<3, TR, TM>(sr, sm, x, y, pz, nx, ny, nz, stride, c, g);
+      collide<3>(g, k);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        TR r;
+        TM a, b;
+        store_f32(&r, g[i][0]);
+        store_f32(&a, g[i][5]);
+        store_f32(&b, g[i][6]);
+        rest0[i] = load_f32(&r);
+        zp0[i] = load_f32(&a);
+        zm0[i] = load_f32(&b);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) store_f32(&s_in[slot][i * 4 + m][t], g[i][1 + m]);
+      }
+    }
+    if (p >= z0 + 1 && inner) {
+      // second step of plane p - 1
+      float g[4][7];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        g[i][0] = rest1[i];
+        g[i][1] = load_f32(&s_in[slot ^ 1][i * 4 + 0][t - 1]);   // +x from x-1
+        g[i][2] = load_f32(&s_in[slot ^ 1][i * 4 + 1][t + 1]);   // -x from x+1
+        g[i][3] = load_f32(&s_in[slot ^ 1][i * 4 + 2][t - EX]);  // +y from y-1
+        g[i][4] = load_f32(&s_in[slot ^ 1][i * 4 + 3][t + EX]);  // -y from y+1
+        g[i][5] = zp2[i];                                        // +z from z-1
+        g[i][6] = zm0[i];                                        // -z from z+1
+      }
+      collide<3>(g, k);
+      const int64_t c = static_cast<int64_t>(p - 1) * plane + static_cast<int64_t>(y0 + ey - 1) * nx + (x0 + ex - 1);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        store_stream(dr + i * stride + c, g[i][0]);
+#pragma unroll
+        for (int m = 0; m < 6; ++m) store_stream(dm + (i * 6 + m) * stride + c, g[i][1 + m]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      zp2[i] = zp1[i];
+      zp1[i] = zp0[i];
+      rest1[i] = rest0[i];
+    }
+    __syncthreads();
+  }
+}
+
 // K >= 3 steps per launch: the tiles of lbm_fused.hpp
 template <typename TR, typename TM, int TX, int TY, int NT, int K, bool XCD = false>
 __global__ __launch_bounds__(NT) void k_stepK_2d(const TR* __restrict__ sr, const TM* __restrict__ sm,
@@ -569,7 +662,16 @@ struct Impl {
   // beats 128x8 (64 blocks): 20.4 vs 19.4 GLUPS FP32 at 256^2.  The split
   // storage is ALU-bound (it rebuilds the upwind equilibria) and runs 128x8
   // on 1024 threads: 91 vs 85 GLUPS for 128x8/512 (64x8/512: 72, 256x4/1024: 77).
-  static constexpr bool kHasStep2 = D == 2 && !std::is_same<TM, double>::value;
+  // 3D: the z-marching two-step kernel for 4-byte planes (FP32, raw FP32)
+  static constexpr bool kHasStep2 =
+      (D == 2 && !std::is_same<TM, double>::value) ||
+      (D == 3 && std::is_same<TR, float>::value && std::is_same<TM, float>::value);
+  // 64 x 8 columns on 704 threads, 32-plane segments (GLUPS at 256^3: 31.5;
+  // 32x16 / 640: 29.2, with 64-plane segments 28.2; 64x12 / 960: 27.5;
+  // 96x8 / 1024: 28.0; 32x8 and 16x16 / 384: 25.3, 20.9; 16- and 24-plane
+  // segments: 29.9, 30.2; one step per launch: 25.2).  The kernel needs 140
+  // VGPRs (one block per CU); capping it at 128 or 96 spills.
+  static constexpr int kT3X = 64, kT3Y = 8, kT3Z = 32, kT3N = 704;
 
   template <int TX, int TY, int NT>
   static hipError_t launch2(const Geometry& g, const RunCoef& r, const void* src, void* dst, hipStream_t s) {
@@ -585,6 +687,14 @@ struct Impl {
   static hipError_t step2(const Geometry& g, const RunCoef& r, const void* src, void* dst, hipStream_t s) {
     if constexpr (!kHasStep2) {
       return hipErrorInvalidValue;
+    } else if constexpr (D == 3) {
+      auto a = planes_of<TR, TM>(const_cast<void*>(src), g.rest_bytes);
+      auto b = planes_of<TR, TM>(dst, g.rest_bytes);
+      const Coef k = make_coef<float>(r, D, DEV);
+      dim3 grid((g.nx + kT3X - 1) / kT3X, (g.ny + kT3Y - 1) / kT3Y, (g.nz + kT3Z - 1) / kT3Z);
+      hipLaunchKernelGGL((k_step2_3d<TR, TM, kT3X, kT3Y, kT3Z, kT3N>), grid, dim3(kT3N), 0, s, a.rest, a.move, b.rest,
+                         b.move, g.nx, g.ny, g.nz, g.stride, k);
+      return hipGetLastError();
     } else if constexpr (IsNeq<TM>::value) {
       return launch2<128, 8, 1024>(g, r, src, dst, s);
     } else if constexpr (IsMom<TM>::value) {
@@ -610,7 +720,7 @@ struct Impl {
   // (TX+2K)(TY+2K)/(TX TY) times and written once per K steps) at the price of
   // recomputing the shrinking borders; K = 6..8 and 32x16, 32x32 or 64x32
   // tiles were within a few percent or slower.
-  static constexpr bool kHasStepK = kHasStep2;
+  static constexpr bool kHasStepK = kHasStep2 && D == 2;
   static constexpr int kStepKThreads = 512;
 
   static constexpr bool kRestInRegisters = sizeof(TR) == 4 && sizeof(TM) == 4;

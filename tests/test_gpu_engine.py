@@ -411,15 +411,44 @@ def test_fusion_settings_and_defaults():
     eng.close()
     p3 = scheme.params_for_grid(3, 8, 0.01)
     e3 = _engine(p3, inputs.abc_flow(8, 0.1, 0.1, 0.1))
-    assert e3.fusion() == 1
+    assert e3.fusion() == 2
     with pytest.raises(lbm.LbmError):
         e3.set_fusion(3)
     e3.close()
 
 
-def test_two_step_fusion_not_available_in_3d():
+@pytest.mark.parametrize("storage", ["f32", "f32_raw"])
+@pytest.mark.parametrize("shape,steps", [((8, 8, 8), 6), ((17, 13, 9), 7), ((40, 20, 33), 5), ((1, 1, 1), 4),
+                                         ((3, 70, 5), 9), ((64, 64, 64), 3)])
+def test_two_step_fusion_3d_is_bitwise(storage, shape, steps):
+    """3D, 4-byte planes: the z-marching two-step kernel (32 x 16 columns,
+    32-plane segments) gives the single-step state, ragged in every direction."""
+    nz, ny, nx = shape
+    dx = 2 * math.pi / max(shape)
+    p = scheme.Params(dim=3, dx=dx, dt=dx * dx / 8, nu=0.02)
+    u = inputs.random_field_box(shape, dx, seed=5, umax=0.05 / dx)
+    blobs = []
+    for fuse in (1, 2):
+        eng = _engine(p, u, storage=storage)
+        eng.set_fusion(fuse)
+        eng.step(steps)
+        blobs.append(eng.save_state())
+        eng.close()
+    assert np.array_equal(blobs[0], blobs[1])
+
+
+def test_two_step_fusion_3d_defaults_and_limits():
     p = scheme.params_for_grid(3, 8, 0.01)
-    eng = _engine(p, inputs.abc_flow(8, 0.1, 0.1, 0.1))
-    with pytest.raises(lbm.LbmError):
-        eng.set_fusion(2)
+    u = inputs.abc_flow(8, 0.1, 0.1, 0.1)
+    eng = _engine(p, u)
+    assert eng.fusion() == 2
+    for bad in (3, 5):
+        with pytest.raises(lbm.LbmError):
+            eng.set_fusion(bad)
     eng.close()
+    for storage in ("f16_dev", "f16_dev_r32", "f16_neq", "f64"):
+        e = _engine(p, u, storage=storage)
+        assert e.fusion() == 1
+        with pytest.raises(lbm.LbmError):
+            e.set_fusion(2)
+        e.close()
