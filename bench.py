@@ -246,16 +246,22 @@ def main():
         for storage in ("f16_dev", "bf16_dev", "f16_dev_r32", "f16_neq"):
             log(f"[bench] variant 2D {storage}")
             ms_v, e = time_engine(n, 2, storage, vs, 10, u0=u0)
+            fuse_v = e.fusion()
             e.close()
             variants[f"2d_{n}_{storage}"] = _variant(cells, ms_v, BYTES_PER_LUP[(storage, 2)], probe)
+            variants[f"2d_{n}_{storage}"]["steps_per_launch"] = fuse_v
         del u0
         n3 = 256
         u3, *_ = make_workload(n3, 3, 1e-3)
-        for storage in ("f32", "f16_dev", "f16_dev_r32", "f16_neq"):
-            log(f"[bench] variant 3D {storage}")
-            ms_v, e = time_engine(n3, 3, storage, vs, 10, u0=u3)
+        for storage, fuse_3 in (("f32", None), ("f32", 1), ("f16_dev", None), ("f16_dev_r32", None),
+                                ("f16_neq", None)):
+            name = f"3d_{n3}_{storage}" + ("_one_step_per_launch" if fuse_3 == 1 else "")
+            log(f"[bench] variant {name}")
+            ms_v, e = time_engine(n3, 3, storage, vs, 10, u0=u3, fuse=fuse_3)
+            fuse_v = e.fusion()
             e.close()
-            variants[f"3d_{n3}_{storage}"] = _variant(n3 ** 3, ms_v, BYTES_PER_LUP[(storage, 3)], probe)
+            variants[name] = _variant(n3 ** 3, ms_v, BYTES_PER_LUP[(storage, 3)], probe)
+            variants[name]["steps_per_launch"] = fuse_v
         for dim_m, n_m in ((2, n), (3, 256)):
             log(f"[bench] variant {dim_m}D moment-only storage, relaxation scheme omega = 1")
             variants[f"{dim_m}d_{n_m}_f32_moments_omega1"] = moments_variant(dim_m, n_m, vs, probe)

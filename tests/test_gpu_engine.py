@@ -419,10 +419,11 @@ def test_fusion_settings_and_defaults():
 
 @pytest.mark.parametrize("storage", ["f32", "f32_raw"])
 @pytest.mark.parametrize("shape,steps", [((8, 8, 8), 6), ((17, 13, 9), 7), ((40, 20, 33), 5), ((1, 1, 1), 4),
-                                         ((3, 70, 5), 9), ((64, 64, 64), 3)])
+                                         ((3, 70, 5), 9), ((64, 64, 64), 3), ((70, 9, 66), 4)])
 def test_two_step_fusion_3d_is_bitwise(storage, shape, steps):
-    """3D, 4-byte planes: the z-marching two-step kernel (32 x 16 columns,
-    32-plane segments) gives the single-step state, ragged in every direction."""
+    """3D, 4-byte planes: the z-marching two-step kernel (64 x 8 columns,
+    32-plane segments) gives the single-step state bit for bit, ragged in
+    every direction and over several segments along z."""
     nz, ny, nx = shape
     dx = 2 * math.pi / max(shape)
     p = scheme.Params(dim=3, dx=dx, dt=dx * dx / 8, nu=0.02)
