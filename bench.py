@@ -198,7 +198,8 @@ def main():
     algo = lup_bytes * fuse * cells          # per launch: 120 B per lattice update x fuse updates per cell
     achieved = algo / (launch_ms * 1e-3) / 1e9
     min_bytes = lup_bytes * cells            # the fused kernel's own minimum: state read once + written once
-    kname = (f"k_stepKr_2d<float,float,32,16,256,{fuse},true>" if fuse >= 3 else
+    kr_tile = {3: "32,16,256", 4: "64,16,512", 5: "32,32,512", 6: "32,16,256"}
+    kname = (f"k_stepKr_2d<float,float,{kr_tile[fuse]},{fuse},true>" if fuse >= 3 else
              "k_step2_2d<float,float,256,8,1024>" if fuse == 2 else "k_step<2,float,float>")
     result = {
         "metric": METRIC,
@@ -534,8 +535,21 @@ def _variant(cells, ms, bytes_per_lup, probe):
             "frac_probe": round(gbs / probe, 4)}
 
 
+def engine_variant(dim: int, n: int, storage: str, steps: int, probe: float) -> dict:
+    """One run of the step engine on the k^-3 field at the library's default
+    fusion: the rate priced at the scheme's bytes per lattice update."""
+    u0, *_ = make_workload(n, dim, 1e-3)
+    ms, e = time_engine(n, dim, storage, steps, 10, u0=u0)
+    fuse = e.fusion()
+    e.close()
+    out = _variant(n ** dim, ms, BYTES_PER_LUP[(storage, dim)], probe)
+    out["steps_per_launch"] = fuse
+    return out
+
+
 # secondary workloads that `--only` runs alone (each as in the variants section)
 ONLY = {
+    "engine_3d": lambda a: engine_variant(3, 256, "f32", a.variant_steps, copy_probe_gbs()),
     "spectrum_2d": lambda a: spectrum_variant(2, cpu_points=10),
     "spectrum_3d": lambda a: spectrum_variant(3, cpu_points=10),
     "moments_2d": lambda a: moments_variant(2, a.n, a.variant_steps, copy_probe_gbs()),

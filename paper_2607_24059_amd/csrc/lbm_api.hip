@@ -120,16 +120,10 @@ void default_block(const Geometry& g, int* bx, int* by) {
 }  // namespace
 
 // Default steps per launch of the multi-step kernels, from sweeps at 4096^2 /
-// 2048^2: FP32 populations (rest in registers, 32x16 tiles) 130.4 / 125.4
-// GLUPS at 5 and 136.6 / 130.4 at 6; the 16-bit and split storages peak at 5;
-// the moment-only storage at 4.
-static int default_depth(int storage) {
-  switch (storage) {
-    case LBM_F32: case LBM_F32_RAW: return 6;
-    case LBM_F32_MOMENTS: return 4;
-    default: return 5;
-  }
-}
+// 2048^2: the population storages peak at 5 (FP32 with the rest in registers
+// on 32x32 tiles: 159.7 / 136.0 GLUPS, against 143.5 / 135.1 at 6 and 139.3 /
+// 132.9 at 4), the moment-only storage at 4.
+static int default_depth(int storage) { return storage == LBM_F32_MOMENTS ? 4 : 5; }
 
 extern "C" {
 

@@ -147,11 +147,13 @@ constexpr int kBatchK = 5;
 template <typename TR, typename TM>
 struct BatchKShape {
   static constexpr bool kRegs = sizeof(TR) == 4 && sizeof(TM) == 4;
-  static constexpr int TX = kRegs ? 32 : 64, TY = 16;
+  // 4-byte planes: 32x32 tiles on 512 threads (two blocks per compute unit),
+  // as in the single-run engine at five steps
+  static constexpr int TX = kRegs ? 32 : 64, TY = kRegs ? 32 : 16;
   // (FP16 + FP32 rest ran 113.5 GLUPS on 1024 threads, 102.2 on 512)
-  static constexpr int NT = kRegs ? 256 : (sizeof(TR) == 2 ? 512 : 1024);
+  static constexpr int NT = kRegs ? 512 : (sizeof(TR) == 2 ? 512 : 1024);
 };
-constexpr int kTKXmin = 32, kTKY = 16;  // smallest tile width (sizes the tile list)
+constexpr int kTKXmin = 32, kTKY = 16;  // smallest tile width and height (size the tile list)
 
 template <typename TR, typename TM>
 __global__ __launch_bounds__((BatchKShape<TR, TM>::NT)) void k_batch_stepK(const BatchRun* __restrict__ runs,
@@ -182,13 +184,13 @@ using BatchKernel = void (*)(const BatchRun*, const BatchTile*, int64_t, char*, 
 
 struct BatchKKernel {
   BatchKernel fn = nullptr;
-  int tx = 0, threads = 0;
+  int tx = 0, ty = 0, threads = 0;
 };
 
 template <typename TR, typename TM>
 BatchKKernel batch_k_of() {
   using S = BatchKShape<TR, TM>;
-  return BatchKKernel{&k_batch_stepK<TR, TM>, S::TX, S::NT};
+  return BatchKKernel{&k_batch_stepK<TR, TM>, S::TX, S::TY, S::NT};
 }
 
 BatchKKernel batch_kernelK(int dim, int storage) {
@@ -500,10 +502,10 @@ hipError_t rebuild(lbm_batch* b) {
 // The multi-step tile list (fixed, like the two-step one).
 hipError_t upload_tilesK(lbm_batch* b) {
   std::vector<BatchTile> t;
-  const int tx = b->kernelK.tx;
+  const int tx = b->kernelK.tx, ty = b->kernelK.ty;
   for (int r = 0; r < b->nruns; ++r) {
     const Geometry& g = b->geo[r];
-    for (int y0 = 0; y0 < g.ny; y0 += kTKY)
+    for (int y0 = 0; y0 < g.ny; y0 += ty)
       for (int x0 = 0; x0 < g.nx; x0 += tx) t.push_back(BatchTile{r, x0, y0, 0, static_cast<int16_t>(log2i(tx))});
   }
   b->ntilesK = static_cast<int64_t>(t.size());

@@ -150,17 +150,51 @@ struct TileKr {
   static constexpr int H = K - 1, EX = TX + 2 * H, EY = TY + 2 * H, EN = EX * EY;
   static constexpr int PER = (EN + NT - 1) / NT;
 
+  // Cell of ownership index o: the TX x TY inner cells first, row by row (so
+  // a wave owns whole rows of the tile and its last-step stores cover whole
+  // 128-byte lines, and the last step runs on the first TX TY / NT indices
+  // only), then the border cells in raster order of the extended tile.
+  __device__ static __forceinline__ void cell_of(int o, int& ex, int& ey) {
+    if (o < TX * TY) {
+      ex = H + o % TX;
+      ey = H + o / TX;
+      return;
+    }
+    int b = o - TX * TY;
+    if (b < H * EX) {
+      ex = b % EX;
+      ey = b / EX;
+      return;
+    }
+    b -= H * EX;
+    if (b < TY * 2 * H) {
+      const int c = b % (2 * H);
+      ex = c < H ? c : c + TX;
+      ey = H + b / (2 * H);
+      return;
+    }
+    b -= TY * 2 * H;
+    ex = b % EX;
+    ey = H + TY + b / EX;
+  }
+
   __device__ static void run(const TR* __restrict__ sr, const TM* __restrict__ sm, TR* __restrict__ dr,
                              TM* __restrict__ dm, int x0, int y0, int nx, int ny, int64_t stride, const Coef& k,
                              TM (&s_move)[12][EN]) {
     float rest[PER][3];   // this thread's cells' rest populations (storage-rounded)
     float mv[PER][12];    // moving populations computed in the current step
+    int e_of[PER];        // LDS slot of each of this thread's cells
+    int d_of[PER];        // its distance from the inner tile (step st updates d <= K - st)
     // step 1 from HBM over the whole extended tile
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
-      const int e = static_cast<int>(threadIdx.x) + j * NT;
-      if (e < EN) {
-        const int ex = e % EX, ey = e / EX;
+      const int o = static_cast<int>(threadIdx.x) + j * NT;
+      int ex, ey;
+      cell_of(o, ex, ey);
+      const int e = ey * EX + ex;
+      e_of[j] = e;
+      d_of[j] = o < EN ? max(max(max(H - ex, ex - (H + TX - 1)), max(H - ey, ey - (H + TY - 1))), 0) : K;
+      if (o < EN) {
         int x = x0 - H + ex, y = y0 - H + ey;
         x = ((x % nx) + nx) % nx;
         y = ((y % ny) + ny) % ny;
@@ -182,12 +216,10 @@ struct TileKr {
     // steps 2 .. K-1 in LDS over shrinking regions, then step K to HBM
 #pragma unroll
     for (int st = 2; st <= K; ++st) {
-      const int lo = st - 1;   // region [lo, EX - lo) x [lo, EY - lo)
 #pragma unroll
       for (int j = 0; j < PER; ++j) {
-        const int e = static_cast<int>(threadIdx.x) + j * NT;
-        const int ex = e % EX, ey = e / EX;
-        const bool in = e < EN && ex >= lo && ex < EX - lo && ey >= lo && ey < EY - lo;
+        const int e = e_of[j];
+        const bool in = d_of[j] <= K - st;
         if (in) {
           float g[3][5];
 #pragma unroll
@@ -209,7 +241,9 @@ struct TileKr {
               for (int m = 0; m < 4; ++m) mv[j][i * 4 + m] = g[i][1 + m];
             }
           } else {
-            const int x = x0 + ex - H, y = y0 + ey - H;
+            // the last step updates the inner cells only: o < TX TY
+            const int o = static_cast<int>(threadIdx.x) + j * NT;
+            const int x = x0 + o % TX, y = y0 + o / TX;
             if (x < nx && y < ny) {
               const int64_t c = static_cast<int64_t>(y) * nx + x;
 #pragma unroll
@@ -226,11 +260,9 @@ struct TileKr {
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
-          const int e = static_cast<int>(threadIdx.x) + j * NT;
-          const int ex = e % EX, ey = e / EX;
-          if (e < EN && ex >= lo && ex < EX - lo && ey >= lo && ey < EY - lo) {
+          if (d_of[j] <= K - st) {
 #pragma unroll
-            for (int q = 0; q < 12; ++q) store_f32(&s_move[q][e], mv[j][q]);
+            for (int q = 0; q < 12; ++q) store_f32(&s_move[q][e_of[j]], mv[j][q]);
           }
         }
         __syncthreads();

@@ -279,17 +279,32 @@ __device__ __forceinline__ void step2_tile(const TR* __restrict__ sr, const TM* 
 // value is rounded to the storage type as a store to HBM would round it, so the
 // result equals two single steps bit for bit; each state value is read about
 // (TX+2)(TY+2)(ZS+2)/(TX TY ZS) times and written once per two steps.
+// Columns are wave-aligned: wave r < TY+2 owns the 64 columns x0 .. x0+63 of
+// extended row r, so its loads and stores cover whole 128-byte lines (a store
+// that covers part of a line costs a partial-line write to HBM), and the last
+// wave owns the 2 (TY+2) border columns x0-1 and x0+64.
 // ----------------------------------------------------------------------------
 template <typename TR, typename TM, int TX, int TY, int ZS, int NT>
 __global__ __launch_bounds__(NT) void k_step2_3d(const TR* __restrict__ sr, const TM* __restrict__ sm,
                                                   TR* __restrict__ dr, TM* __restrict__ dm, int nx, int ny, int nz,
                                                   int64_t stride, Coef k) {
   constexpr int EX = TX + 2, EY = TY + 2, EN = EX * EY;
-  static_assert(NT >= EN, "one thread per column of the extended tile");
+  static_assert(TX == 64 && NT == 64 * (EY + 1) && 2 * EY <= 64, "one wave per row plus one for the border");
   __shared__ TM s_in[2][16][EN];  // +-x, +-y populations of the four sets, two planes
   const int t = threadIdx.x;
-  const bool col = t < EN;
-  const int ex = t % EX, ey = t / EX;
+  int ex, ey;
+  bool col;
+  if (t < 64 * EY) {
+    ey = t / 64;
+    ex = 1 + t % 64;
+    col = true;
+  } else {
+    const int j = t - 64 * EY;
+    ey = j / 2;
+    ex = (j % 2) ? EX - 1 : 0;
+    col = j < 2 * EY;
+  }
+  const int e = ey * EX + ex;  // the column's LDS slot (used only where col holds)
   const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * ZS;
   int x = x0 - 1 + ex, y = y0 - 1 + ey;
   x = ((x % nx) + nx) % nx;  // the border may wrap (several times on tiny grids)
@@ -323,7 +338,7 @@ __global__ __launch_bounds__(NT) void k_step2_3d(const TR* __restrict__ sr, cons
         zp0[i] = load_f32(&a);
         zm0[i] = load_f32(&b);
 #pragma unroll
-        for (int m = 0; m < 4; ++m) store_f32(&s_in[slot][i * 4 + m][t], g[i][1 + m]);
+        for (int m = 0; m < 4; ++m) store_f32(&s_in[slot][i * 4 + m][e], g[i][1 + m]);
       }
     }
     if (p >= z0 + 1 && inner) {
@@ -332,10 +347,10 @@ __global__ __launch_bounds__(NT) void k_step2_3d(const TR* __restrict__ sr, cons
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         g[i][0] = rest1[i];
-        g[i][1] = load_f32(&s_in[slot ^ 1][i * 4 + 0][t - 1]);   // +x from x-1
-        g[i][2] = load_f32(&s_in[slot ^ 1][i * 4 + 1][t + 1]);   // -x from x+1
-        g[i][3] = load_f32(&s_in[slot ^ 1][i * 4 + 2][t - EX]);  // +y from y-1
-        g[i][4] = load_f32(&s_in[slot ^ 1][i * 4 + 3][t + EX]);  // -y from y+1
+        g[i][1] = load_f32(&s_in[slot ^ 1][i * 4 + 0][e - 1]);   // +x from x-1
+        g[i][2] = load_f32(&s_in[slot ^ 1][i * 4 + 1][e + 1]);   // -x from x+1
+        g[i][3] = load_f32(&s_in[slot ^ 1][i * 4 + 2][e - EX]);  // +y from y-1
+        g[i][4] = load_f32(&s_in[slot ^ 1][i * 4 + 3][e + EX]);  // -y from y+1
         g[i][5] = zp2[i];                                        // +z from z-1
         g[i][6] = zm0[i];                                        // -z from z+1
       }
@@ -752,7 +767,15 @@ struct Impl {
       hipLaunchKernelGGL((k_stepK_mom_2d<TX, TY, NT, K, false>), grid, dim3(NT), 0, s, a.rest,
                          reinterpret_cast<float*>(b.rest), g.nx, g.ny, g.stride, k);
     } else if constexpr (kRestInRegisters) {
-      constexpr int TX = 32, TY = 16, NT = 256;
+      // the tile per depth (inner-first cell order; GLUPS at 4096^2 / 2048^2):
+      // K = 5: 32x32 on 512 threads, 159.7 / 136.0 (its 77 KB of LDS lets two
+      // blocks share a CU; 135.5 without the XCD order), against 145.3 / 136.4
+      // for 32x16 on 256; K = 4: 64x16 on 512, 139.3 / 132.9 against 125.0 /
+      // 122.1; K = 3 and 6: 32x16 on 256 (102.2 and 143.5 at 4096^2; 32x32 at
+      // K = 6 needs 85 KB per block and ran 108.6)
+      constexpr int TX = K == 5 ? 32 : K == 4 ? 64 : 32;
+      constexpr int TY = K == 5 ? 32 : 16;
+      constexpr int NT = K == 5 || K == 4 ? 512 : 256;
       const int64_t tiles = static_cast<int64_t>((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY);
       hipLaunchKernelGGL((k_stepKr_2d<TR, TM, TX, TY, NT, K, true>), dim3(static_cast<uint32_t>(tiles)), dim3(NT), 0,
                          s, a.rest, a.move, b.rest, b.move, g.nx, g.ny, g.stride, k);
