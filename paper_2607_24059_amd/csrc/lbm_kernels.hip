@@ -739,12 +739,14 @@ struct Impl {
   static constexpr int kStepKThreads = 512;
 
   static constexpr bool kRestInRegisters = sizeof(TR) == 4 && sizeof(TM) == 4;
-  // split FP16 storage: 64x8 tiles on 512 threads (GLUPS at 4096^2, K = 2 /
-  // 3 / 4 / 5 / 6: 88.0 / 97.6 / 96.1 / 98.3 / 90.3; 64x16 on 512, 32x16 on
-  // 256 and 32x32 on 512 threads peaked at 94.9, 96.5 and 85.1): every stage
-  // rebuilds the storage rounding, so the kernel stays ALU-bound
+  // split FP16 storage: 32x24 tiles on 1024 threads (GLUPS at 4096^2 / 2048^2
+  // at K = 5: 139.9 / 135.1; on 768 threads 137.6 / 125.8; 32x16 on 512 116.4 /
+  // 107.9; 64x8 on 512 107.6 / 102.2; 64x16 and 32x32 on 512 88.5 and 82.2;
+  // 32x24 at K = 4: 119.2).  Its 77 KB of FP32 populations in LDS is the
+  // largest five-step tile of which two fit in one CU.  Every stage rebuilds
+  // the storage rounding, so the kernel is ALU-bound.
   struct NeqKTile {
-    static constexpr int TX = 64, TY = 8, NT = 512;
+    static constexpr int TX = 32, TY = 24, NT = 1024;
   };
 
   template <int K>
