@@ -139,9 +139,9 @@ __global__ __launch_bounds__(kT2N) void k_batch_step2(const BatchRun* __restrict
 
 // kBatchK steps per launch (2D): the single-run engine's multi-step tiles
 // (lbm_fused.hpp) walked by a persistent grid, each tile wrapping periodically
-// in its own run; the same tile shapes as the single-run engine (32x16 cells
-// on 256 threads with the rest populations in registers for 4-byte planes,
-// 64x16 otherwise), so again bit-identical to single steps.
+// in its own run; the single-run engine's tile code (32x32 cells on 512
+// threads with the rest populations in registers for 4-byte planes, 64x16
+// otherwise), so again bit-identical to single steps.
 constexpr int kBatchK = 5;
 
 template <typename TR, typename TM>
@@ -205,7 +205,8 @@ BatchKKernel batch_kernelK(int dim, int storage) {
   return {};
 }
 
-// multi-step tiles of one 2D run for tile width tx (at most this many for any width >= kTKXmin)
+// multi-step tiles of one 2D run for tile width tx (at most this many for any
+// width >= kTKXmin and height >= kTKY)
 int64_t tilesK_of(const Geometry& g, int tx) {
   return static_cast<int64_t>((g.nx + tx - 1) / tx) * ((g.ny + kTKY - 1) / kTKY);
 }
