@@ -96,8 +96,8 @@ __global__ __launch_bounds__(kT2N) void k_batch_step2(const BatchRun* __restrict
     for (int e = threadIdx.x; e < EN; e += kT2N) {
       const int ex = e % EX, ey = e / EX;
       int x = tl.x0 - 1 + ex, y = tl.y0 - 1 + ey;
-      x = ((x % nx) + nx) % nx;  // the border may wrap (several times on tiny runs)
-      y = ((y % ny) + ny) % ny;
+      x = wrap_coord(x, nx);  // the border may wrap (several times on tiny runs)
+      y = wrap_coord(y, ny);
       const int64_t c = static_cast<int64_t>(y) * nx + x;
       float g[3][5];
       gather_cell<2, TR, TM>(a.rest, a.move, x, y, 0, nx, ny, 1, stride, c, g);

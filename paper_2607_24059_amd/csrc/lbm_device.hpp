@@ -201,6 +201,19 @@ __device__ __forceinline__ void equilibrium(const R (&W)[D + 1], R inv, const Co
 // Relax the populations of one cell in place: f* = f + omega (f^eq - f),
 // equation (LBM_scheme).  g[i][l] holds plain values (ref = 0) or deviations;
 // R is the arithmetic type (FP32, or FP64 for the FP64 storage).
+// 1 / rho in the relaxation: the hardware reciprocal (1 ulp) in FP32, as in
+// every kernel that relaxes a cell, and the correctly rounded quotient in FP64
+__device__ __forceinline__ float recip_r(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip_r(double x) { return 1.0 / x; }
+
+// Periodic index of v on a grid of n cells, for v within a tile border of the
+// grid: two compares while v lies in [-n, 2n), the remainder otherwise (tiny
+// grids, where a border wraps several times).
+__device__ __forceinline__ int wrap_coord(int v, int n) {
+  if (v >= -n && v < 2 * n) return v < 0 ? v + n : (v >= n ? v - n : v);
+  return ((v % n) + n) % n;
+}
+
 template <int D, typename R>
 __device__ __forceinline__ void collide(R (&g)[D + 1][2 * D + 1], const CoefT<R>& k) {
   R W[D + 1];
@@ -211,7 +224,7 @@ __device__ __forceinline__ void collide(R (&g)[D + 1][2 * D + 1], const CoefT<R>
     for (int l = 1; l < 2 * D + 1; ++l) s = s + g[i][l];
     W[i] = s;
   }
-  const R inv = R(1) / (W[0] + k.ref);
+  const R inv = recip_r(W[0] + k.ref);
   R eq[D + 1][2 * D + 1];
   equilibrium<D, R>(W, inv, k, eq);
 #pragma unroll

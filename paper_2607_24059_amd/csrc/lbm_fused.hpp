@@ -100,8 +100,8 @@ struct TileK {
     for (int e = threadIdx.x; e < EN; e += NT) {
       const int ex = e % EX, ey = e / EX;
       int x = x0 - H + ex, y = y0 - H + ey;
-      x = ((x % nx) + nx) % nx;  // the border may wrap (several times on tiny grids)
-      y = ((y % ny) + ny) % ny;
+      x = wrap_coord(x, nx);  // the border may wrap (several times on tiny grids)
+      y = wrap_coord(y, ny);
       const int64_t c = static_cast<int64_t>(y) * nx + x;
       float g[3][5];
       gather_cell<2, TR, TM>(sr, sm, x, y, 0, nx, ny, 1, stride, c, g);
@@ -196,8 +196,8 @@ struct TileKr {
       d_of[j] = o < EN ? max(max(max(H - ex, ex - (H + TX - 1)), max(H - ey, ey - (H + TY - 1))), 0) : K;
       if (o < EN) {
         int x = x0 - H + ex, y = y0 - H + ey;
-        x = ((x % nx) + nx) % nx;
-        y = ((y % ny) + ny) % ny;
+        x = wrap_coord(x, nx);
+        y = wrap_coord(y, ny);
         const int64_t c = static_cast<int64_t>(y) * nx + x;
         float g[3][5];
         gather_cell<2, TR, TM>(sr, sm, x, y, 0, nx, ny, 1, stride, c, g);
@@ -317,8 +317,8 @@ struct TileMomK {
     for (int e = threadIdx.x; e < EN; e += NT) {
       const int ex = e % EX, ey = e / EX;
       int x = x0 - H + ex, y = y0 - H + ey;
-      x = ((x % nx) + nx) % nx;  // the border may wrap (several times on tiny grids)
-      y = ((y % ny) + ny) % ny;
+      x = wrap_coord(x, nx);  // the border may wrap (several times on tiny grids)
+      y = wrap_coord(y, ny);
       const int64_t c = static_cast<int64_t>(y) * nx + x;
       int64_t src[4];
       upwind_sources<2>(x, y, 0, nx, ny, 1, c, src);
@@ -424,8 +424,8 @@ struct TileNeqK {
     for (int e = threadIdx.x; e < EN; e += NT) {
       const int ex = e % EX, ey = e / EX;
       int x = x0 - H + ex, y = y0 - H + ey;
-      x = ((x % nx) + nx) % nx;  // the border may wrap (several times on tiny grids)
-      y = ((y % ny) + ny) % ny;
+      x = wrap_coord(x, nx);  // the border may wrap (several times on tiny grids)
+      y = wrap_coord(y, ny);
       const int64_t c = static_cast<int64_t>(y) * nx + x;
       int64_t src[4];
       upwind_sources<2>(x, y, 0, nx, ny, 1, c, src);

@@ -128,8 +128,8 @@ __device__ __forceinline__ void step2_neq_tile(const float* __restrict__ sr, con
   for (int e = threadIdx.x; e < EN; e += NT) {
     const int ex = e % EX, ey = e / EX;
     int x = x0 - 1 + ex, y = y0 - 1 + ey;
-    x = ((x % nx) + nx) % nx;  // the border may wrap (several times on tiny grids)
-    y = ((y % ny) + ny) % ny;
+    x = wrap_coord(x, nx);  // the border may wrap (several times on tiny grids)
+    y = wrap_coord(y, ny);
     const int64_t c = static_cast<int64_t>(y) * nx + x;
     int64_t src[4];
     upwind_sources<2>(x, y, 0, nx, ny, 1, c, src);
@@ -188,8 +188,8 @@ __device__ __forceinline__ void step2_mom_tile(const float* __restrict__ sr, flo
   for (int e = threadIdx.x; e < EN; e += NT) {
     const int ex = e % EX, ey = e / EX;
     int x = x0 - 1 + ex, y = y0 - 1 + ey;
-    x = ((x % nx) + nx) % nx;  // the border may wrap (several times on tiny grids)
-    y = ((y % ny) + ny) % ny;
+    x = wrap_coord(x, nx);  // the border may wrap (several times on tiny grids)
+    y = wrap_coord(y, ny);
     const int64_t c = static_cast<int64_t>(y) * nx + x;
     int64_t src[4];
     upwind_sources<2>(x, y, 0, nx, ny, 1, c, src);
@@ -226,8 +226,8 @@ __device__ __forceinline__ void step2_tile(const TR* __restrict__ sr, const TM* 
   for (int e = threadIdx.x; e < EN; e += NT) {
     const int ex = e % EX, ey = e / EX;
     int x = x0 - 1 + ex, y = y0 - 1 + ey;
-    x = ((x % nx) + nx) % nx;  // the border may wrap (several times on tiny grids)
-    y = ((y % ny) + ny) % ny;
+    x = wrap_coord(x, nx);  // the border may wrap (several times on tiny grids)
+    y = wrap_coord(y, ny);
     const int64_t c = static_cast<int64_t>(y) * nx + x;
     float g[3][5];
     gather_cell<2, TR, TM>(sr, sm, x, y, 0, nx, ny, 1, stride, c, g);
@@ -307,8 +307,8 @@ __global__ __launch_bounds__(NT) void k_step2_3d(const TR* __restrict__ sr, cons
   const int e = ey * EX + ex;  // the column's LDS slot (used only where col holds)
   const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * ZS;
   int x = x0 - 1 + ex, y = y0 - 1 + ey;
-  x = ((x % nx) + nx) % nx;  // the border may wrap (several times on tiny grids)
-  y = ((y % ny) + ny) % ny;
+  x = wrap_coord(x, nx);  // the border may wrap (several times on tiny grids)
+  y = wrap_coord(y, ny);
   const bool inner = col && ex >= 1 && ex <= TX && ey >= 1 && ey <= TY && x0 + ex - 1 < nx && y0 + ey - 1 < ny;
   const int64_t plane = static_cast<int64_t>(nx) * ny;
   const int64_t cxy = static_cast<int64_t>(y) * nx + x;
