@@ -75,6 +75,15 @@ __device__ __forceinline__ void lds_stages(TR (&s_rest)[3][EX * EY], TM (&s_move
   }
 }
 
+// The first step of a tile reads its whole extended tile from HBM while the
+// other block on the compute unit works in LDS; raising the wave priority over
+// that step gets its loads issued ahead of the other block's arithmetic
+// (five-step FP32 tiles at 4096^2: 168 against 159 GLUPS; raising it over the
+// last step's stores as well: 165; moment-only tiles 311 against 264).
+// Results do not depend on it.
+__device__ __forceinline__ void hbm_phase_begin() { __builtin_amdgcn_s_setprio(1); }
+__device__ __forceinline__ void hbm_phase_end() { __builtin_amdgcn_s_setprio(0); }
+
 // XCD: with a one-dimensional grid, consecutive blocks go to the eight XCDs in
 // turn; XCD-major numbering gives each XCD a contiguous band of tiles, so the
 // borders that neighbouring tiles share are read through the same L2.
@@ -97,6 +106,7 @@ struct TileK {
                              TM* __restrict__ dm, int x0, int y0, int nx, int ny, int64_t stride, const Coef& k,
                              TR (&s_rest)[3][EN], TM (&s_move)[12][EN]) {
     // first step, from HBM, over the whole extended tile
+    hbm_phase_begin();
     for (int e = threadIdx.x; e < EN; e += NT) {
       const int ex = e % EX, ey = e / EX;
       int x = x0 - H + ex, y = y0 - H + ey;
@@ -113,6 +123,7 @@ struct TileK {
         for (int m = 0; m < 4; ++m) store_f32(&s_move[i * 4 + m][e], g[i][1 + m]);
       }
     }
+    hbm_phase_end();
     __syncthreads();
     // steps 2 .. K-1 in LDS
     lds_stages<TR, TM, EX, EY, NT, 1, H - 1>(s_rest, s_move, k);
@@ -186,6 +197,7 @@ struct TileKr {
     int e_of[PER];        // LDS slot of each of this thread's cells
     int d_of[PER];        // its distance from the inner tile (step st updates d <= K - st)
     // step 1 from HBM over the whole extended tile
+    hbm_phase_begin();
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
       const int o = static_cast<int>(threadIdx.x) + j * NT;
@@ -212,6 +224,7 @@ struct TileKr {
         }
       }
     }
+    hbm_phase_end();
     __syncthreads();
     // steps 2 .. K-1 in LDS over shrinking regions, then step K to HBM
 #pragma unroll
@@ -314,6 +327,7 @@ struct TileMomK {
 
   __device__ static void run(const float* __restrict__ sr, float* __restrict__ dr, int x0, int y0, int nx, int ny,
                              int64_t stride, const Coef& k, float (&s_w)[3][EN]) {
+    hbm_phase_begin();
     for (int e = threadIdx.x; e < EN; e += NT) {
       const int ex = e % EX, ey = e / EX;
       int x = x0 - H + ex, y = y0 - H + ey;
@@ -327,6 +341,7 @@ struct TileMomK {
 #pragma unroll
       for (int i = 0; i < 3; ++i) s_w[i][e] = out[i];
     }
+    hbm_phase_end();
     __syncthreads();
     lds_stage<1>(s_w, k);
     for (int t = threadIdx.x; t < TX * TY; t += NT) {
@@ -421,6 +436,8 @@ struct TileNeqK {
   __device__ static void run(const float* __restrict__ sr, const neq16* __restrict__ sm, float* __restrict__ dr,
                              neq16* __restrict__ dm, int x0, int y0, int nx, int ny, int64_t stride, const Coef& k,
                              const NeqScale<2>& sc, float (&s_f)[15][EN]) {
+    // (no raised priority here: this first step rebuilds the neighbours'
+    // equilibria and is arithmetic-bound itself; with it, 117 against 130 GLUPS)
     for (int e = threadIdx.x; e < EN; e += NT) {
       const int ex = e % EX, ey = e / EX;
       int x = x0 - H + ex, y = y0 - H + ey;
