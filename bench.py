@@ -38,6 +38,7 @@ BYTES_PER_LUP = {("f32", 2): 120, ("f16_dev", 2): 60, ("bf16_dev", 2): 60, ("f16
 KERNEL_SOURCES = ("paper_2607_24059_amd/csrc/lbm_kernels.hip", "paper_2607_24059_amd/csrc/lbm_device.hpp",
                   "paper_2607_24059_amd/csrc/lbm_fused.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stepK_2d_f32_4096_traffic.json")
+VARIANT_WARMUP = 50   # untimed steps before each variant's timed steps (clocks settle)
 
 
 def log(*a):
@@ -158,7 +159,7 @@ def main():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--variant-steps", type=int, default=200)
+    ap.add_argument("--variant-steps", type=int, default=1000)
     ap.add_argument("--no-equal-error", action="store_true")
     ap.add_argument("--equal-error-seeds", type=int, default=2)
     ap.add_argument("--only", choices=sorted(ONLY),
@@ -237,16 +238,16 @@ def main():
         variants = {}
         vs = args.variant_steps
         log("[bench] variant 2D f32 single step per launch")
-        ms_v, e = time_engine(n, 2, "f32", vs, 10, u0=u0, fuse=1)
+        ms_v, e = time_engine(n, 2, "f32", vs, VARIANT_WARMUP, u0=u0, fuse=1)
         e.close()
         variants[f"2d_{n}_f32_one_step_per_launch"] = _variant(cells, ms_v, BYTES_PER_LUP[("f32", 2)], probe)
         log("[bench] variant 2D f32 two steps per launch")
-        ms_v, e = time_engine(n, 2, "f32", vs, 10, u0=u0, fuse=2)
+        ms_v, e = time_engine(n, 2, "f32", vs, VARIANT_WARMUP, u0=u0, fuse=2)
         e.close()
         variants[f"2d_{n}_f32_two_steps_per_launch"] = _variant(cells, ms_v, BYTES_PER_LUP[("f32", 2)], probe)
         for storage in ("f16_dev", "bf16_dev", "f16_dev_r32", "f16_neq"):
             log(f"[bench] variant 2D {storage}")
-            ms_v, e = time_engine(n, 2, storage, vs, 10, u0=u0)
+            ms_v, e = time_engine(n, 2, storage, vs, VARIANT_WARMUP, u0=u0)
             fuse_v = e.fusion()
             e.close()
             variants[f"2d_{n}_{storage}"] = _variant(cells, ms_v, BYTES_PER_LUP[(storage, 2)], probe)
@@ -258,7 +259,7 @@ def main():
                                 ("f16_neq", None)):
             name = f"3d_{n3}_{storage}" + ("_one_step_per_launch" if fuse_3 == 1 else "")
             log(f"[bench] variant {name}")
-            ms_v, e = time_engine(n3, 3, storage, vs, 10, u0=u3, fuse=fuse_3)
+            ms_v, e = time_engine(n3, 3, storage, vs, VARIANT_WARMUP, u0=u3, fuse=fuse_3)
             fuse_v = e.fusion()
             e.close()
             variants[name] = _variant(n3 ** 3, ms_v, BYTES_PER_LUP[(storage, 3)], probe)
@@ -337,7 +338,7 @@ def moments_variant(dim: int, n: int, steps: int, probe: float) -> dict:
     prm = lbm.make_params(dim, (n,) * dim, dx, dt, 1e-3, omega_rho=1.0, omega_q=1.0, alpha_rho=0.05,
                           storage="f32_moments")   # (omega_rho, alpha_rho) = (1, 1/20) of Section 5.1
     eng = lbm.Engine.create(prm, u0)
-    eng.step(10)
+    eng.step(VARIANT_WARMUP)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -362,7 +363,7 @@ def walls_variant(n: int, steps: int, probe: float) -> dict:
     u0, dx, dt, _ = make_workload(n, 2, 1e-3)
     eng = lbm.Engine.create(lbm.make_params(2, (n, n), dx, dt, 1e-3), u0)
     eng.set_walls(np.stack([np.full(n, 0.05 / dx), np.zeros(n)]), 1.0, correction=True)
-    eng.step(10)
+    eng.step(VARIANT_WARMUP)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -539,7 +540,7 @@ def engine_variant(dim: int, n: int, storage: str, steps: int, probe: float) -> 
     """One run of the step engine on the k^-3 field at the library's default
     fusion: the rate priced at the scheme's bytes per lattice update."""
     u0, *_ = make_workload(n, dim, 1e-3)
-    ms, e = time_engine(n, dim, storage, steps, 10, u0=u0)
+    ms, e = time_engine(n, dim, storage, steps, VARIANT_WARMUP, u0=u0)
     fuse = e.fusion()
     e.close()
     out = _variant(n ** dim, ms, BYTES_PER_LUP[(storage, dim)], probe)
