@@ -147,10 +147,10 @@ struct TileK {
 };
 
 // Variant for 4-byte planes with the rest populations in registers: every
-// thread owns the same cells of the extended tile in all K steps (cell e =
-// threadIdx + j NT), so a cell's rest populations, which only that cell reads,
-// never go through LDS; LDS holds the 12 moving planes only (48 B per cell in
-// FP32, against 60 B).  Not used for 16-bit planes: there the compiler turns
+// thread owns the same cells of the extended tile in all K steps (ownership
+// index threadIdx + j NT, mapped to cells by cell_of), so a cell's rest
+// populations, which only that cell reads, never go through LDS; LDS holds the
+// 12 moving planes only (48 B per cell in FP32, against 60 B).  Not used for 16-bit planes: there the compiler turns
 // the last relaxation FMA and the rounding to FP16 into one fused instruction
 // (one rounding) in some kernels and not in others (two roundings), and this
 // kernel's register round trip of the rest values takes the two-rounding form,
