@@ -305,7 +305,15 @@ __global__ __launch_bounds__(NT) void k_step2_3d(const TR* __restrict__ sr, cons
     col = j < 2 * EY;
   }
   const int e = ey * EX + ex;  // the column's LDS slot (used only where col holds)
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * ZS;
+  // one-dimensional grid in XCD-major order: XCD j (block b runs on XCD b mod
+  // 8) takes the j-th eighth of the tiles in raster order (x, then y, then
+  // z), so the tiles that run together on one XCD are neighbours and share
+  // their border lines through its L2 (38.5 against 37.4 GLUPS at 256^3)
+  const int tx_n = (nx + TX - 1) / TX, ty_n = (ny + TY - 1) / TY;
+  const int nt = tx_n * ty_n * ((nz + ZS - 1) / ZS);
+  const int b = blockIdx.x;
+  const int tt = (nt % 8 == 0) ? (b % 8) * (nt / 8) + b / 8 : b;
+  const int x0 = (tt % tx_n) * TX, y0 = ((tt / tx_n) % ty_n) * TY, z0 = (tt / (tx_n * ty_n)) * ZS;
   int x = x0 - 1 + ex, y = y0 - 1 + ey;
   x = wrap_coord(x, nx);  // the border may wrap (several times on tiny grids)
   y = wrap_coord(y, ny);
@@ -706,7 +714,9 @@ struct Impl {
       auto a = planes_of<TR, TM>(const_cast<void*>(src), g.rest_bytes);
       auto b = planes_of<TR, TM>(dst, g.rest_bytes);
       const Coef k = make_coef<float>(r, D, DEV);
-      dim3 grid((g.nx + kT3X - 1) / kT3X, (g.ny + kT3Y - 1) / kT3Y, (g.nz + kT3Z - 1) / kT3Z);
+      const int64_t tiles = static_cast<int64_t>((g.nx + kT3X - 1) / kT3X) * ((g.ny + kT3Y - 1) / kT3Y) *
+                            ((g.nz + kT3Z - 1) / kT3Z);
+      dim3 grid(static_cast<uint32_t>(tiles), 1, 1);
       hipLaunchKernelGGL((k_step2_3d<TR, TM, kT3X, kT3Y, kT3Z, kT3N>), grid, dim3(kT3N), 0, s, a.rest, a.move, b.rest,
                          b.move, g.nx, g.ny, g.nz, g.stride, k);
       return hipGetLastError();
