@@ -46,11 +46,10 @@ __device__ __forceinline__ void store_f32(float* p, float v) { *p = v; }
 __device__ __forceinline__ void store_f32(_Float16* p, float v) {
   *p = static_cast<_Float16>(v);  // round to nearest even
 }
+// BF16 bits of v, rounded to nearest even by the hardware conversion (one
+// instruction on gfx950, against six for the same rounding in integer code)
 __device__ __forceinline__ uint16_t bf16_bits(float v) {
-  uint32_t u = __float_as_uint(v);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>((u >> 16) | 0x40u);  // quiet NaN
-  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
-  return static_cast<uint16_t>(u >> 16);
+  return __builtin_bit_cast(uint16_t, static_cast<__bf16>(v));
 }
 __device__ __forceinline__ void store_f32(bf16* p, float v) { p->bits = bf16_bits(v); }
 
