@@ -1,7 +1,9 @@
 """What the trained correction network gains over the scheme without it.
 
 The network shipped in paper_2607_24059_amd/closure_weights.npz (trained on
-seeds 0..95 by `python -m paper_2607_24059_amd.closure`) corrects a 256^2 run
+seeds 0..199, 64 pairs each, 25 epochs, by `python -m
+paper_2607_24059_amd.closure`; the file's metadata records the configuration)
+corrects a 256^2 run
 every 4 steps; the reference is the plain scheme at 2048^2 in FP64 storage,
 restricted to 256^2.  On held-out seeds the corrected run must beat the plain
 256^2 run by at least 2x on the divergence-free velocity error after 256
