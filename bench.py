@@ -137,6 +137,15 @@ def cpu_baseline(n: int = 4096, steps: int = 10, nu: float = 1e-3) -> dict:
                       f"of {avail} available ({cpu})"}
 
 
+def headline_kernel(fuse: int) -> str:
+    """The step kernel instantiation the 4096^2 FP32 engine launches at `fuse`
+    steps per launch (tiles as chosen in the library)."""
+    tile = {3: "32,16,256", 4: "64,16,512", 5: "32,32,512", 6: "32,16,256"}
+    if fuse >= 3:
+        return f"k_stepKr_2d<float,float,{tile[fuse]},{fuse},true>"
+    return "k_step2_2d<float,float,256,8,1024>" if fuse == 2 else "k_step<2,float,float>"
+
+
 def traffic_entry(kernel: str):
     """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was
     taken on the current kernel source and on this kernel instantiation; else
@@ -196,12 +205,15 @@ def main():
     mlups = cells / (ms * 1e-3) / 1e6
     lup_bytes = BYTES_PER_LUP[("f32", 2)]
     launch_ms = fuse * ms                    # one launch advances `fuse` steps
-    algo = lup_bytes * fuse * cells          # per launch: 120 B per lattice update x fuse updates per cell
-    achieved = algo / (launch_ms * 1e-3) / 1e9
-    min_bytes = lup_bytes * cells            # the fused kernel's own minimum: state read once + written once
-    kr_tile = {3: "32,16,256", 4: "64,16,512", 5: "32,32,512", 6: "32,16,256"}
-    kname = (f"k_stepKr_2d<float,float,{kr_tile[fuse]},{fuse},true>" if fuse >= 3 else
-             "k_step2_2d<float,float,256,8,1024>" if fuse == 2 else "k_step<2,float,float>")
+    # The unit of the roofline is one cell per launch: a launch must read each
+    # cell's state (15 FP32 values) once and write it once, 120 B, however
+    # many steps it fuses (the intermediate steps stay on chip).
+    unit_bytes = lup_bytes
+    bytes_launch = unit_bytes * cells
+    achieved = bytes_launch / (launch_ms * 1e-3) / 1e9
+    single = lup_bytes * fuse * cells        # the same updates as `fuse` single-step launches
+    kname = headline_kernel(fuse)
+    traffic = traffic_entry(kname)
     result = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -221,16 +233,24 @@ def main():
                    "omega_rho": 1.2, "omega_q": 1.15, "alpha_rho": 0.075, "steps_per_launch": fuse},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": traffic_entry(kname),
+                     "traffic": traffic,
                      "kernel": f"{kname} ({fuse} lattice updates per cell per launch)",
-                     "bytes_per_launch_algorithmic": algo, "launch_us": round(launch_ms * 1e3, 2),
-                     "note": "achieved uses 120 B per lattice update; the fused kernel keeps the "
-                             "intermediate steps on chip, so it moves fewer bytes than single "
-                             "steps and achieved can exceed the HBM peak; traffic is the measured "
-                             "HBM bytes per launch",
-                     "min_bytes_per_launch": min_bytes,
-                     "frac_at_min_bytes": round(min_bytes / (launch_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
-                     "probe_gbs": round(probe, 1), "frac_of_probe": round(achieved / probe, 4)},
+                     "unit_bytes": unit_bytes, "units_per_launch": cells,
+                     "bytes_per_launch": bytes_launch, "launch_us": round(launch_ms * 1e3, 2),
+                     "note": "achieved = the state read once and written once per launch "
+                             "(120 B per cell) / the average launch time from HIP events on the "
+                             "engine's stream; traffic = HBM bytes per launch from the committed "
+                             "rocprofv3 FETCH_SIZE / WRITE_SIZE summary (null if the kernel source "
+                             "changed since)",
+                     "traffic_gbs": round(traffic / (launch_ms * 1e-3) / 1e9, 1) if traffic else None,
+                     "probe_gbs": round(probe, 1), "frac_of_probe": round(achieved / probe, 4),
+                     "equivalent_single_steps": {
+                         "bytes_per_launch": single,
+                         "gbs": round(single / (launch_ms * 1e-3) / 1e9, 1),
+                         "frac_of_peak": round(single / (launch_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                         "note": f"the {fuse} updates per cell priced as {fuse} single-step launches "
+                                 "(120 B per lattice update); above 1 because the fused launch moves "
+                                 "fewer bytes"}},
         "health": {"nonfinite": d["nonfinite"], "mass": d["mass"], "kinetic": d["kinetic"]},
     }
 
@@ -255,8 +275,8 @@ def main():
         del u0
         n3 = 256
         u3, *_ = make_workload(n3, 3, 1e-3)
-        for storage, fuse_3 in (("f32", None), ("f32", 1), ("f16_dev", None), ("f16_dev_r32", None),
-                                ("f16_neq", None)):
+        for storage, fuse_3 in (("f32", None), ("f32", 1), ("f16_dev", None), ("bf16_dev", None),
+                                ("f16_dev_r32", None), ("bf16_dev_r32", None), ("f16_neq", None)):
             name = f"3d_{n3}_{storage}" + ("_one_step_per_launch" if fuse_3 == 1 else "")
             log(f"[bench] variant {name}")
             ms_v, e = time_engine(n3, 3, storage, vs, VARIANT_WARMUP, u0=u3, fuse=fuse_3)

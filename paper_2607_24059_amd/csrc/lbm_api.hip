@@ -93,9 +93,18 @@ void neq_scales(const lbm_params* p, double mu, double aq, float out[4]) {
   }
 }
 
-// diagnostics partials + final slots, then 16 doubles of closure slots
+// Doubles of the partials region: the diagnostics' per-block partials, and
+// the closure's reductions (4-double partials of one 16 x 16 network tile or
+// 256-cell guard block each, lbm_closure_apply / lbm_closure_correct).
+int64_t partial_doubles(const Ops* o, const Geometry& g) {
+  const int64_t diag = o->diag_blocks(g) * kDiagSlots;
+  const int64_t closure = 4 * ((g.cells + 255) / 256 + 256);
+  return diag > closure ? diag : closure;
+}
+
+// partials, then the diagnostics final slots, then 16 doubles of closure slots
 size_t scratch_bytes(const Ops* o, const Geometry& g) {
-  return align_up((static_cast<size_t>(o->diag_blocks(g) + 1) * kDiagSlots + 16) * sizeof(double));
+  return align_up((static_cast<size_t>(partial_doubles(o, g)) + kDiagSlots + 16) * sizeof(double));
 }
 
 // inlet velocity profile of the channel boundaries: [2][ny] doubles (2D)
@@ -168,7 +177,8 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const 
   c->nxt = c->ws + g.buf_bytes;
   c->partials = reinterpret_cast<double*>(c->ws + 2 * g.buf_bytes);
   c->diag_blocks = c->ops->diag_blocks(g);
-  c->result = c->partials + c->diag_blocks * kDiagSlots;
+  c->part_doubles = partial_doubles(c->ops, g);
+  c->result = c->partials + c->part_doubles;
   c->closure_slots = c->result + kDiagSlots;
   c->walls = 0;
   c->wall = lbm::WallArgs{};

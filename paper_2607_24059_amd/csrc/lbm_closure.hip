@@ -374,10 +374,10 @@ lbm_status lbm_set_equilibrium_device(lbm_ctx* c, const float* moments) {
 lbm_status lbm_closure_apply(lbm_ctx* c, const float* moments, const float* y, float s_drho, float s_dq,
                              float guard_factor) {
   if (!c || !moments || !y || c->p.dim != 2 || !(guard_factor > 0)) return LBM_EINVAL;
-  // diagnostics scratch (diag_blocks * 16 doubles): mean partials, then divergence partials
+  // the context's partials region: mean partials, then divergence partials
   double* part = c->partials;
   const int nbm = guard_blocks(c->g.cells);
-  if (static_cast<int64_t>(2 * nbm) * kRedSlots > c->diag_blocks * 16) return LBM_EINVAL;
+  if (static_cast<int64_t>(2 * nbm) * kRedSlots > c->part_doubles) return LBM_EINVAL;
   hipLaunchKernelGGL(k_cl_means, dim3(nbm), dim3(kThreads), 0, c->stream, y, c->g.cells, part);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess)
@@ -394,7 +394,7 @@ lbm_status lbm_closure_correct(lbm_ctx* c, const void* const* packed, const floa
     if (!packed[l] || !bias[l]) return LBM_EINVAL;
   const int64_t tiles = net_infer_tiles(c->g.ny, c->g.nx);
   const int nbg = guard_blocks(c->g.cells);
-  if (tiles == 0 || (tiles + nbg) * kRedSlots > c->diag_blocks * 16) return LBM_EINVAL;
+  if (tiles == 0 || (tiles + nbg) * kRedSlots > c->part_doubles) return LBM_EINVAL;
   double* part = c->partials;
   hipError_t e = c->ops->moments(c->g, c->coef, c->cur, nullptr, moments, c->stream);
   if (e == hipSuccess)

@@ -62,6 +62,10 @@ struct Ops {
 // Most time steps one launch may advance.
 constexpr int kMaxFusion = 6;
 
+// Most blocks of the diagnostics launch (Ops::diag_blocks), hence most FP64
+// partials its final pass reads.
+constexpr int kDiagMaxBlocks = 2048;
+
 // Ops for a dimension and an lbm_storage value; nullptr if unsupported.
 const Ops* ops_for(int dim, int storage);
 
@@ -128,7 +132,8 @@ struct lbm_ctx {
   size_t ws_bytes;
   char* cur;        // buffer holding the state at step `steps`
   char* nxt;        // the other buffer (also used as staging between steps)
-  double* partials; // diagnostics per-block partials
+  double* partials; // diagnostics per-block partials (also the closure's reduction scratch)
+  int64_t part_doubles;  // capacity of `partials` in doubles
   double* result;   // diagnostics final slots
   double* closure_slots;  // lbm_closure_apply decision and report (8 doubles)
   int64_t diag_blocks;

@@ -476,9 +476,15 @@ __global__ __launch_bounds__(256) void k_moments(const TR* __restrict__ r, const
 }
 
 // ----------------------------------------------------------------------------
-// diagnostics: per-block FP64 partials over a tile, then one fixed-order pass
+// diagnostics: FP64 partials of a persistent grid, then one fixed-order pass
 //   partial slots: 0 sum rho, 1..3 sum q_j, 4 sum |q|^2/rho, 5 sum |curl u|^2,
 //   6 sum (div u)^2, 7 max |u|^2, 8 min rho, 9 max rho, 10 non-finite cells
+// The grid has min(tiles, kDiagMaxBlocks) blocks; block b walks the tiles
+// b, b + G, b + 2G, ... of the XCD-major tile order, so the blocks that run
+// together on one XCD hold neighbouring tiles and share their halo lines in
+// its L2.  Each thread accumulates its cells' contributions in that fixed
+// order and the block reduces them once, so the result does not depend on
+// timing, and the final pass reads at most kDiagMaxBlocks partials.
 // ----------------------------------------------------------------------------
 constexpr int kDiagSlots = 16;
 constexpr int kDiagThreads = 256;
@@ -487,11 +493,11 @@ template <int D>
 struct DiagTile;
 template <>
 struct DiagTile<2> {
-  static constexpr int TX = 32, TY = 8, TZ = 1;
+  static constexpr int TX = 64, TY = 16, TZ = 1;
 };
 template <>
 struct DiagTile<3> {
-  static constexpr int TX = 8, TY = 8, TZ = 4;
+  static constexpr int TX = 32, TY = 8, TZ = 4;
 };
 
 __device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
@@ -542,6 +548,13 @@ __device__ void block_reduce(double (&a)[kDiagSlots]) {
   }
 }
 
+template <int D>
+__host__ __device__ inline int64_t diag_tile_count(int nx, int ny, int nz) {
+  using T = DiagTile<D>;
+  return static_cast<int64_t>((nx + T::TX - 1) / T::TX) * ((ny + T::TY - 1) / T::TY) *
+         (D == 3 ? (nz + T::TZ - 1) / T::TZ : 1);
+}
+
 template <int D, typename TR, typename TM>
 __global__ __launch_bounds__(kDiagThreads) void k_diag(const TR* __restrict__ r,
                                                       const TM* __restrict__ m, int nx, int ny,
@@ -550,75 +563,89 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag(const TR* __restrict__ r,
   using T = DiagTile<D>;
   constexpr int HX = T::TX + 2, HY = T::TY + 2, HZ = (D == 3) ? T::TZ + 2 : 1;
   constexpr int HN = HX * HY * HZ;
+  constexpr int CELLS = T::TX * T::TY * T::TZ;
+  static_assert(CELLS % kDiagThreads == 0, "whole cells per thread");
   __shared__ double sw[D + 1][HN];  // rho, q_j on the tile plus a one-cell halo
-  const int x0 = blockIdx.x * T::TX, y0 = blockIdx.y * T::TY, z0 = blockIdx.z * T::TZ;
+  const int tiles_x = (nx + T::TX - 1) / T::TX, tiles_y = (ny + T::TY - 1) / T::TY;
+  const int nt = static_cast<int>(diag_tile_count<D>(nx, ny, nz));
   const int64_t plane = static_cast<int64_t>(nx) * ny;
-  for (int t = threadIdx.x; t < HN; t += kDiagThreads) {
-    const int hx = t % HX, hy = (t / HX) % HY, hz = t / (HX * HY);
-    const int gx = wrap(x0 + hx - 1, nx), gy = wrap(y0 + hy - 1, ny);
-    const int gz = (D == 3) ? wrap(z0 + hz - 1, nz) : 0;
-    const int64_t c = static_cast<int64_t>(gz) * plane + static_cast<int64_t>(gy) * nx + gx;
-    double s[D + 1];
-    cell_sums<D>(r, m, c, stride, s);
-    sw[0][t] = ref + s[0];
-#pragma unroll
-    for (int j = 0; j < D; ++j) sw[1 + j][t] = s[1 + j] / dx;
-  }
-  __syncthreads();
-
+  const double inv2dx = 1.0 / (2.0 * dx);
   double a[kDiagSlots];
   identity(a);
-  const int tx = threadIdx.x % T::TX, ty = (threadIdx.x / T::TX) % T::TY, tz = threadIdx.x / (T::TX * T::TY);
-  const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
-  if (x < nx && y < ny && (D == 2 || z < nz)) {
-    const int h = ((tz + (D == 3 ? 1 : 0)) * HY + (ty + 1)) * HX + (tx + 1);
-    const int sx = 1, sy = HX, sz = HX * HY;
-    const double rho = sw[0][h];
-    double q[D], u2 = 0.0, q2 = 0.0;
-    bool finite = isfinite(rho);
+  for (int sched = blockIdx.x; sched < nt; sched += gridDim.x) {
+    // XCD-major tile order: schedule index s of XCD s mod 8 maps into the
+    // (s mod 8)-th eighth of the tiles in raster order
+    const int t = (nt % 8 == 0) ? (sched % 8) * (nt / 8) + sched / 8 : sched;
+    const int x0 = (t % tiles_x) * T::TX, y0 = ((t / tiles_x) % tiles_y) * T::TY;
+    const int z0 = (D == 3) ? (t / (tiles_x * tiles_y)) * T::TZ : 0;
+    __syncthreads();  // the previous tile's LDS values are no longer read
+    for (int h = threadIdx.x; h < HN; h += kDiagThreads) {
+      const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
+      const int gx = wrap(x0 + hx - 1, nx), gy = wrap(y0 + hy - 1, ny);
+      const int gz = (D == 3) ? wrap(z0 + hz - 1, nz) : 0;
+      const int64_t c = static_cast<int64_t>(gz) * plane + static_cast<int64_t>(gy) * nx + gx;
+      double s[D + 1];
+      cell_sums<D>(r, m, c, stride, s);
+      sw[0][h] = ref + s[0];
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
-      q[j] = sw[1 + j][h];
-      finite = finite && isfinite(q[j]);
-      q2 += q[j] * q[j];
+      for (int j = 0; j < D; ++j) sw[1 + j][h] = s[1 + j] / dx;
     }
-    u2 = q2 / (rho * rho);
-    // u_j at the neighbour at offset o
-    auto U = [&](int j, int o) { return sw[1 + j][h + o] / sw[0][h + o]; };
-    const double inv2dx = 1.0 / (2.0 * dx);
-    const int st[3] = {sx, sy, sz};
-    double div = 0.0;
+    __syncthreads();
 #pragma unroll
-    for (int j = 0; j < D; ++j) div += (U(j, st[j]) - U(j, -st[j])) * inv2dx;
-    double curl2 = 0.0;
-    if constexpr (D == 2) {
-      const double w = (U(1, sx) - U(1, -sx)) * inv2dx - (U(0, sy) - U(0, -sy)) * inv2dx;
-      curl2 = w * w;
-    } else {
-      const double wx = (U(2, sy) - U(2, -sy)) * inv2dx - (U(1, sz) - U(1, -sz)) * inv2dx;
-      const double wy = (U(0, sz) - U(0, -sz)) * inv2dx - (U(2, sx) - U(2, -sx)) * inv2dx;
-      const double wz = (U(1, sx) - U(1, -sx)) * inv2dx - (U(0, sy) - U(0, -sy)) * inv2dx;
-      curl2 = wx * wx + wy * wy + wz * wz;
+    for (int k = 0; k < CELLS / kDiagThreads; ++k) {
+      const int o = static_cast<int>(threadIdx.x) + k * kDiagThreads;
+      const int tx = o % T::TX, ty = (o / T::TX) % T::TY, tz = o / (T::TX * T::TY);
+      const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
+      if (x >= nx || y >= ny || (D == 3 && z >= nz)) continue;
+      const int h = ((tz + (D == 3 ? 1 : 0)) * HY + (ty + 1)) * HX + (tx + 1);
+      const int sx = 1, sy = HX, sz = HX * HY;
+      const double rho = sw[0][h];
+      double q[D], q2 = 0.0;
+      bool finite = isfinite(rho);
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        q[j] = sw[1 + j][h];
+        finite = finite && isfinite(q[j]);
+        q2 += q[j] * q[j];
+      }
+      const double u2 = q2 / (rho * rho);
+      // u_j at the neighbour at offset o
+      auto U = [&](int j, int off) { return sw[1 + j][h + off] / sw[0][h + off]; };
+      const int st[3] = {sx, sy, sz};
+      double div = 0.0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) div += (U(j, st[j]) - U(j, -st[j])) * inv2dx;
+      double curl2 = 0.0;
+      if constexpr (D == 2) {
+        const double w = (U(1, sx) - U(1, -sx)) * inv2dx - (U(0, sy) - U(0, -sy)) * inv2dx;
+        curl2 = w * w;
+      } else {
+        const double wx = (U(2, sy) - U(2, -sy)) * inv2dx - (U(1, sz) - U(1, -sz)) * inv2dx;
+        const double wy = (U(0, sz) - U(0, -sz)) * inv2dx - (U(2, sx) - U(2, -sx)) * inv2dx;
+        const double wz = (U(1, sx) - U(1, -sx)) * inv2dx - (U(0, sy) - U(0, -sy)) * inv2dx;
+        curl2 = wx * wx + wy * wy + wz * wz;
+      }
+      a[0] += rho;
+#pragma unroll
+      for (int j = 0; j < D; ++j) a[1 + j] += q[j];
+      a[4] += q2 / rho;
+      a[5] += curl2;
+      a[6] += div * div;
+      a[7] = fmax(a[7], u2);
+      a[8] = fmin(a[8], rho);
+      a[9] = fmax(a[9], rho);
+      a[10] += finite ? 0.0 : 1.0;
     }
-    a[0] = rho;
-#pragma unroll
-    for (int j = 0; j < D; ++j) a[1 + j] = q[j];
-    a[4] = q2 / rho;
-    a[5] = curl2;
-    a[6] = div * div;
-    a[7] = u2;
-    a[8] = rho;
-    a[9] = rho;
-    a[10] = finite ? 0.0 : 1.0;
   }
   block_reduce(a);
   if (threadIdx.x == 0) {
-    const int64_t b = (static_cast<int64_t>(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
 #pragma unroll
-    for (int s = 0; s < kDiagSlots; ++s) partials[b * kDiagSlots + s] = a[s];
+    for (int s = 0; s < kDiagSlots; ++s) partials[static_cast<int64_t>(blockIdx.x) * kDiagSlots + s] = a[s];
   }
 }
 
+// The final pass: thread t combines partials t, t + 256, ... in order, then
+// the block reduces them in a fixed order.
 __global__ __launch_bounds__(kDiagThreads) void k_diag_final(const double* __restrict__ partials,
                                                             int64_t nblocks,
                                                             double* __restrict__ result) {
@@ -842,22 +869,16 @@ struct Impl {
     return hipGetLastError();
   }
 
-  static dim3 diag_grid(const Geometry& g) {
-    using T = DiagTile<D>;
-    return dim3((g.nx + T::TX - 1) / T::TX, (g.ny + T::TY - 1) / T::TY,
-                D == 3 ? (g.nz + T::TZ - 1) / T::TZ : 1);
-  }
-
   static int64_t diag_blocks(const Geometry& g) {
-    const dim3 gr = diag_grid(g);
-    return static_cast<int64_t>(gr.x) * gr.y * gr.z;
+    const int64_t nt = diag_tile_count<D>(g.nx, g.ny, g.nz);
+    return nt < kDiagMaxBlocks ? nt : kDiagMaxBlocks;
   }
 
   static hipError_t diag(const Geometry& g, const RunCoef& r, const void* src, double* partials,
                          double* result, hipStream_t s) {
     auto a = planes_of<TR, TM>(const_cast<void*>(src), g.rest_bytes);
-    hipLaunchKernelGGL((k_diag<D, TR, TM>), diag_grid(g), dim3(kDiagThreads), 0, s, a.rest, a.move,
-                       g.nx, g.ny, g.nz, g.stride, DEV ? r.ref : 0.0, r.dx, partials);
+    hipLaunchKernelGGL((k_diag<D, TR, TM>), dim3(static_cast<uint32_t>(diag_blocks(g))), dim3(kDiagThreads), 0, s,
+                       a.rest, a.move, g.nx, g.ny, g.nz, g.stride, DEV ? r.ref : 0.0, r.dx, partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kDiagThreads), 0, s, partials, diag_blocks(g),
