@@ -176,6 +176,20 @@ lbm_status lbm_moments_device(lbm_ctx* ctx, float* out);
  * struct is filled either way).  Synchronises. */
 lbm_status lbm_diagnostics(lbm_ctx* ctx, lbm_diag* out);
 
+/* Allocation-free diagnostics, for callers that cannot allocate device
+ * memory (serving loops, harnesses that forbid allocation): the results of
+ * lbm_diagnostics, bit for bit (same kernels, same fixed reduction order),
+ * with the per-block partials and the final slots in a static device array
+ * of the library instead of the context's workspace: at most 2048 partials of
+ * 16 doubles plus the final slots, 262 KB per GPU, held until the process
+ * ends.  lbm_init looks up the array's device address once per device.
+ * Nothing is allocated and nothing needs clearing (every slot read is written
+ * earlier in the same call).  Calls that overlap on one GPU (several threads
+ * or streams) share the array and race: serialise them.  LBM_EINVAL for NULL
+ * arguments or a partial count above the array's capacity; LBM_EDEVICE if the
+ * address lookup failed; LBM_ENONFINITE as lbm_diagnostics.  Synchronises. */
+lbm_status lbm_diagnostics_noalloc(lbm_ctx* ctx, lbm_diag* out);
+
 /* Size of a full state snapshot: every population plane (without padding:
  * the D+1 rest planes of cells x rest element, then the (D+1) 2D moving planes
  * of cells x moving element, in the element types of the storage mode), then

@@ -5,6 +5,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "lbm.h"
@@ -119,6 +120,38 @@ char* staging(lbm_ctx* c) {
   return c->ws + 2 * c->g.buf_bytes + scratch_bytes(c->ops, c->g) + profile_bytes(&c->p);
 }
 
+// ---- scratch of the allocation-free diagnostics ------------------------------
+// lbm_diagnostics_noalloc keeps the per-block partials and the final slots in
+// this file-scope device array instead of the workspace: at most
+// kDiagMaxBlocks partials of kDiagSlots doubles, then the final slots
+// (262 KB).  Every GPU the library runs on holds its own copy until the
+// process ends.  In host code the array's name is not a device address: its
+// address on each device is looked up once, with that device current
+// (static_scratch_of_current_device), and only that pointer is passed on.
+constexpr int64_t kStaticDiagDoubles = (static_cast<int64_t>(lbm::kDiagMaxBlocks) + 1) * kDiagSlots;
+static __device__ __align__(256) double scratch[kStaticDiagDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device (looked up once per device).
+hipError_t static_scratch_of_current_device(double** out) {
+  int d = -1;
+  hipError_t e = hipGetDevice(&d);
+  if (e != hipSuccess) return e;
+  if (d < 0 || d >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_dev[d]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[d] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_dev[d];
+  return hipSuccess;
+}
+
 void default_block(const Geometry& g, int* bx, int* by) {
   int x = 256;
   while (x > 64 && x / 2 >= g.nx) x /= 2;
@@ -186,6 +219,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const 
                                 : nullptr;
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->steps = 0;
+  c->static_scratch = nullptr;
   default_block(g, &c->bx, &c->by);
   // deeper fusion from 1024^2 cells on; smaller grids are launch-bound and
   // keep the two-step kernel's small tiles
@@ -204,6 +238,8 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const 
   if (e == hipSuccess) e = c->ops->init(g, c->coef, su, sr, c->cur, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->closure_slots, 0, 16 * sizeof(double), c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  // set-up of lbm_diagnostics_noalloc: the static scratch's address on this device
+  if (e == hipSuccess) e = static_scratch_of_current_device(&c->static_scratch);
   if (e != hipSuccess) {
     delete c;
     return LBM_EDEVICE;
@@ -279,11 +315,13 @@ lbm_status lbm_moments_device(lbm_ctx* c, float* out) {
   return dev(c->ops->moments(c->g, c->coef, c->cur, nullptr, out, c->stream));
 }
 
-lbm_status lbm_diagnostics(lbm_ctx* c, lbm_diag* out) {
-  if (!c || !out) return LBM_EINVAL;
+}  // extern "C"
+
+// Diagnostics with the partials and final slots in `partials` and `result`.
+static lbm_status diagnostics_into(lbm_ctx* c, double* partials, double* result, lbm_diag* out) {
   double r[kDiagSlots];
-  hipError_t e = c->ops->diag(c->g, c->coef, c->cur, c->partials, c->result, c->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(r, c->result, sizeof(r), hipMemcpyDeviceToHost, c->stream);
+  hipError_t e = c->ops->diag(c->g, c->coef, c->cur, partials, result, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(r, result, sizeof(r), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return LBM_EDEVICE;
   const double dv = pow(c->p.dx, c->p.dim);
@@ -301,6 +339,26 @@ lbm_status lbm_diagnostics(lbm_ctx* c, lbm_diag* out) {
   out->nonfinite = static_cast<int64_t>(r[10]);
   out->flags = c->flags;
   return out->nonfinite > 0 ? LBM_ENONFINITE : LBM_OK;
+}
+
+extern "C" {
+
+lbm_status lbm_diagnostics(lbm_ctx* c, lbm_diag* out) {
+  if (!c || !out) return LBM_EINVAL;
+  return diagnostics_into(c, c->partials, c->result, out);
+}
+
+// The kernels of lbm_diagnostics, with their scratch in the static array:
+// every partial slot the final pass reads is written by the first launch of
+// the same call, so nothing needs clearing; calls that overlap on one GPU
+// share the array and race.
+lbm_status lbm_diagnostics_noalloc(lbm_ctx* c, lbm_diag* out) {
+  if (!c || !out) return LBM_EINVAL;
+  if (!c->static_scratch) return LBM_EDEVICE;
+  if (c->diag_blocks < 1 || c->diag_blocks > lbm::kDiagMaxBlocks) return LBM_EINVAL;
+  double* partials = c->static_scratch;
+  double* result = c->static_scratch + static_cast<int64_t>(lbm::kDiagMaxBlocks) * kDiagSlots;
+  return diagnostics_into(c, partials, result, out);
 }
 
 // The snapshot holds every plane without its padding: the rest planes

@@ -136,6 +136,7 @@ struct lbm_ctx {
   int64_t part_doubles;  // capacity of `partials` in doubles
   double* result;   // diagnostics final slots
   double* closure_slots;  // lbm_closure_apply decision and report (8 doubles)
+  double* static_scratch; // device address of the library's static diagnostics scratch on this device
   int64_t diag_blocks;
   hipStream_t stream;
   int64_t steps;

@@ -87,6 +87,7 @@ SIGNATURES = {
     "lbm_moments": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "lbm_moments_device": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lbm_diagnostics": (C.c_int, [C.c_void_p, C.POINTER(lbm_diag)]),
+    "lbm_diagnostics_noalloc": (C.c_int, [C.c_void_p, C.POINTER(lbm_diag)]),
     "lbm_state_bytes": (C.c_size_t, [C.c_void_p]),
     "lbm_save_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "lbm_load_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
@@ -190,6 +191,14 @@ def lbm_diagnostics(ctx: int) -> tuple[int, lbm_diag]:
     st = lib().lbm_diagnostics(C.c_void_p(ctx), C.byref(d))
     if st not in (LBM_OK, LBM_ENONFINITE):
         raise LbmError(st, "lbm_diagnostics")
+    return st, d
+
+
+def lbm_diagnostics_noalloc(ctx: int) -> tuple[int, lbm_diag]:
+    d = lbm_diag()
+    st = lib().lbm_diagnostics_noalloc(C.c_void_p(ctx), C.byref(d))
+    if st not in (LBM_OK, LBM_ENONFINITE):
+        raise LbmError(st, "lbm_diagnostics_noalloc")
     return st, d
 
 
