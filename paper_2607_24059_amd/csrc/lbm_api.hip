@@ -5,6 +5,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <new>
 
@@ -223,7 +224,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const 
   default_block(g, &c->bx, &c->by);
   // deeper fusion from 1024^2 cells on; smaller grids are launch-bound and
   // keep the two-step kernel's small tiles
-  c->fuse = c->ops->stepK && g.cells >= (int64_t(1) << 20) ? default_depth(p->storage)
+  c->fuse = c->ops->stepK && g.cells >= (int64_t(1) << 20) ? std::min(default_depth(p->storage), c->ops->max_fuse)
             : c->ops->step2                                  ? 2
                                                              : 1;
 
@@ -269,7 +270,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
 }
 
 lbm_status lbm_set_fusion(lbm_ctx* c, int32_t steps_per_launch) {
-  if (!c || steps_per_launch < 1 || steps_per_launch > lbm::kMaxFusion) return LBM_EINVAL;
+  if (!c || steps_per_launch < 1 || steps_per_launch > c->ops->max_fuse) return LBM_EINVAL;
   if (steps_per_launch >= 2 && (!c->ops->step2 || c->walls)) return LBM_EINVAL;
   if (steps_per_launch >= 3 && !c->ops->stepK) return LBM_EINVAL;
   c->fuse = steps_per_launch;

@@ -156,6 +156,11 @@ struct CoefT {
   R w_rho;     // omega_rho
   R w_q;       // omega_q
   R ref;       // rho_ref for deviation storage, 0 for plain storage
+  // the relaxation's coefficients with omega folded in (collide)
+  R r_rho, r_q;        // 1 - omega (exact in R: omega lies in (0, 2))
+  R aw_rho, aw_q;      // omega alpha
+  R d2aw_rho, d2aw_q;  // 2 D (omega alpha), from the rounded omega alpha
+  R cw_rho, cw_q;      // omega / (2 mu)
 };
 using Coef = CoefT<float>;
 
@@ -213,6 +218,14 @@ __device__ __forceinline__ int wrap_coord(int v, int n) {
   return ((v % n) + n) % n;
 }
 
+// Relaxation of one cell, f* = f + omega (f^eq - f), evaluated as
+// f* = (1 - omega) f + omega f^eq with omega folded into the equilibrium
+// coefficients (omega alpha, omega / (2 mu)), so that each entry costs one FMA
+// after omega f^eq (about 60 operations per cell in 2D against 79 for the
+// separate difference and FMA).  The rest entry, omega (1 - 2 D alpha) W, is
+// formed as omega W - (2 D omega alpha) W with 2 D omega alpha = 2 D times the
+// rounded omega alpha: the coefficients of one set then sum to omega exactly
+// in 2D (see equilibrium() for why a rounded 1 - 2 D alpha would bias the sums).
 template <int D, typename R>
 __device__ __forceinline__ void collide(R (&g)[D + 1][2 * D + 1], const CoefT<R>& k) {
   R W[D + 1];
@@ -224,13 +237,32 @@ __device__ __forceinline__ void collide(R (&g)[D + 1][2 * D + 1], const CoefT<R>
     W[i] = s;
   }
   const R inv = recip_r(W[0] + k.ref);
-  R eq[D + 1][2 * D + 1];
-  equilibrium<D, R>(W, inv, k, eq);
+  const R wl = W[0];
+  {  // density set: F_{rho j} = W_j
+    const R base = k.aw_rho * wl;
+    g[0][0] = fma_r(k.r_rho, g[0][0], fma_r(-k.d2aw_rho, wl, k.w_rho * wl));
 #pragma unroll
-  for (int i = 0; i < D + 1; ++i) {
-    const R w = (i == 0) ? k.w_rho : k.w_q;
+    for (int j = 0; j < D; ++j) {
+      const R flux = k.cw_rho * W[1 + j];
+      g[0][1 + 2 * j] = fma_r(k.r_rho, g[0][1 + 2 * j], base + flux);
+      g[0][2 + 2 * j] = fma_r(k.r_rho, g[0][2 + 2 * j], base - flux);
+    }
+  }
+  // momentum sets: F_{ij} = W_i W_j / W_rho + delta_ij P(W_rho), P(rho) = rho
+  const R cinv = k.cw_q * inv;
+  const R cwl = k.cw_q * wl;
 #pragma unroll
-    for (int l = 0; l < 2 * D + 1; ++l) g[i][l] = fma_r(w, eq[i][l] - g[i][l], g[i][l]);
+  for (int i = 0; i < D; ++i) {
+    const R wi = W[1 + i];
+    const R base = k.aw_q * wi;
+    g[1 + i][0] = fma_r(k.r_q, g[1 + i][0], fma_r(-k.d2aw_q, wi, k.w_q * wi));
+    const R ci = cinv * wi;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const R flux = (i == j) ? fma_r(ci, W[1 + j], cwl) : ci * W[1 + j];
+      g[1 + i][1 + 2 * j] = fma_r(k.r_q, g[1 + i][1 + 2 * j], base + flux);
+      g[1 + i][2 + 2 * j] = fma_r(k.r_q, g[1 + i][2 + 2 * j], base - flux);
+    }
   }
 }
 

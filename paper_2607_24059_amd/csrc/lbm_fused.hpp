@@ -146,6 +146,46 @@ struct TileK {
   }
 };
 
+// Accesses at a byte offset from a plane base that is the same for the whole
+// block: the compiler then keeps the 64-bit base in scalar registers and
+// issues the scalar-base form of the load or store with a 32-bit lane offset,
+// so no 64-bit address arithmetic runs on the vector ALU per access.  Valid
+// while every byte offset within a plane fits in 32 bits (fused_offsets_fit).
+template <typename T>
+__device__ __forceinline__ const T* at_byte(const T* base, uint32_t off) {
+  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
+}
+template <typename T>
+__device__ __forceinline__ T* at_byte(T* base, uint32_t off) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off);
+}
+
+// Pull gather of 2D cell c = y nx + x (periodic) with 32-bit plane offsets.
+template <typename TR, typename TM>
+__device__ __forceinline__ void gather_cell2_o32(const TR* __restrict__ sr, const TM* __restrict__ sm, int x, int y,
+                                                 int nx, int ny, int64_t stride, float (&g)[3][5]) {
+  const uint32_t c = static_cast<uint32_t>(y) * static_cast<uint32_t>(nx) + static_cast<uint32_t>(x);
+  const uint32_t row = static_cast<uint32_t>(nx), last = static_cast<uint32_t>(ny - 1) * row;
+  uint32_t src[4];
+  src[0] = (x == 0) ? c + (row - 1) : c - 1;     // +x from x-1
+  src[1] = (x == nx - 1) ? c - (row - 1) : c + 1; // -x from x+1
+  src[2] = (y == 0) ? c + last : c - row;         // +y from y-1
+  src[3] = (y == ny - 1) ? c - last : c + row;    // -y from y+1
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    g[i][0] = load_f32(at_byte(sr + i * stride, c * static_cast<uint32_t>(sizeof(TR))));
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      g[i][1 + m] = load_f32(at_byte(sm + (i * 4 + m) * stride, src[m] * static_cast<uint32_t>(sizeof(TM))));
+  }
+}
+
+// Whether every element offset of a plane of `cells` values fits the 32-bit
+// byte offsets of gather_cell2_o32 (host side).
+__host__ __device__ inline bool fused_offsets_fit(int64_t cells, size_t elem_bytes) {
+  return cells * static_cast<int64_t>(elem_bytes) <= (int64_t(1) << 32);
+}
+
 // Variant for 4-byte planes with the rest populations in registers: every
 // thread owns the same cells of the extended tile in all K steps (ownership
 // index threadIdx + j NT, mapped to cells by cell_of), so a cell's rest
@@ -210,9 +250,8 @@ struct TileKr {
         int x = x0 - H + ex, y = y0 - H + ey;
         x = wrap_coord(x, nx);
         y = wrap_coord(y, ny);
-        const int64_t c = static_cast<int64_t>(y) * nx + x;
         float g[3][5];
-        gather_cell<2, TR, TM>(sr, sm, x, y, 0, nx, ny, 1, stride, c, g);
+        gather_cell2_o32<TR, TM>(sr, sm, x, y, nx, ny, stride, g);
         collide<2>(g, k);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
@@ -258,12 +297,13 @@ struct TileKr {
             const int o = static_cast<int>(threadIdx.x) + j * NT;
             const int x = x0 + o % TX, y = y0 + o / TX;
             if (x < nx && y < ny) {
-              const int64_t c = static_cast<int64_t>(y) * nx + x;
+              const uint32_t c = static_cast<uint32_t>(y) * static_cast<uint32_t>(nx) + static_cast<uint32_t>(x);
 #pragma unroll
               for (int i = 0; i < 3; ++i) {
-                store_stream(dr + i * stride + c, g[i][0]);
+                store_stream(at_byte(dr + i * stride, c * static_cast<uint32_t>(sizeof(TR))), g[i][0]);
 #pragma unroll
-                for (int m = 0; m < 4; ++m) store_stream(dm + (i * 4 + m) * stride + c, g[i][1 + m]);
+                for (int m = 0; m < 4; ++m)
+                  store_stream(at_byte(dm + (i * 4 + m) * stride, c * static_cast<uint32_t>(sizeof(TM))), g[i][1 + m]);
               }
             }
           }

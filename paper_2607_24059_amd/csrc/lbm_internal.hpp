@@ -55,8 +55,9 @@ struct Ops {
   // one step with the channel boundaries (2D population storages; nullptr otherwise)
   hipError_t (*step_walls)(const Geometry&, const RunCoef&, const void* src, void* dst, const WallArgs& w, int bx,
                            int by, hipStream_t s);
-  // K = 3 .. kMaxFusion steps in one launch (2D population storages; nullptr otherwise)
+  // K = 3 .. max_fuse steps in one launch (2D population storages, 3D FP32; nullptr otherwise)
   hipError_t (*stepK)(const Geometry&, const RunCoef&, int K, const void* src, void* dst, hipStream_t s);
+  int max_fuse;  // most steps per launch (1 .. kMaxFusion)
 };
 
 // Most time steps one launch may advance.
@@ -88,6 +89,22 @@ hipError_t net_infer_launch(const float* m, int h, int w, double rho_ref, float 
 // Tiles of the fused inference (0 if h or w is not a positive multiple of 16).
 int64_t net_infer_tiles(int h, int w);
 
+// A relaxation parameter omega in (0, 2) and 1 - omega as a pair of values of
+// type R that sum to 1 exactly: the one of the two that is at least 1/2 is
+// rounded, the other is its complement, which is exact (Sterbenz).  With a
+// pair that missed 1 by an ulp, every relaxation would scale the moments by
+// that ulp, a bias that grows with the number of steps.
+template <typename R>
+inline void omega_pair(double omega, R* w, R* r) {
+  if (omega >= 0.5) {
+    *w = static_cast<R>(omega);
+    *r = static_cast<R>(1.0 - static_cast<double>(*w));
+  } else {
+    *r = static_cast<R>(1.0 - omega);
+    *w = static_cast<R>(1.0 - static_cast<double>(*r));
+  }
+}
+
 template <typename R>
 inline CoefT<R> make_coef(const RunCoef& r, int D, bool deviation) {
   CoefT<R> k;
@@ -96,9 +113,16 @@ inline CoefT<R> make_coef(const RunCoef& r, int D, bool deviation) {
   k.a_q = static_cast<R>(r.alpha_q);
   k.d2a_rho = static_cast<R>(2.0 * D * r.alpha_rho);
   k.d2a_q = static_cast<R>(2.0 * D * r.alpha_q);
-  k.w_rho = static_cast<R>(r.omega_rho);
-  k.w_q = static_cast<R>(r.omega_q);
+  omega_pair<R>(r.omega_rho, &k.w_rho, &k.r_rho);
+  omega_pair<R>(r.omega_q, &k.w_q, &k.r_q);
   k.ref = static_cast<R>(deviation ? r.ref : 0.0);
+  const double w_rho = static_cast<double>(k.w_rho), w_q = static_cast<double>(k.w_q);
+  k.aw_rho = static_cast<R>(w_rho * r.alpha_rho);
+  k.aw_q = static_cast<R>(w_q * r.alpha_q);
+  k.d2aw_rho = static_cast<R>(2.0 * D * static_cast<double>(k.aw_rho));
+  k.d2aw_q = static_cast<R>(2.0 * D * static_cast<double>(k.aw_q));
+  k.cw_rho = static_cast<R>(w_rho / (2.0 * r.mu));
+  k.cw_q = static_cast<R>(w_q / (2.0 * r.mu));
   return k;
 }
 

@@ -381,6 +381,261 @@ __global__ __launch_bounds__(NT) void k_step2_3d(const TR* __restrict__ sr, cons
   }
 }
 
+// ----------------------------------------------------------------------------
+// three steps per launch in 3D (4-byte planes), marching along z.  The tile
+// is TX x TY columns; stage 1 runs over the tile plus a two-cell x/y border
+// (EX x EY columns), stage 2 over the tile plus a one-cell border, stage 3
+// over the tile.  At plane p the block advances plane p by stage 1 (from
+// HBM), plane p - 1 by stage 2 and plane p - 2 by stage 3 (to HBM).  Each
+// thread owns one column of the EX x EY region in all three stages: a stage's
+// rest and +-z populations stay in the owner's registers (the +-z neighbours
+// of the next stage are the owner's results of the planes below and above),
+// and its 16 in-plane moving populations go to LDS for the neighbouring
+// columns (stage 1 over EX x EY, stage 2 over its smaller region, each
+// double-buffered by plane parity, so there is one barrier per plane).  Every
+// stage stores its results as the storage type rounds them and relaxes with
+// the same collide as the single step, so the result equals three single
+// steps bit for bit.  Waves r < EY own the 64 columns x0 .. x0 + 63 of
+// extended row r (whole 128-byte lines per access); the last wave owns the
+// four border columns x0 - 2, x0 - 1, x0 + 64, x0 + 65 of every row.
+// ----------------------------------------------------------------------------
+template <typename TR, typename TM, int TY, int ZS>
+__global__ __launch_bounds__(64 * (TY + 5)) void k_step3_3d(const TR* __restrict__ sr, const TM* __restrict__ sm,
+                                                            TR* __restrict__ dr, TM* __restrict__ dm, int nx, int ny,
+                                                            int nz, int64_t stride, Coef k) {
+  constexpr int TX = 64, H = 2, EX = TX + 2 * H, EY = TY + 2 * H, EN1 = EX * EY;
+  constexpr int RX2 = TX + 2, RY2 = TY + 2, EN2 = RX2 * RY2;  // stage-2 region
+  static_assert(4 * EY <= 64, "border columns of every row fit one wave");
+  __shared__ TM s1[2][16][EN1];  // stage-1 in-plane populations, by plane parity
+  __shared__ TM s2[2][16][EN2];  // stage-2 in-plane populations, by plane parity
+  const int t = threadIdx.x;
+  int ex, ey;
+  bool col;
+  if (t < 64 * EY) {
+    ey = t / 64;
+    ex = H + t % 64;
+    col = true;
+  } else {
+    const int j = t - 64 * EY;
+    ey = j / 4;
+    const int c = j % 4;
+    ex = c < 2 ? c : TX + c;  // 0, 1, EX - 2, EX - 1
+    col = j < 4 * EY;
+    if (!col) ey = 0;
+  }
+  const bool in2 = col && ex >= 1 && ex < EX - 1 && ey >= 1 && ey < EY - 1;
+  const bool in3 = col && ex >= H && ex < H + TX && ey >= H && ey < H + TY;
+  const int e1 = ey * EX + ex;
+  const int e2 = in2 ? (ey - 1) * RX2 + (ex - 1) : 0;
+  const int tx_n = (nx + TX - 1) / TX, ty_n = (ny + TY - 1) / TY;
+  const int nt = tx_n * ty_n * ((nz + ZS - 1) / ZS);
+  const int b = blockIdx.x;
+  const int tt = (nt % 8 == 0) ? (b % 8) * (nt / 8) + b / 8 : b;
+  const int x0 = (tt % tx_n) * TX, y0 = ((tt / tx_n) % ty_n) * TY, z0 = (tt / (tx_n * ty_n)) * ZS;
+  int x = x0 - H + ex, y = y0 - H + ey;
+  x = wrap_coord(x, nx);  // the border may wrap (several times on tiny grids)
+  y = wrap_coord(y, ny);
+  const bool out = in3 && x0 + ex - H < nx && y0 + ey - H < ny;
+  const int64_t plane = static_cast<int64_t>(nx) * ny;
+  const int64_t cxy = static_cast<int64_t>(y) * nx + x;
+  const int zend = min(z0 + ZS, nz);
+  // stage histories: rest and +z of the previous plane, +z of the one before
+  float r1p[4], z1p[4], z1pp[4], r2p[4], z2p[4], z2pp[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) r1p[i] = z1p[i] = z1pp[i] = r2p[i] = z2p[i] = z2pp[i] = 0.0f;
+  for (int p = z0 - 2; p <= zend + 1; ++p) {
+    const int sl = p & 1;
+    // stage 1, plane p, from HBM
+    float r1[4], zp1[4], zm1[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r1[i] = zp1[i] = zm1[i] = 0.0f;
+    if (col) {
+      const int pz = wrap_coord(p, nz);
+      const int64_t c = static_cast<int64_t>(pz) * plane + cxy;
+      float g[4][7];
+      gather_cell<3, TR, TM>(sr, sm, x, y, pz, nx, ny, nz, stride, c, g);
+      collide<3>(g, k);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        TR a;
+        TM bp, bm;
+        store_f32(&a, g[i][0]);
+        store_f32(&bp, g[i][5]);
+        store_f32(&bm, g[i][6]);
+        r1[i] = load_f32(&a);
+        zp1[i] = load_f32(&bp);
+        zm1[i] = load_f32(&bm);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) store_f32(&s1[sl][i * 4 + m][e1], g[i][1 + m]);
+      }
+    }
+    // stage 2, plane p - 1, from the stage-1 results
+    float zm2[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) zm2[i] = 0.0f;
+    if (p >= z0 && in2) {
+      float g[4][7];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        g[i][0] = r1p[i];
+        g[i][1] = load_f32(&s1[sl ^ 1][i * 4 + 0][e1 - 1]);   // +x from x-1
+        g[i][2] = load_f32(&s1[sl ^ 1][i * 4 + 1][e1 + 1]);   // -x from x+1
+        g[i][3] = load_f32(&s1[sl ^ 1][i * 4 + 2][e1 - EX]);  // +y from y-1
+        g[i][4] = load_f32(&s1[sl ^ 1][i * 4 + 3][e1 + EX]);  // -y from y+1
+        g[i][5] = z1pp[i];                                    // +z from z-1
+        g[i][6] = zm1[i];                                     // -z from z+1
+      }
+      collide<3>(g, k);
+      float r2[4], zp2[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        TR a;
+        TM bp, bm;
+        store_f32(&a, g[i][0]);
+        store_f32(&bp, g[i][5]);
+        store_f32(&bm, g[i][6]);
+        r2[i] = load_f32(&a);
+        zp2[i] = load_f32(&bp);
+        zm2[i] = load_f32(&bm);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) store_f32(&s2[sl ^ 1][i * 4 + m][e2], g[i][1 + m]);
+      }
+      // stage 3, plane p - 2, from the stage-2 results, to HBM
+      if (p >= z0 + 2 && out) {
+        float h[4][7];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          h[i][0] = r2p[i];
+          h[i][1] = load_f32(&s2[sl][i * 4 + 0][e2 - 1]);
+          h[i][2] = load_f32(&s2[sl][i * 4 + 1][e2 + 1]);
+          h[i][3] = load_f32(&s2[sl][i * 4 + 2][e2 - RX2]);
+          h[i][4] = load_f32(&s2[sl][i * 4 + 3][e2 + RX2]);
+          h[i][5] = z2pp[i];
+          h[i][6] = zm2[i];
+        }
+        collide<3>(h, k);
+        const int64_t c = static_cast<int64_t>(p - 2) * plane + static_cast<int64_t>(y0 + ey - H) * nx +
+                          (x0 + ex - H);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          store_stream(dr + i * stride + c, h[i][0]);
+#pragma unroll
+          for (int m = 0; m < 6; ++m) store_stream(dm + (i * 6 + m) * stride + c, h[i][1 + m]);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        z2pp[i] = z2p[i];
+        z2p[i] = zp2[i];
+        r2p[i] = r2[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      z1pp[i] = z1p[i];
+      z1p[i] = zp1[i];
+      r1p[i] = r1[i];
+    }
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------------------------
+// one step of the 3D moment-only storage, marching along z.  A block owns a
+// TX x TY column tile and a z segment; each thread keeps its column's W at
+// planes z - 1, z and z + 1 in registers (the +-z neighbours of the stencil),
+// and plane z of the tile plus a one-cell x/y halo goes to LDS for the
+// in-plane neighbours (double-buffered: one barrier per plane).  Each plane
+// of W is read once by the tile (plus the halo, mostly from L2) instead of
+// by seven stencil points, and the stencil evaluates step_moments exactly as
+// the cell-parallel kernel does, so the result is the same bit for bit.  The
+// loads of plane z + 2 are issued before plane z is evaluated.
+// ----------------------------------------------------------------------------
+template <int TX, int TY, int ZS>
+__global__ __launch_bounds__(TX * TY) void k_step_mom_3d(const float* __restrict__ sr, float* __restrict__ dr, int nx,
+                                                         int ny, int nz, int64_t stride, Coef k) {
+  constexpr int NT = TX * TY, EX = TX + 2, EY = TY + 2, EN = EX * EY;
+  constexpr int NH = 2 * EX + 2 * TY;  // halo cells of a plane: two rows of EX, two columns of TY
+  static_assert(NH <= NT, "one halo cell per thread at most");
+  __shared__ float s_w[2][4][EN];
+  const int t = static_cast<int>(threadIdx.x);
+  // tile order: XCD-major over (x, y, z-segment) in raster order
+  const int tx_n = (nx + TX - 1) / TX, ty_n = (ny + TY - 1) / TY;
+  const int nt = tx_n * ty_n * ((nz + ZS - 1) / ZS);
+  const int b = blockIdx.x;
+  const int tt = (nt % 8 == 0) ? (b % 8) * (nt / 8) + b / 8 : b;
+  const int x0 = (tt % tx_n) * TX, y0 = ((tt / tx_n) % ty_n) * TY, z0 = (tt / (tx_n * ty_n)) * ZS;
+  const int zend = min(z0 + ZS, nz);
+  const int ox = t % TX, oy = t / TX;
+  const int x = x0 + ox, y = y0 + oy;
+  const bool own = x < nx && y < ny;
+  const int e_own = (oy + 1) * EX + (ox + 1);
+  // the thread's own column (wrapped, so that ragged tiles load valid cells)
+  const int64_t plane = static_cast<int64_t>(nx) * ny;
+  const int64_t c_own = static_cast<int64_t>(wrap_coord(y, ny)) * nx + wrap_coord(x, nx);
+  // the thread's halo cell: rows y0 - 1 and y0 + TY (EX cells each, corners
+  // included), then columns x0 - 1 and x0 + TX of the TY inner rows
+  int e_h = -1;
+  int64_t c_h = 0;
+  if (t < NH) {
+    int hx, hy;
+    if (t < 2 * EX) {
+      hx = t % EX;
+      hy = (t < EX) ? 0 : EY - 1;
+    } else {
+      const int u = t - 2 * EX;
+      hx = (u % 2) ? EX - 1 : 0;
+      hy = 1 + u / 2;
+    }
+    e_h = hy * EX + hx;
+    c_h = static_cast<int64_t>(wrap_coord(y0 - 1 + hy, ny)) * nx + wrap_coord(x0 - 1 + hx, nx);
+  }
+  auto zoff = [&](int z) { return static_cast<int64_t>(wrap_coord(z, nz)) * plane; };
+  float wm[4], w0[4], wp[4], wn[4], h0[4], hn[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    wm[i] = sr[i * stride + zoff(z0 - 1) + c_own];
+    w0[i] = sr[i * stride + zoff(z0) + c_own];
+    wp[i] = sr[i * stride + zoff(z0 + 1) + c_own];
+    h0[i] = (e_h >= 0) ? sr[i * stride + zoff(z0) + c_h] : 0.0f;
+  }
+  int buf = 0;
+  for (int z = z0; z < zend; ++z) {
+    // issue the loads of the next plane's values before this plane's stencil
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      wn[i] = sr[i * stride + zoff(z + 2) + c_own];
+      hn[i] = (e_h >= 0) ? sr[i * stride + zoff(z + 1) + c_h] : 0.0f;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      s_w[buf][i][e_own] = w0[i];
+      if (e_h >= 0) s_w[buf][i][e_h] = h0[i];
+    }
+    __syncthreads();
+    if (own) {
+      const int off[4] = {-1, 1, -EX, EX};  // upwind neighbour of velocity +x, -x, +y, -y
+      float out[4];
+      step_moments<3>(
+          [&](int i, int nb) {
+            return nb < 0 ? w0[i] : nb == 4 ? wm[i] : nb == 5 ? wp[i] : s_w[buf][i][e_own + off[nb]];
+          },
+          k, out);
+      const int64_t c = static_cast<int64_t>(z) * plane + static_cast<int64_t>(y) * nx + x;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) store_stream(dr + i * stride + c, out[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      wm[i] = w0[i];
+      w0[i] = wp[i];
+      wp[i] = wn[i];
+      h0[i] = hn[i];
+    }
+    buf ^= 1;
+  }
+}
+
 // K >= 3 steps per launch: the tiles of lbm_fused.hpp
 template <typename TR, typename TM, int TX, int TY, int NT, int K, bool XCD = false>
 __global__ __launch_bounds__(NT) void k_stepK_2d(const TR* __restrict__ sr, const TM* __restrict__ sm,
@@ -690,11 +945,22 @@ struct Impl {
     return hipGetLastError();
   }
 
+  // 3D moment-only storage: the z-marching kernel, 64 x 16 column tiles on
+  // 1024 threads, 32-plane segments
+  static constexpr int kM3X = 64, kM3Y = 16, kM3Z = 32;
+
   static hipError_t step(const Geometry& g, const RunCoef& r, const void* src, void* dst, int bx,
                          int by, hipStream_t s) {
     auto a = planes_of<TR, TM>(const_cast<void*>(src), g.rest_bytes);
     auto b = planes_of<TR, TM>(dst, g.rest_bytes);
     const auto k = make_coef<typename ComputeOf<TM>::type>(r, D, DEV);
+    if constexpr (D == 3 && IsMom<TM>::value) {
+      const int64_t tiles = static_cast<int64_t>((g.nx + kM3X - 1) / kM3X) * ((g.ny + kM3Y - 1) / kM3Y) *
+                            ((g.nz + kM3Z - 1) / kM3Z);
+      hipLaunchKernelGGL((k_step_mom_3d<kM3X, kM3Y, kM3Z>), dim3(static_cast<uint32_t>(tiles)), dim3(kM3X * kM3Y), 0,
+                         s, a.rest, reinterpret_cast<float*>(b.rest), g.nx, g.ny, g.nz, g.stride, k);
+      return hipGetLastError();
+    }
     dim3 block(bx, by, 1);
     dim3 grid((g.nx + bx - 1) / bx, (g.ny + by - 1) / by, g.nz);
     hipLaunchKernelGGL((k_step<D, TR, TM>), grid, block, 0, s, a.rest, a.move, b.rest, b.move, g.nx,
@@ -772,7 +1038,13 @@ struct Impl {
   // (TX+2K)(TY+2K)/(TX TY) times and written once per K steps) at the price of
   // recomputing the shrinking borders; K = 6..8 and 32x16, 32x32 or 64x32
   // tiles were within a few percent or slower.
-  static constexpr bool kHasStepK = kHasStep2 && D == 2;
+  static constexpr bool kHasStepK =
+      (kHasStep2 && D == 2) || (D == 3 && std::is_same<TR, float>::value && std::is_same<TM, float>::value);
+  // most steps per launch: 6 in 2D, 3 for the 3D FP32 storages, else the
+  // two-step kernel's 2 or one
+  static constexpr int kMaxFuse = kHasStepK ? (D == 2 ? kMaxFusion : 3) : kHasStep2 ? 2 : 1;
+  // 3D, three steps: 64 x 6 columns on 704 threads, 32-plane segments
+  static constexpr int kT3KY = 6, kT3KZ = 32;
   static constexpr int kStepKThreads = 512;
 
   static constexpr bool kRestInRegisters = sizeof(TR) == 4 && sizeof(TM) == 4;
@@ -831,6 +1103,17 @@ struct Impl {
                           hipStream_t s) {
     if constexpr (!kHasStepK) {
       return hipErrorInvalidValue;
+    } else if constexpr (D == 3) {
+      if (K != 3) return hipErrorInvalidValue;
+      auto a = planes_of<TR, TM>(const_cast<void*>(src), g.rest_bytes);
+      auto b = planes_of<TR, TM>(dst, g.rest_bytes);
+      const Coef k = make_coef<float>(r, D, DEV);
+      const int64_t tiles = static_cast<int64_t>((g.nx + 63) / 64) * ((g.ny + kT3KY - 1) / kT3KY) *
+                            ((g.nz + kT3KZ - 1) / kT3KZ);
+      hipLaunchKernelGGL((k_step3_3d<TR, TM, kT3KY, kT3KZ>), dim3(static_cast<uint32_t>(tiles)),
+                         dim3(64 * (kT3KY + 5)), 0, s, a.rest, a.move, b.rest, b.move, g.nx, g.ny, g.nz, g.stride,
+                         k);
+      return hipGetLastError();
     } else {
       switch (K) {
         case 3: return launchK<3>(g, r, src, dst, s);
@@ -888,7 +1171,7 @@ struct Impl {
 
   static const Ops* ops() {
     static const Ops o = {&init, &step, kHasStep2 ? &step2 : nullptr, &moments, &diag, &diag_blocks,
-                          kHasWalls ? &step_walls : nullptr, kHasStepK ? &stepK : nullptr};
+                          kHasWalls ? &step_walls : nullptr, kHasStepK ? &stepK : nullptr, kMaxFuse};
     return &o;
   }
 };

@@ -415,30 +415,34 @@ def test_fusion_settings_and_defaults():
     p3 = scheme.params_for_grid(3, 8, 0.01)
     e3 = _engine(p3, inputs.abc_flow(8, 0.1, 0.1, 0.1))
     assert e3.fusion() == 2
+    e3.set_fusion(3)
     with pytest.raises(lbm.LbmError):
-        e3.set_fusion(3)
+        e3.set_fusion(4)
     e3.close()
 
 
 @pytest.mark.parametrize("storage", ["f32", "f32_raw"])
 @pytest.mark.parametrize("shape,steps", [((8, 8, 8), 6), ((17, 13, 9), 7), ((40, 20, 33), 5), ((1, 1, 1), 4),
-                                         ((3, 70, 5), 9), ((64, 64, 64), 3), ((70, 9, 66), 4)])
-def test_two_step_fusion_3d_is_bitwise(storage, shape, steps):
+                                         ((3, 70, 5), 9), ((64, 64, 64), 3), ((70, 9, 66), 4), ((33, 7, 130), 8)])
+def test_multi_step_fusion_3d_is_bitwise(storage, shape, steps):
     """3D, 4-byte planes: the z-marching two-step kernel (64 x 8 columns,
-    32-plane segments) gives the single-step state bit for bit, ragged in
-    every direction and over several segments along z."""
+    32-plane segments) and three-step kernel (64 x 6 columns, 32-plane
+    segments) give the single-step state bit for bit, ragged in every
+    direction, over several segments along z, and with remainders that run
+    as shorter launches."""
     nz, ny, nx = shape
     dx = 2 * math.pi / max(shape)
     p = scheme.Params(dim=3, dx=dx, dt=dx * dx / 8, nu=0.02)
     u = inputs.random_field_box(shape, dx, seed=5, umax=0.05 / dx)
     blobs = []
-    for fuse in (1, 2):
+    for fuse in (1, 2, 3):
         eng = _engine(p, u, storage=storage)
         eng.set_fusion(fuse)
         eng.step(steps)
         blobs.append(eng.save_state())
         eng.close()
     assert np.array_equal(blobs[0], blobs[1])
+    assert np.array_equal(blobs[0], blobs[2])
 
 
 def test_two_step_fusion_3d_defaults_and_limits():
@@ -446,7 +450,7 @@ def test_two_step_fusion_3d_defaults_and_limits():
     u = inputs.abc_flow(8, 0.1, 0.1, 0.1)
     eng = _engine(p, u)
     assert eng.fusion() == 2
-    for bad in (3, 5):
+    for bad in (4, 5, 7):
         with pytest.raises(lbm.LbmError):
             eng.set_fusion(bad)
     eng.close()
