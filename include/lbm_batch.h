@@ -59,8 +59,11 @@ lbm_status lbm_batch_init(lbm_batch** out, int32_t dim, int32_t storage, int32_t
 /* Choose the tile shape of every size class (runs grouped by nx rounded up to
  * a power of two), then the number of blocks of the persistent launch (4, 8,
  * 16 or 32 per compute unit, or one per tile), and in 2D the number of blocks
- * of the two-step launch (1, 2, 4 or 8 per compute unit, or one per tile), by
- * timing each candidate on the batch's own buffers; the state is not changed.  If cache_path is non-NULL (else the environment
+ * of the two-step launch (1, 2, 4 or 8 per compute unit, or one per tile), the
+ * five-step tile shape of every size class (each shape timed on the class's
+ * runs alone) and the blocks per compute unit of the five-step launches, by
+ * timing each candidate on the batch's own buffers; the state is not changed.
+ * If cache_path is non-NULL (else the environment
  * variable LBM_AUTOTUNE_CACHE, if set) previously tuned shapes for this
  * device, dimension and storage are read from that text file and new ones are
  * appended.  Rebuilds the step graph.  Synchronises. */
@@ -87,6 +90,16 @@ int32_t lbm_batch_grid(const lbm_batch* b);
  * fusion is 5, else the two-step kernel's (0 if the batch has none, i.e. in
  * 3D).  Chosen by lbm_batch_autotune. */
 int32_t lbm_batch_fused_grid(const lbm_batch* b);
+
+/* Cell tile (tx x ty) of run r in the five-step launches (2D population
+ * storages; LBM_EINVAL otherwise).  Three shapes exist per storage (4-byte
+ * planes: 32x32, 32x16, 16x16; 16-bit planes: 64x16, 32x32, 32x16);
+ * lbm_batch_autotune picks one per size class, the first one otherwise. */
+lbm_status lbm_batch_fused_tile(const lbm_batch* b, int32_t run, int32_t* tx, int32_t* ty);
+
+/* Use fused tile shape `shape` (0, 1 or 2, in the order above) for every run
+ * (results do not depend on it).  Rebuilds the step graphs.  Synchronises. */
+lbm_status lbm_batch_set_fused_shape(lbm_batch* b, int32_t shape);
 
 /* Steps per launch: 1 (one-step kernel), 2 (two-step kernel) or 5 (five-step
  * kernel, the default); 2 and 5 in 2D only; LBM_EINVAL otherwise.  Every

@@ -41,6 +41,8 @@ SIGNATURES = {
     "lbm_batch_tile_width": (C.c_int32, [C.c_void_p, C.c_int32]),
     "lbm_batch_grid": (C.c_int32, [C.c_void_p]),
     "lbm_batch_fused_grid": (C.c_int32, [C.c_void_p]),
+    "lbm_batch_fused_tile": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "lbm_batch_set_fused_shape": (C.c_int, [C.c_void_p, C.c_int32]),
     "lbm_batch_set_fusion": (C.c_int, [C.c_void_p, C.c_int32]),
     "lbm_batch_fusion": (C.c_int32, [C.c_void_p]),
     "lbm_batch_destroy": (None, [C.c_void_p]),
@@ -131,6 +133,16 @@ def lbm_batch_fused_grid(h: int) -> int:
     return int(blib().lbm_batch_fused_grid(C.c_void_p(h)))
 
 
+def lbm_batch_fused_tile(h: int, run: int) -> tuple[int, int]:
+    tx, ty = C.c_int32(), C.c_int32()
+    _ok(blib().lbm_batch_fused_tile(C.c_void_p(h), run, C.byref(tx), C.byref(ty)), "lbm_batch_fused_tile")
+    return tx.value, ty.value
+
+
+def lbm_batch_set_fused_shape(h: int, shape: int) -> None:
+    _ok(blib().lbm_batch_set_fused_shape(C.c_void_p(h), int(shape)), "lbm_batch_set_fused_shape")
+
+
 def lbm_batch_set_fusion(h: int, steps_per_launch: int) -> None:
     _ok(blib().lbm_batch_set_fusion(C.c_void_p(h), steps_per_launch), "lbm_batch_set_fusion")
 
@@ -204,6 +216,12 @@ class Batch:
 
     def tile_width(self, r: int) -> int:
         return lbm_batch_tile_width(self.handle, r)
+
+    def fused_tile(self, r: int) -> tuple[int, int]:
+        return lbm_batch_fused_tile(self.handle, r)
+
+    def set_fused_shape(self, shape: int) -> None:
+        lbm_batch_set_fused_shape(self.handle, shape)
 
     def close(self) -> None:
         if self.handle:

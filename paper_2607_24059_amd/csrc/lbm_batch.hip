@@ -141,39 +141,43 @@ __global__ __launch_bounds__(kT2N) void k_batch_step2(const BatchRun* __restrict
 
 // kBatchK steps per launch (2D): the single-run engine's multi-step tiles
 // (lbm_fused.hpp) walked by a persistent grid, each tile wrapping periodically
-// in its own run; the single-run engine's tile code (32x32 cells on 512
-// threads with the rest populations in registers for 4-byte planes, 64x16
-// otherwise), so again bit-identical to single steps.
+// in its own run, so again bit-identical to single steps.  Three tile shapes
+// per storage; lbm_batch_autotune picks one per size class (the tiles of each
+// shape are one launch of that shape's kernel, and the launches of one fused
+// step are independent graph nodes).
 constexpr int kBatchK = 5;
+constexpr int kShapes = 3;
 
-template <typename TR, typename TM>
+template <typename TR, typename TM, int S>
 struct BatchKShape {
   static constexpr bool kRegs = sizeof(TR) == 4 && sizeof(TM) == 4;
-  // 4-byte planes: 32x32 tiles on 512 threads (two blocks per compute unit),
-  // as in the single-run engine at five steps
-  static constexpr int TX = kRegs ? 32 : 64, TY = kRegs ? 32 : 16;
-  // (FP16 + FP32 rest ran 113.5 GLUPS on 1024 threads, 102.2 on 512)
-  static constexpr int NT = kRegs ? 512 : (sizeof(TR) == 2 ? 512 : 1024);
+  // 4-byte planes, rest populations in registers: 32x32 on 512 threads (the
+  // single-run engine's tile, two blocks per compute unit), 32x16 on 256
+  // (three blocks per compute unit), 16x16 on 256 (small runs: more tiles);
+  // 16-bit planes: 64x16 on 512, 32x32 on 512, 32x16 on 256.
+  static constexpr int TX = kRegs ? (S == 2 ? 16 : 32) : (S == 0 ? 64 : 32);
+  static constexpr int TY = kRegs ? (S == 0 ? 32 : 16) : (S == 1 ? 32 : 16);
+  static constexpr int NT = kRegs ? (S == 0 ? 512 : 256) : (S == 2 ? 256 : 512);
 };
-constexpr int kTKXmin = 32, kTKY = 16;  // smallest tile width and height (size the tile list)
+constexpr int kTKXmin = 16, kTKYmin = 16;  // smallest tile width and height (size the tile list)
 
-template <typename TR, typename TM>
-__global__ __launch_bounds__((BatchKShape<TR, TM>::NT)) void k_batch_stepK(const BatchRun* __restrict__ runs,
-                                                                         const BatchTile* __restrict__ tiles,
-                                                                         int64_t ntiles, char* __restrict__ base,
-                                                                         int parity) {
-  using S = BatchKShape<TR, TM>;
+template <typename TR, typename TM, int S>
+__global__ __launch_bounds__((BatchKShape<TR, TM, S>::NT)) void k_batch_stepK(const BatchRun* __restrict__ runs,
+                                                                            const BatchTile* __restrict__ tiles,
+                                                                            int64_t ntiles, char* __restrict__ base,
+                                                                            int parity) {
+  using SH = BatchKShape<TR, TM, S>;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const BatchTile tl = tiles[t];
     const BatchRun& r = runs[tl.run];
     const auto a = planes_of<TR, TM>(base + r.off[parity], static_cast<size_t>(r.rest_bytes));
     const auto b = planes_of<TR, TM>(base + r.off[parity ^ 1], static_cast<size_t>(r.rest_bytes));
-    if constexpr (S::kRegs) {
-      using T = TileKr<TR, TM, S::TX, S::TY, S::NT, kBatchK>;
+    if constexpr (SH::kRegs) {
+      using T = TileKr<TR, TM, SH::TX, SH::TY, SH::NT, kBatchK>;
       __shared__ TM s_move[12][T::EN];
       T::run(a.rest, a.move, b.rest, b.move, tl.x0, tl.y0, r.nx, r.ny, r.stride, r.k, s_move);
     } else {
-      using T = TileK<TR, TM, S::TX, S::TY, S::NT, kBatchK>;
+      using T = TileK<TR, TM, SH::TX, SH::TY, SH::NT, kBatchK>;
       __shared__ TR s_rest[3][T::EN];
       __shared__ TM s_move[12][T::EN];
       T::run(a.rest, a.move, b.rest, b.move, tl.x0, tl.y0, r.nx, r.ny, r.stride, r.k, s_rest, s_move);
@@ -189,28 +193,36 @@ struct BatchKKernel {
   int tx = 0, ty = 0, threads = 0;
 };
 
+template <typename TR, typename TM, int S>
+BatchKKernel batch_k_shape() {
+  using SH = BatchKShape<TR, TM, S>;
+  return BatchKKernel{&k_batch_stepK<TR, TM, S>, SH::TX, SH::TY, SH::NT};
+}
+
 template <typename TR, typename TM>
-BatchKKernel batch_k_of() {
-  using S = BatchKShape<TR, TM>;
-  return BatchKKernel{&k_batch_stepK<TR, TM>, S::TX, S::TY, S::NT};
+void batch_k_of(BatchKKernel (&out)[kShapes]) {
+  out[0] = batch_k_shape<TR, TM, 0>();
+  out[1] = batch_k_shape<TR, TM, 1>();
+  out[2] = batch_k_shape<TR, TM, 2>();
 }
 
-BatchKKernel batch_kernelK(int dim, int storage) {
-  if (dim != 2) return {};
+// the multi-step kernels of a storage (all null where there are none)
+void batch_kernelK(int dim, int storage, BatchKKernel (&out)[kShapes]) {
+  for (auto& k : out) k = BatchKKernel{};
+  if (dim != 2) return;
   switch (storage) {
-    case LBM_F32: case LBM_F32_RAW: return batch_k_of<float, float>();
-    case LBM_F16_DEV: return batch_k_of<_Float16, _Float16>();
-    case LBM_BF16_DEV: return batch_k_of<bf16, bf16>();
-    case LBM_F16_DEV_R32: return batch_k_of<float, _Float16>();
-    case LBM_BF16_DEV_R32: return batch_k_of<float, bf16>();
+    case LBM_F32: case LBM_F32_RAW: batch_k_of<float, float>(out); return;
+    case LBM_F16_DEV: batch_k_of<_Float16, _Float16>(out); return;
+    case LBM_BF16_DEV: batch_k_of<bf16, bf16>(out); return;
+    case LBM_F16_DEV_R32: batch_k_of<float, _Float16>(out); return;
+    case LBM_BF16_DEV_R32: batch_k_of<float, bf16>(out); return;
   }
-  return {};
 }
 
-// multi-step tiles of one 2D run for tile width tx (at most this many for any
-// width >= kTKXmin and height >= kTKY)
-int64_t tilesK_of(const Geometry& g, int tx) {
-  return static_cast<int64_t>((g.nx + tx - 1) / tx) * ((g.ny + kTKY - 1) / kTKY);
+// multi-step tiles of one 2D run for a tx x ty tile (at most this many for any
+// tile of at least kTKXmin x kTKYmin cells)
+int64_t tilesK_of(const Geometry& g, int tx, int ty) {
+  return static_cast<int64_t>((g.nx + tx - 1) / tx) * ((g.ny + ty - 1) / ty);
 }
 
 BatchKernel batch_kernel2(int dim, int storage) {
@@ -295,10 +307,12 @@ struct lbm_batch {
   int grid2 = 0;                  // persistent grid of the fused kernel
   int fuse = 1;                   // steps per launch: 1, 2 (two-step kernel) or kBatchK
   BatchKernel kernel2 = nullptr;
-  BatchKKernel kernelK;           // kBatchK steps per launch (2D population storages)
+  BatchKKernel kernelK[kShapes];  // kBatchK steps per launch (2D population storages), per tile shape
+  std::map<int, int> shape_of_class;  // fused tile shape per size class
   BatchTile* d_tilesK = nullptr;
   int64_t ntilesK = 0;
-  int gridK = 0;
+  int64_t startK[kShapes] = {0, 0, 0}, countK[kShapes] = {0, 0, 0};  // tile ranges of the shapes
+  int gridK = 0;                  // blocks per CU of each multi-step launch (0: one per tile)
   hipGraphExec_t exec_mainK[2] = {nullptr, nullptr};  // kFusedGraphLaunches K-step launches from parity p
   hipGraphExec_t exec_oneK[2] = {nullptr, nullptr};   // one K-step launch from parity p
   hipGraphExec_t exec_main2[2] = {nullptr, nullptr};  // kFusedGraphLaunches fused launches from parity p
@@ -357,7 +371,7 @@ Layout layout(int dim, int storage, int nruns, const lbm_run_spec* runs) {
     L.max_tiles += mt;
     if (dim == 2) {
       L.tiles2 += tiles2_of(g);
-      L.tilesK += tilesK_of(g, kTKXmin);
+      L.tilesK += tilesK_of(g, kTKXmin, kTKYmin);
     }
     geo.push_back(g);
   }
@@ -420,12 +434,22 @@ hipError_t launch_step2(lbm_batch* b, int parity, hipStream_t s) {
   return hipGetLastError();
 }
 
+// blocks of a multi-step launch over n tiles
+unsigned gridK_for(const lbm_batch* b, int64_t n) {
+  const int64_t cap = b->gridK > 0 ? static_cast<int64_t>(b->gridK) * b->cus : n;
+  return static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(n, std::min<int64_t>(cap, 0x7fffffff))));
+}
+
 hipError_t launch_stepK(lbm_batch* b, int parity, hipStream_t s) {
-  if (b->ntilesK == 0) return hipSuccess;
-  const unsigned grid = static_cast<unsigned>(std::min<int64_t>(b->ntilesK, b->gridK));
-  hipLaunchKernelGGL(b->kernelK.fn, dim3(grid), dim3(b->kernelK.threads), 0, s, b->d_runs, b->d_tilesK, b->ntilesK,
-                     b->ws, parity);
-  return hipGetLastError();
+  for (int sh = 0; sh < kShapes; ++sh) {
+    if (b->countK[sh] == 0) continue;
+    const BatchTile* t = b->d_tilesK + b->startK[sh];
+    hipLaunchKernelGGL(b->kernelK[sh].fn, dim3(gridK_for(b, b->countK[sh])), dim3(b->kernelK[sh].threads), 0, s,
+                       b->d_runs, t, b->countK[sh], b->ws, parity);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 void destroy_graphs(lbm_batch* b) {
@@ -476,6 +500,43 @@ hipError_t make_graph(lbm_batch* b, BatchKernel kernel, const BatchTile* tiles, 
   return e;
 }
 
+// A graph of `count` consecutive multi-step launches starting at `parity`:
+// each launch is one kernel node per tile shape in use (independent of each
+// other), each depending on every node of the previous launch.
+hipError_t make_graphK(lbm_batch* b, int parity, int count, hipGraphExec_t* out) {
+  hipGraph_t g = nullptr;
+  hipError_t e = hipGraphCreate(&g, 0);
+  if (e != hipSuccess) return e;
+  std::vector<hipGraphNode_t> prev, cur;
+  for (int l = 0; l < count && e == hipSuccess; ++l) {
+    cur.clear();
+    for (int sh = 0; sh < kShapes && e == hipSuccess; ++sh) {
+      if (b->countK[sh] == 0) continue;
+      int par = (parity + l) & 1;
+      const BatchRun* runs = b->d_runs;
+      const BatchTile* tiles = b->d_tilesK + b->startK[sh];
+      int64_t nt = b->countK[sh];
+      char* base = b->ws;
+      void* args[] = {&runs, &tiles, &nt, &base, &par};
+      hipKernelNodeParams kp;
+      memset(&kp, 0, sizeof(kp));
+      kp.func = reinterpret_cast<void*>(b->kernelK[sh].fn);
+      kp.gridDim = dim3(gridK_for(b, nt));
+      kp.blockDim = dim3(b->kernelK[sh].threads);
+      kp.sharedMemBytes = 0;
+      kp.kernelParams = args;
+      kp.extra = nullptr;
+      hipGraphNode_t node;
+      e = hipGraphAddKernelNode(&node, g, prev.empty() ? nullptr : prev.data(), prev.size(), &kp);
+      cur.push_back(node);
+    }
+    prev.swap(cur);
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  return e;
+}
+
 hipError_t rebuild(lbm_batch* b) {
   destroy_graphs(b);
   hipError_t e = upload_tiles(b, build_tiles(b, {}));
@@ -490,41 +551,44 @@ hipError_t rebuild(lbm_batch* b) {
       if (e == hipSuccess) e = make_graph(b, b->kernel2, b->d_tiles2, b->ntiles2, b->grid2, kT2N, p, 1, &b->exec_two[p]);
     }
   }
-  if (b->kernelK.fn) {
+  if (b->kernelK[0].fn && b->ntilesK > 0) {
     for (int p = 0; p < 2 && e == hipSuccess; ++p) {
-      e = make_graph(b, b->kernelK.fn, b->d_tilesK, b->ntilesK, b->gridK, b->kernelK.threads, p,
-                     kFusedGraphLaunches, &b->exec_mainK[p]);
-      if (e == hipSuccess)
-        e = make_graph(b, b->kernelK.fn, b->d_tilesK, b->ntilesK, b->gridK, b->kernelK.threads, p, 1,
-                       &b->exec_oneK[p]);
+      e = make_graphK(b, p, kFusedGraphLaunches, &b->exec_mainK[p]);
+      if (e == hipSuccess) e = make_graphK(b, p, 1, &b->exec_oneK[p]);
     }
   }
   return e;
 }
 
-// The multi-step tile list (fixed, like the two-step one).
-hipError_t upload_tilesK(lbm_batch* b) {
-  std::vector<BatchTile> t;
-  const int tx = b->kernelK.tx, ty = b->kernelK.ty;
-  for (int r = 0; r < b->nruns; ++r) {
-    const Geometry& g = b->geo[r];
-    for (int y0 = 0; y0 < g.ny; y0 += ty)
-      for (int x0 = 0; x0 < g.nx; x0 += tx) t.push_back(BatchTile{r, x0, y0, 0, static_cast<int16_t>(log2i(tx))});
+// The multi-step tile list of the runs selected by `use` (all if empty): the
+// tiles of each shape in one contiguous range, each range in XCD-major order
+// (list slot s is taken by a block on XCD s % 8, with one block per tile or a
+// persistent grid that is a multiple of 8, so the slots of XCD j get the j-th
+// eighth of the range in raster order and neighbouring tiles share their
+// border reads through one L2).
+hipError_t upload_tilesK(lbm_batch* b, const std::vector<char>& use = {}) {
+  std::vector<BatchTile> all;
+  for (int sh = 0; sh < kShapes; ++sh) {
+    std::vector<BatchTile> t;
+    const int tx = b->kernelK[sh].tx, ty = b->kernelK[sh].ty;
+    for (int r = 0; r < b->nruns; ++r) {
+      if ((!use.empty() && !use[r]) || b->shape_of_class.at(b->cls[r]) != sh) continue;
+      const Geometry& g = b->geo[r];
+      for (int y0 = 0; y0 < g.ny; y0 += ty)
+        for (int x0 = 0; x0 < g.nx; x0 += tx) t.push_back(BatchTile{r, x0, y0, 0, static_cast<int16_t>(log2i(tx))});
+    }
+    const size_t n = t.size();
+    b->startK[sh] = static_cast<int64_t>(all.size());
+    b->countK[sh] = static_cast<int64_t>(n);
+    if (n % 8 == 0) {
+      for (size_t q = 0; q < n; ++q) all.push_back(t[(q % 8) * (n / 8) + q / 8]);
+    } else {
+      all.insert(all.end(), t.begin(), t.end());
+    }
   }
-  b->ntilesK = static_cast<int64_t>(t.size());
-  if (t.empty()) return hipSuccess;
-  // XCD-major order: list slot s is taken by a block on XCD s % 8 (one block
-  // per tile, or a persistent grid that is a multiple of 8), so the slots of
-  // XCD j get the j-th eighth of the tiles in raster order and neighbouring
-  // tiles share their border reads through one L2
-  const size_t n = t.size();
-  std::vector<BatchTile> perm(n);
-  if (n % 8 == 0) {
-    for (size_t s = 0; s < n; ++s) perm[s] = t[(s % 8) * (n / 8) + s / 8];
-  } else {
-    perm = t;
-  }
-  hipError_t e = hipMemcpyAsync(b->d_tilesK, perm.data(), n * sizeof(BatchTile), hipMemcpyHostToDevice,
+  b->ntilesK = static_cast<int64_t>(all.size());
+  if (all.empty()) return hipSuccess;
+  hipError_t e = hipMemcpyAsync(b->d_tilesK, all.data(), all.size() * sizeof(BatchTile), hipMemcpyHostToDevice,
                                 b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   return e;
@@ -613,8 +677,8 @@ lbm_status lbm_batch_init(lbm_batch** out, int32_t dim, int32_t storage, int32_t
   b->stream = static_cast<hipStream_t>(hip_stream);
   b->kernel = batch_kernel(dim, storage);
   b->kernel2 = batch_kernel2(dim, storage);
-  b->kernelK = batch_kernelK(dim, storage);
-  b->fuse = b->kernelK.fn ? kBatchK : b->kernel2 ? 2 : 1;
+  batch_kernelK(dim, storage, b->kernelK);
+  b->fuse = b->kernelK[0].fn ? kBatchK : b->kernel2 ? 2 : 1;
   const Ops* ops = ops_for(dim, storage);
   const bool devn = storage_is_deviation(storage);
 
@@ -626,6 +690,7 @@ lbm_status lbm_batch_init(lbm_batch** out, int32_t dim, int32_t storage, int32_t
     b->total_cells += g.cells;
     b->cls.push_back(pow2_class(g.nx));
     if (!b->bx_of_class.count(b->cls.back())) b->bx_of_class[b->cls.back()] = default_bx(g);
+    b->shape_of_class[b->cls.back()] = 0;
     BatchRun& d = host_runs[r];
     d.nx = g.nx;
     d.ny = g.ny;
@@ -659,9 +724,9 @@ lbm_status lbm_batch_init(lbm_batch** out, int32_t dim, int32_t storage, int32_t
     b->cus = cus;
     b->grid = 8 * cus;  // 8 resident 256-thread blocks per CU at the kernel's register use
     b->grid2 = 2 * cus;  // two resident 512-thread fused blocks per CU (LDS tile of up to 40 KB)
-    b->gridK = 4 * cus;
+    b->gridK = 4;  // blocks per compute unit of each multi-step launch
     if (b->kernel2) e = upload_tiles2(b);
-    if (e == hipSuccess && b->kernelK.fn) e = upload_tilesK(b);
+    if (e == hipSuccess && b->kernelK[0].fn) e = upload_tilesK(b);
     if (e == hipSuccess) e = rebuild(b);
   }
   if (e != hipSuccess) {
@@ -685,7 +750,7 @@ lbm_status lbm_batch_autotune(lbm_batch* b, const char* cache_path) {
       int d, st, cl, bx;
       while (fscanf(f, "%127s %d %d %d %d", arch, &d, &st, &cl, &bx) == 5)
         if (key == arch && d == b->dim && st == b->storage && (cl < 0 || bx == 64 || bx == 128 || bx == 256))
-          cached[cl] = bx;
+          cached[cl] = bx;  // cl >= 0: one-step tile width; -1, -2, -3: grids; -(1000 + cl): fused shape
       fclose(f);
     }
   }
@@ -782,31 +847,64 @@ lbm_status lbm_batch_autotune(lbm_batch* b, const char* cache_path) {
     b->grid2 = best_pc > 0 ? best_pc * b->cus : static_cast<int>(std::min<int64_t>(b->ntiles2, 0x7fffffff));
     fresh.emplace_back(-2, best_pc);
   }
-  // persistent grid of the multi-step kernel (class -3), as for the two-step one
-  if (e == hipSuccess && b->kernelK.fn && cached.count(-3)) {
-    const int per_cu = cached[-3];
-    b->gridK = per_cu > 0 ? per_cu * b->cus : static_cast<int>(std::min<int64_t>(b->ntilesK, 0x7fffffff));
-  } else if (e == hipSuccess && b->kernelK.fn) {
+  // fused tile shape of every size class (cache key -(1000 + class)): each
+  // candidate timed on the class's runs alone, one block per tile
+  auto time_K = [&](float* ms) {
+    for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch_stepK(b, b->parity, b->stream);
+    if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+    for (int it = 0; it < 5 && e == hipSuccess; ++it) e = launch_stepK(b, b->parity, b->stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+  };
+  if (e == hipSuccess && b->kernelK[0].fn) {
+    const int grid_keep = b->gridK;
+    b->gridK = 0;
+    for (auto& kv : b->shape_of_class) {
+      const int cl = kv.first, key = -(1000 + cl);
+      if (cached.count(key) && cached[key] >= 0 && cached[key] < kShapes) {
+        kv.second = cached[key];
+        continue;
+      }
+      std::vector<char> use(b->nruns, 0);
+      for (int r = 0; r < b->nruns; ++r) use[r] = (b->cls[r] == cl);
+      float best = 1e30f;
+      int best_sh = kv.second;
+      for (int sh = 0; sh < kShapes && e == hipSuccess; ++sh) {
+        kv.second = sh;
+        e = upload_tilesK(b, use);
+        float ms = 0;
+        time_K(&ms);
+        if (e == hipSuccess && ms < best) {
+          best = ms;
+          best_sh = sh;
+        }
+      }
+      kv.second = best_sh;
+      fresh.emplace_back(key, best_sh);
+    }
+    b->gridK = grid_keep;
+    if (e == hipSuccess) e = upload_tilesK(b);
+  }
+  // blocks per compute unit of each multi-step launch (class -3; 0: one block per tile)
+  if (e == hipSuccess && b->kernelK[0].fn && cached.count(-3)) {
+    b->gridK = std::max(0, cached[-3]);
+  } else if (e == hipSuccess && b->kernelK[0].fn) {
     const int cands[] = {1, 2, 4, 8, 0};
     float best = 1e30f;
     int best_pc = 4;
     for (int pc : cands) {
       if (e != hipSuccess) break;
-      b->gridK = pc > 0 ? pc * b->cus : static_cast<int>(std::min<int64_t>(b->ntilesK, 0x7fffffff));
+      b->gridK = pc;
       // a launch reads the current buffer and writes the other: the state is kept
-      for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch_stepK(b, b->parity, b->stream);
-      if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
-      for (int it = 0; it < 5 && e == hipSuccess; ++it) e = launch_stepK(b, b->parity, b->stream);
-      if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      time_K(&ms);
       if (e == hipSuccess && ms < best) {
         best = ms;
         best_pc = pc;
       }
     }
-    b->gridK = best_pc > 0 ? best_pc * b->cus : static_cast<int>(std::min<int64_t>(b->ntilesK, 0x7fffffff));
+    b->gridK = best_pc;
     fresh.emplace_back(-3, best_pc);
   }
   hipEventDestroy(e0);
@@ -917,14 +1015,35 @@ int32_t lbm_batch_grid(const lbm_batch* b) { return b ? b->grid : -1; }
 
 int32_t lbm_batch_fused_grid(const lbm_batch* b) {
   if (!b) return -1;
-  if (b->fuse == kBatchK) return b->gridK;
+  if (b->fuse == kBatchK) {
+    int64_t blocks = 0;
+    for (int sh = 0; sh < kShapes; ++sh)
+      if (b->countK[sh]) blocks += gridK_for(b, b->countK[sh]);
+    return static_cast<int32_t>(std::min<int64_t>(blocks, 0x7fffffff));
+  }
   return b->kernel2 ? b->grid2 : 0;
+}
+
+lbm_status lbm_batch_fused_tile(const lbm_batch* b, int32_t run, int32_t* tx, int32_t* ty) {
+  if (!b || run < 0 || run >= b->nruns || !b->kernelK[0].fn) return LBM_EINVAL;
+  const BatchKKernel& k = b->kernelK[b->shape_of_class.at(b->cls[run])];
+  if (tx) *tx = k.tx;
+  if (ty) *ty = k.ty;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_set_fused_shape(lbm_batch* b, int32_t shape) {
+  if (!b || !b->kernelK[0].fn || shape < 0 || shape >= kShapes) return LBM_EINVAL;
+  for (auto& kv : b->shape_of_class) kv.second = shape;
+  hipError_t e = upload_tilesK(b);
+  if (e == hipSuccess) e = rebuild(b);
+  return dev(e);
 }
 
 lbm_status lbm_batch_set_fusion(lbm_batch* b, int32_t steps_per_launch) {
   if (!b) return LBM_EINVAL;
   if (steps_per_launch == 2 && !b->kernel2) return LBM_EINVAL;
-  if (steps_per_launch == kBatchK && !b->kernelK.fn) return LBM_EINVAL;
+  if (steps_per_launch == kBatchK && !b->kernelK[0].fn) return LBM_EINVAL;
   if (steps_per_launch != 1 && steps_per_launch != 2 && steps_per_launch != kBatchK) return LBM_EINVAL;
   b->fuse = steps_per_launch;
   return LBM_OK;

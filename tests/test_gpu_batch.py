@@ -72,6 +72,30 @@ def test_batch_bitwise_equals_single_runs_2d(storage, steps, fuse):
     b.close()
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16_dev_r32", "bf16_dev"])
+@pytest.mark.parametrize("shape", [0, 1, 2])
+def test_every_fused_tile_shape_is_bitwise(storage, shape):
+    """Each of the three five-step tile shapes the autotuner chooses from
+    gives the single-run states bit for bit (ragged, tiny and non-square runs;
+    52 = 10 x 5 + 2 steps)."""
+    runs, u0s = _mixed_runs(2)
+    b = B.Batch.create(2, storage, runs, u0s)
+    b.set_fused_shape(shape)
+    tiles = {b.fused_tile(r) for r in range(len(runs))}
+    assert len(tiles) == 1
+    expect = {"f32": [(32, 32), (32, 16), (16, 16)]}.get(storage, [(64, 16), (32, 32), (32, 16)])[shape]
+    assert tiles == {expect}
+    print(f"[batch] {storage} fused tile {expect}", flush=True)
+    b.step(52)
+    for r, (run, u0) in enumerate(zip(runs, u0s)):
+        rho, q = b.moments(r)
+        rho1, q1 = _single(2, storage, run, u0, 52)
+        assert np.array_equal(rho, rho1) and np.array_equal(q, q1), r
+    with pytest.raises(lbm.LbmError):
+        b.set_fused_shape(3)
+    b.close()
+
+
 def test_batch_bitwise_equals_single_runs_3d():
     runs, u0s = _mixed_runs(3)
     b = B.Batch.create(3, "f32", runs, u0s)
@@ -133,6 +157,7 @@ def test_autotune_keeps_state_and_caches(tmp_path):
         assert np.array_equal(rho, before[r][0]) and np.array_equal(q, before[r][1])
         w = b.tile_width(r)
         assert w in (64, 128, 256)
+        assert b.fused_tile(r) in ((32, 32), (32, 16), (16, 16))
     assert os.path.exists(cache) and open(cache).read().strip()
     lines_first = open(cache).read()
     assert b.fused_grid() > 0
