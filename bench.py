@@ -330,20 +330,23 @@ def equal_error_section(n_seeds: int) -> dict:
     reference, on the closure workload: k^-3 fields (held-out seeds 1000...),
     nu = 5e-4, coarse 256^2, reference = the plain scheme at 2048^2 in FP64
     storage restricted to 256^2, 256 coarse steps.  Plain levels 256^2, 512^2,
-    1024^2 in FP32 and in FP16 + FP32-rest storage; the corrected 256^2 run
-    uses the committed trained network.  Errors: relative L2 of the
-    divergence-free part of u.  Times: HIP events around each run's steps."""
+    1024^2, 2048^2 in FP32, FP64, split FP16 and FP16 + FP32-rest storage; the
+    corrected 256^2 run uses the committed trained network.  Errors: relative
+    L2 of u and of its divergence-free part, each with its own equal-error
+    speedups.  Times: HIP events around each run's steps."""
     from paper_2607_24059_amd import closure, cnn
     params, meta = closure.load_model(closure.WEIGHTS)
     cfg = closure.Config(**{k: v for k, v in meta["config"].items()
                             if k in ("coarse_n", "factor", "nu", "mach", "mu", "every", "guard")})
     cfg.test_seeds = list(range(1000, 1000 + n_seeds))
     net = cnn.Net(params=params)
-    ev = closure.evaluate(cfg, net, meta["scales"], log=log)
+    ev = closure.evaluate(cfg, net, meta["scales"], log=log, levels=(256, 512, 1024, 2048),
+                          plain_storages=("f32", "f64", "f16_neq", "f16_dev_r32"))
     return _finite({"workload": f"k^-3 field, nu={cfg.nu}, coarse {cfg.coarse_n}^2, reference FP64 "
                         f"{cfg.fine_n}^2 restricted, {cfg.horizon} coarse steps, "
                         f"seeds {cfg.test_seeds[0]}..{cfg.test_seeds[-1]}",
-            "error_metric": "relative L2 of the divergence-free part of u",
+            "error_metrics": {"u": "relative L2 of u on the coarse grid",
+                              "u_sol": "relative L2 of the divergence-free part of u"},
             "plain": ev["plain"], "closure": ev["closure"], "speedup": ev["speedup_equal_error"]})
 
 
@@ -460,12 +463,15 @@ def batch_variant(storage: str, steps: int, probe: float, n_runs: int = 512, fus
     ms = ev0.elapsed_time(ev1) / steps
     cells, tiles, _ = b.info()
     widths = sorted({(int(r.n[0]), b.tile_width(i)) for i, r in enumerate(runs)})
+    shapes = sorted({(int(r.n[0]), "x".join(map(str, b.fused_tile(i)))) for i, r in enumerate(runs)}) \
+        if fuse == 5 else []
     grid, grid2 = b.grid(), b.fused_grid()
     b.close()
     out = _variant(cells, ms, BYTES_PER_LUP[(storage, 2)], probe)
     out.update({"runs": n_runs, "cells": cells, "tiles": tiles, "steps": steps, "steps_per_launch": fuse,
                 "grid": grid, "fused_grid": grid2,
-                "tile_width_by_n": {str(n): w for n, w in widths}})
+                "tile_width_by_n": {str(n): w for n, w in widths},
+                "fused_tile_by_n": {str(n): t for n, t in shapes}})
     return out
 
 

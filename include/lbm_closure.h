@@ -40,6 +40,21 @@ lbm_status lbm_closure_features(const float* moments, int32_t dim, int64_t cells
 lbm_status lbm_closure_target(const float* m_next, const float* m_now, int64_t cells, float s_drho,
                               float s_dq, float* t, void* stream);
 
+/* Divergence-free training target of a window (2D, n x n periodic, 1 <= n <= 1024):
+ *   out_rho = now_rho,   out_q = now_q + P(fine_q - now_q)
+ * for [3][n][n] device moment planes (rho, q_x, q_y), where P is the spectral
+ * Helmholtz projection onto divergence-free fields, d^(k) - k (k . d^(k)) / |k|^2
+ * for every wavenumber k != 0 (signed: k = m for m < n/2, m - n otherwise) with
+ * the mean kept.  The artificial compressibility of the scheme carries
+ * acoustic waves at a speed ~1/dx that differs on every grid; the projection
+ * keeps the incompressible dynamics a coarse correction can learn.  Computed
+ * in FP64 (discrete Fourier sums), rounded to FP32 once.  scratch: device
+ * memory of lbm_closure_project_scratch_bytes(n) bytes (0 for an invalid n);
+ * out must not alias the inputs.  Asynchronous on `stream`. */
+size_t lbm_closure_project_scratch_bytes(int32_t n);
+lbm_status lbm_closure_project(const float* m_fine, const float* m_now, int32_t n, float* out, void* scratch,
+                               void* stream);
+
 /* Replace the state of ctx by the equilibrium of the device moments (end of
  * Section 2: populations at equilibrium); the step count is kept. */
 lbm_status lbm_set_equilibrium_device(lbm_ctx* ctx, const float* moments);

@@ -94,3 +94,28 @@ def closure_run(f, p: scheme.Params, params, scales, steps: int, every: int = 4,
         else:
             rej += 1
     return f, acc, rej
+
+
+def solenoidal(u: np.ndarray) -> np.ndarray:
+    """Divergence-free part of a periodic 2D field u[2][n][n] (x last): the
+    spectral Helmholtz projection u^(k) - k (k . u^(k)) / |k|^2 for every
+    wavenumber k != 0, with numpy's signed frequencies (fftfreq) and the mean
+    kept.  The correction network is trained on the divergence-free part of
+    the fine-minus-coarse momentum difference."""
+    n = u.shape[-1]
+    k = np.fft.fftfreq(n, 1.0 / n)
+    kx, ky = k[None, :], k[:, None]
+    k2 = kx * kx + ky * ky
+    k2[0, 0] = 1.0
+    ux, uy = np.fft.fft2(u[0]), np.fft.fft2(u[1])
+    div = kx * ux + ky * uy
+    return np.stack([np.fft.ifft2(ux - kx * div / k2).real, np.fft.ifft2(uy - ky * div / k2).real])
+
+
+def projected_target(m_fine: np.ndarray, m_now: np.ndarray) -> np.ndarray:
+    """Training target of a window: the density of the coarse state and its
+    momentum plus the divergence-free part of the fine-minus-coarse momentum
+    difference (moment planes [3][n][n]: rho, q_x, q_y)."""
+    out = m_now.astype(np.float64).copy()
+    out[1:] += solenoidal(m_fine[1:].astype(np.float64) - m_now[1:].astype(np.float64))
+    return out

@@ -36,3 +36,15 @@ def test_last_decreasing_level():
     assert cl.last_decreasing_level(LEVELS, ERR) == 512
     assert cl.last_decreasing_level(LEVELS, {"256": 4e-5, "512": 1e-5, "1024": 3e-6}) == 1024
     assert cl.last_decreasing_level(LEVELS, {"256": 4e-5, "512": 5e-5, "1024": 3e-6}) == 256
+
+
+def test_restriction_binding_checks_the_buffer_sizes():
+    """The restriction writes 3 (nfx/r)(nfy/r) values: a level that does not
+    divide the fine grid, or an output buffer of another size, is refused
+    before any device call."""
+    torch = pytest.importorskip("torch")
+    fine = torch.empty(3 * 2048 * 2048)
+    with pytest.raises(ValueError):
+        cl.lbm_restrict(fine, 2048, 2048, 2048 // 768, 1.0, torch.empty(3 * 768 * 768), None)
+    with pytest.raises(ValueError):
+        cl.lbm_restrict(fine, 2048, 2048, 3, 1.0, torch.empty(3 * 682 * 682), None)

@@ -224,7 +224,8 @@ def test_end_to_end_small_configuration():
     assert math.isfinite(ev["closure"]["u_sol"]) and math.isfinite(ev["plain"]["f32"]["u_sol"]["64"])
     assert math.isfinite(ev["plain"]["f16_dev_r32"]["time_ms"]["128"])
     assert ev["closure"]["accepted"] + ev["closure"]["rejected"] == 4
-    assert "speedup" in ev["speedup_equal_error"]["closure"]
+    assert "speedup" in ev["speedup_equal_error"]["u_sol"]["closure"]
+    assert "speedup" in ev["speedup_equal_error"]["u"]["closure"]
 
 
 def test_graph_replayed_window_equals_eager():
@@ -254,3 +255,28 @@ def test_graph_replayed_window_equals_eager():
     assert ra["n_accepted"] == rb["n_accepted"] == 4
     eager.close()
     graph.close()
+
+
+@pytest.mark.parametrize("n", [256, 64, 75, 1])
+def test_projection_matches_oracle(n):
+    """The divergence-free training target on the device (FP64 Fourier sums,
+    rounded once to FP32) against the oracle's spectral projection: every
+    value within one FP32 rounding of the oracle's, the density copied, and
+    the scratch size / argument checks."""
+    rng = np.random.default_rng(n)
+    now = np.stack([1 + 1e-3 * rng.standard_normal((n, n)), rng.standard_normal((n, n)),
+                    rng.standard_normal((n, n))]).astype(np.float32)
+    fine = (now + 1e-2 * rng.standard_normal((3, n, n))).astype(np.float32)
+    ref = ocl.projected_target(fine.astype(np.float64), now.astype(np.float64))
+    out = torch.empty((3, n, n), dtype=torch.float32, device="cuda")
+    nb = cl.lbm_closure_project_scratch_bytes(n)
+    assert nb == 2 * n * n * 16
+    scratch = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    cl.lbm_closure_project(dev(fine), dev(now), n, out, scratch, torch.cuda.current_stream())
+    got = out.double().cpu().numpy()
+    assert np.array_equal(got[0], now[0].astype(np.float64))
+    ulp = np.spacing(np.abs(ref[1:]).astype(np.float32)).astype(np.float64)
+    assert np.all(np.abs(got[1:] - ref[1:]) <= ulp), float(np.max(np.abs(got[1:] - ref[1:]) / ulp))
+    assert cl.lbm_closure_project_scratch_bytes(0) == 0 and cl.lbm_closure_project_scratch_bytes(1025) == 0
+    with pytest.raises(lbm.LbmError):
+        cl.lbm_closure_project(out, dev(now), n, out, scratch, torch.cuda.current_stream())

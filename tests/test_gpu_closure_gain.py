@@ -42,6 +42,6 @@ def test_trained_network_beats_plain_coarse():
         assert corr <= 0.5 * plain
         assert ps["closure_u"][i] <= ps["plain_coarse_u"][i]
     assert ev["closure"]["rejected"] == 0
-    sp = ev["speedup_equal_error"]["closure"]
+    sp = ev["speedup_equal_error"]["u_sol"]["closure"]
     print(f"[gain] equal-error speedup over plain FP32: {sp}", flush=True)
     assert math.isfinite(sp["N_star"]) and sp["N_star"] > 256

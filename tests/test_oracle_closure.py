@@ -80,3 +80,63 @@ def test_guard_accepts_a_small_divergence_free_correction():
     d_q = 1e-3 * inputs.random_field_2d(n, 9, umax=1.0)
     ok, div0, div1 = closure.guard(rho, q, np.zeros_like(rho), d_q, p.dx)
     assert ok and math.isfinite(div1)
+
+
+def _spectral_div(u):
+    n = u.shape[-1]
+    k = np.fft.fftfreq(n, 1.0 / n)
+    return np.fft.ifft2(1j * k[None, :] * np.fft.fft2(u[0]) + 1j * k[:, None] * np.fft.fft2(u[1])).real
+
+
+@pytest.mark.parametrize("n", [8, 15, 64])
+def test_solenoidal_projection_properties(n):
+    """The Helmholtz projection keeps divergence-free fields, removes gradient
+    fields, is idempotent and leaves a field of zero spectral divergence; the
+    mean is kept.  Fields from a stream function and a potential sampled at
+    cell centres (exact trigonometric sums, so exactly solenoidal / irrotational
+    on the grid)."""
+    x = (np.arange(n) + 0.5) * 2 * np.pi / n
+    X, Y = np.meshgrid(x, x)
+    rng = np.random.default_rng(n)
+    psi_x, psi_y = np.zeros((n, n)), np.zeros((n, n))
+    phi_x, phi_y = np.zeros((n, n)), np.zeros((n, n))
+    for kx in range(-2, 3):
+        for ky in range(-2, 3):
+            a, b = rng.normal(size=2)
+            # psi = a sin(kx x + ky y), phi = b cos(kx x + ky y)
+            arg = kx * X + ky * Y
+            psi_x += a * ky * np.cos(arg)      # u = (d_y psi, -d_x psi)
+            psi_y += -a * kx * np.cos(arg)
+            phi_x += -b * kx * np.sin(arg)     # grad phi
+            phi_y += -b * ky * np.sin(arg)
+    sol = np.stack([psi_x, psi_y]) + np.array([0.3, -0.2])[:, None, None]
+    grad = np.stack([phi_x, phi_y])
+    scale = np.max(np.abs(sol))
+    assert np.max(np.abs(closure.solenoidal(sol) - sol)) <= 1e-13 * scale
+    assert np.max(np.abs(closure.solenoidal(grad))) <= 1e-13 * np.max(np.abs(grad))
+    mixed = sol + grad
+    p = closure.solenoidal(mixed)
+    assert np.max(np.abs(p - sol)) <= 1e-13 * scale
+    assert np.max(np.abs(closure.solenoidal(p) - p)) <= 1e-13 * scale
+    assert np.max(np.abs(_spectral_div(p))) <= 1e-12 * scale * n
+    # a random field without content at the Nyquist frequency (n even), where
+    # numpy's signed frequency -n/2 pairs a mode with itself
+    r = rng.normal(size=(2, n, n))
+    if n % 2 == 0:
+        rh = np.fft.fft2(r)
+        rh[:, n // 2, :] = 0.0
+        rh[:, :, n // 2] = 0.0
+        r = np.fft.ifft2(rh).real
+    pr = closure.solenoidal(r)
+    assert np.allclose(pr.mean(axis=(1, 2)), r.mean(axis=(1, 2)), atol=1e-14)
+    assert np.max(np.abs(_spectral_div(pr))) <= 1e-12 * n
+
+
+def test_projected_target_keeps_density_and_adds_projection():
+    n = 16
+    rng = np.random.default_rng(3)
+    now = rng.normal(size=(3, n, n))
+    fine = now + 1e-3 * rng.normal(size=(3, n, n))
+    t = closure.projected_target(fine, now)
+    assert np.array_equal(t[0], now[0])
+    assert np.allclose(t[1:] - now[1:], closure.solenoidal(fine[1:] - now[1:]), atol=1e-16)
