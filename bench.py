@@ -140,7 +140,7 @@ def cpu_baseline(n: int = 4096, steps: int = 10, nu: float = 1e-3) -> dict:
 def headline_kernel(fuse: int) -> str:
     """The step kernel instantiation the 4096^2 FP32 engine launches at `fuse`
     steps per launch (tiles as chosen in the library)."""
-    tile = {3: "32,16,256", 4: "64,16,512", 5: "32,32,512", 6: "32,16,256"}
+    tile = {3: "32,16,256", 4: "64,16,512", 5: "32,32,768", 6: "32,16,256"}
     if fuse >= 3:
         return f"k_stepKr_2d<float,float,{tile[fuse]},{fuse},true>"
     return "k_step2_2d<float,float,256,8,1024>" if fuse == 2 else "k_step<2,float,float>"
@@ -275,9 +275,9 @@ def main():
         del u0
         n3 = 256
         u3, *_ = make_workload(n3, 3, 1e-3)
-        for storage, fuse_3 in (("f32", None), ("f32", 1), ("f16_dev", None), ("bf16_dev", None),
+        for storage, fuse_3 in (("f32", None), ("f32", 2), ("f32", 1), ("f16_dev", None), ("bf16_dev", None),
                                 ("f16_dev_r32", None), ("bf16_dev_r32", None), ("f16_neq", None)):
-            name = f"3d_{n3}_{storage}" + ("_one_step_per_launch" if fuse_3 == 1 else "")
+            name = f"3d_{n3}_{storage}" + {1: "_one_step_per_launch", 2: "_two_steps_per_launch"}.get(fuse_3, "")
             log(f"[bench] variant {name}")
             ms_v, e = time_engine(n3, 3, storage, vs, VARIANT_WARMUP, u0=u3, fuse=fuse_3)
             fuse_v = e.fusion()

@@ -152,11 +152,12 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const 
  * The result is bit-identical for any fusion setting.  Asynchronous. */
 lbm_status lbm_step(lbm_ctx* ctx, int64_t nsteps);
 
-/* Time steps per launch, 1 .. 6.  In 2D, 2 .. 6 in any storage but LBM_F64;
- * in 3D, 2 for LBM_F32 and LBM_F32_RAW (a kernel that marches along z); channel
- * boundaries allow 1 only.  LBM_EINVAL otherwise.  Default in 2D from 2^20
- * cells on: 4 for LBM_F32_MOMENTS, 5 otherwise; else 2 where available, 1
- * otherwise. */
+/* Time steps per launch, 1 .. 6.  In 2D, 2 .. 6 in any storage but LBM_F64
+ * (3 .. 6 only while a plane holds at most 2^32 bytes, i.e. 2^30 FP32 cells);
+ * in 3D, 2 and 3 for LBM_F32 and LBM_F32_RAW (kernels that march along z);
+ * channel boundaries allow 1 only.  LBM_EINVAL otherwise.  Default from 2^20
+ * cells on: 4 for LBM_F32_MOMENTS in 2D, 5 for the other 2D storages, 3 for
+ * the 3D FP32 storages; else 2 where available, 1 otherwise. */
 lbm_status lbm_set_fusion(lbm_ctx* ctx, int32_t steps_per_launch);
 
 /* The current number of time steps per launch (0 for a NULL context). */

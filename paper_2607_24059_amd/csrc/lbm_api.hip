@@ -10,6 +10,7 @@
 #include <new>
 
 #include "lbm.h"
+#include "lbm_fused.hpp"
 #include "lbm_internal.hpp"
 
 using lbm::Geometry;
@@ -162,6 +163,15 @@ void default_block(const Geometry& g, int* bx, int* by) {
 
 }  // namespace
 
+// Whether a context may run the K >= 3 kernels: the 2D tiles address a plane
+// with 32-bit byte offsets (fused_offsets_fit), so planes of more than 2^32
+// bytes take the two-step kernel.
+static bool multi_step_fits(const lbm_ctx* c) {
+  return c->ops->stepK && (c->p.dim != 2 || lbm::fused_offsets_fit(c->g.cells, c->g.move_elem > c->g.rest_elem
+                                                                                    ? c->g.move_elem
+                                                                                    : c->g.rest_elem));
+}
+
 // Default steps per launch of the multi-step kernels, from sweeps at 4096^2 /
 // 2048^2: the population storages peak at 5 (FP32 with the rest in registers
 // on 32x32 tiles: 159.7 / 136.0 GLUPS, against 143.5 / 135.1 at 6 and 139.3 /
@@ -224,9 +234,9 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const 
   default_block(g, &c->bx, &c->by);
   // deeper fusion from 1024^2 cells on; smaller grids are launch-bound and
   // keep the two-step kernel's small tiles
-  c->fuse = c->ops->stepK && g.cells >= (int64_t(1) << 20) ? std::min(default_depth(p->storage), c->ops->max_fuse)
-            : c->ops->step2                                  ? 2
-                                                             : 1;
+  c->fuse = multi_step_fits(c) && g.cells >= (int64_t(1) << 20) ? std::min(default_depth(p->storage), c->ops->max_fuse)
+            : c->ops->step2                                        ? 2
+                                                                   : 1;
 
   // stage u0 (and rho0) as FP64 in the idle buffer, then build the equilibrium
   double* su = reinterpret_cast<double*>(staging(c));
@@ -272,7 +282,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
 lbm_status lbm_set_fusion(lbm_ctx* c, int32_t steps_per_launch) {
   if (!c || steps_per_launch < 1 || steps_per_launch > c->ops->max_fuse) return LBM_EINVAL;
   if (steps_per_launch >= 2 && (!c->ops->step2 || c->walls)) return LBM_EINVAL;
-  if (steps_per_launch >= 3 && !c->ops->stepK) return LBM_EINVAL;
+  if (steps_per_launch >= 3 && !multi_step_fits(c)) return LBM_EINVAL;
   c->fuse = steps_per_launch;
   return LBM_OK;
 }

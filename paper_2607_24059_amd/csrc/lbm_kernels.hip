@@ -443,17 +443,30 @@ __global__ __launch_bounds__(64 * (TY + 5)) void k_step3_3d(const TR* __restrict
   float r1p[4], z1p[4], z1pp[4], r2p[4], z2p[4], z2pp[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) r1p[i] = z1p[i] = z1pp[i] = r2p[i] = z2p[i] = z2pp[i] = 0.0f;
+  // the stage-1 gather of the next plane is issued before the current plane's
+  // work (45.6 against 45.0 GLUPS at 256^3); loads stay in flight across the
+  // barrier, which waits on LDS only
+  float gn[4][7];
+  if (col) {
+    const int pz = wrap_coord(z0 - 2, nz);
+    gather_cell<3, TR, TM>(sr, sm, x, y, pz, nx, ny, nz, stride, static_cast<int64_t>(pz) * plane + cxy, gn);
+  }
   for (int p = z0 - 2; p <= zend + 1; ++p) {
     const int sl = p & 1;
+    float g[4][7];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int l = 0; l < 7; ++l) g[i][l] = gn[i][l];
+    if (col && p + 1 <= zend + 1) {
+      const int pz = wrap_coord(p + 1, nz);
+      gather_cell<3, TR, TM>(sr, sm, x, y, pz, nx, ny, nz, stride, static_cast<int64_t>(pz) * plane + cxy, gn);
+    }
     // stage 1, plane p, from HBM
     float r1[4], zp1[4], zm1[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) r1[i] = zp1[i] = zm1[i] = 0.0f;
     if (col) {
-      const int pz = wrap_coord(p, nz);
-      const int64_t c = static_cast<int64_t>(pz) * plane + cxy;
-      float g[4][7];
-      gather_cell<3, TR, TM>(sr, sm, x, y, pz, nx, ny, nz, stride, c, g);
       collide<3>(g, k);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -979,9 +992,11 @@ struct Impl {
   // storage is ALU-bound (it rebuilds the upwind equilibria) and runs 128x8
   // on 1024 threads: 91 vs 85 GLUPS for 128x8/512 (64x8/512: 72, 256x4/1024: 77).
   // 3D: the z-marching two-step kernel for 4-byte planes (FP32, raw FP32)
-  static constexpr bool kHasStep2 =
-      (D == 2 && !std::is_same<TM, double>::value) ||
-      (D == 3 && std::is_same<TR, float>::value && std::is_same<TM, float>::value);
+  // 3D: the z-marching kernels for the population storages (FP32 and the
+  // 16-bit deviation storages; not FP64 or the split and moment-only ones)
+  static constexpr bool k3DPop = D == 3 && !std::is_same<TM, double>::value && !IsNeq<TM>::value &&
+                                 !IsMom<TM>::value;
+  static constexpr bool kHasStep2 = (D == 2 && !std::is_same<TM, double>::value) || k3DPop;
   // 64 x 8 columns on 704 threads, 32-plane segments (GLUPS at 256^3: 31.5;
   // 32x16 / 640: 29.2, with 64-plane segments 28.2; 64x12 / 960: 27.5;
   // 96x8 / 1024: 28.0; 32x8 and 16x16 / 384: 25.3, 20.9; 16- and 24-plane
@@ -1038,8 +1053,7 @@ struct Impl {
   // (TX+2K)(TY+2K)/(TX TY) times and written once per K steps) at the price of
   // recomputing the shrinking borders; K = 6..8 and 32x16, 32x32 or 64x32
   // tiles were within a few percent or slower.
-  static constexpr bool kHasStepK =
-      (kHasStep2 && D == 2) || (D == 3 && std::is_same<TR, float>::value && std::is_same<TM, float>::value);
+  static constexpr bool kHasStepK = (kHasStep2 && D == 2) || k3DPop;
   // most steps per launch: 6 in 2D, 3 for the 3D FP32 storages, else the
   // two-step kernel's 2 or one
   static constexpr int kMaxFuse = kHasStepK ? (D == 2 ? kMaxFusion : 3) : kHasStep2 ? 2 : 1;
@@ -1079,14 +1093,16 @@ struct Impl {
                          reinterpret_cast<float*>(b.rest), g.nx, g.ny, g.stride, k);
     } else if constexpr (kRestInRegisters) {
       // the tile per depth (inner-first cell order; GLUPS at 4096^2 / 2048^2):
-      // K = 5: 32x32 on 512 threads, 159.7 / 136.0 (its 77 KB of LDS lets two
+      // K = 5: 32x32, 159.7 / 136.0 on 512 threads (its 77 KB of LDS lets two
       // blocks share a CU; 135.5 without the XCD order), against 145.3 / 136.4
-      // for 32x16 on 256; K = 4: 64x16 on 512, 139.3 / 132.9 against 125.0 /
-      // 122.1; K = 3 and 6: 32x16 on 256 (102.2 and 143.5 at 4096^2; 32x32 at
-      // K = 6 needs 85 KB per block and ran 108.6)
+      // for 32x16 on 256; on 768 threads (24 waves per CU instead of 16,
+      // 60 VGPRs) 177.5 against 172.7 after the relaxation change (640: 115);
+      // K = 4: 64x16 on 512, 139.3 / 132.9 against 125.0 / 122.1; K = 3 and
+      // 6: 32x16 on 256 (102.2 and 143.5 at 4096^2; 32x32 at K = 6 needs 85 KB
+      // per block and ran 108.6)
       constexpr int TX = K == 5 ? 32 : K == 4 ? 64 : 32;
       constexpr int TY = K == 5 ? 32 : 16;
-      constexpr int NT = K == 5 || K == 4 ? 512 : 256;
+      constexpr int NT = K == 5 ? 768 : K == 4 ? 512 : 256;
       const int64_t tiles = static_cast<int64_t>((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY);
       hipLaunchKernelGGL((k_stepKr_2d<TR, TM, TX, TY, NT, K, true>), dim3(static_cast<uint32_t>(tiles)), dim3(NT), 0,
                          s, a.rest, a.move, b.rest, b.move, g.nx, g.ny, g.stride, k);

@@ -421,15 +421,15 @@ def test_fusion_settings_and_defaults():
     e3.close()
 
 
-@pytest.mark.parametrize("storage", ["f32", "f32_raw"])
+@pytest.mark.parametrize("storage", ["f32", "f32_raw", "f16_dev", "bf16_dev", "f16_dev_r32", "bf16_dev_r32"])
 @pytest.mark.parametrize("shape,steps", [((8, 8, 8), 6), ((17, 13, 9), 7), ((40, 20, 33), 5), ((1, 1, 1), 4),
                                          ((3, 70, 5), 9), ((64, 64, 64), 3), ((70, 9, 66), 4), ((33, 7, 130), 8)])
 def test_multi_step_fusion_3d_is_bitwise(storage, shape, steps):
-    """3D, 4-byte planes: the z-marching two-step kernel (64 x 8 columns,
-    32-plane segments) and three-step kernel (64 x 6 columns, 32-plane
-    segments) give the single-step state bit for bit, ragged in every
-    direction, over several segments along z, and with remainders that run
-    as shorter launches."""
+    """3D population storages: the z-marching two-step kernel (64 x 8
+    columns, 32-plane segments) and three-step kernel (64 x 6 columns,
+    32-plane segments) give the single-step state bit for bit, ragged in
+    every direction, over several segments along z, and with remainders that
+    run as shorter launches."""
     nz, ny, nx = shape
     dx = 2 * math.pi / max(shape)
     p = scheme.Params(dim=3, dx=dx, dt=dx * dx / 8, nu=0.02)
@@ -454,9 +454,16 @@ def test_two_step_fusion_3d_defaults_and_limits():
         with pytest.raises(lbm.LbmError):
             eng.set_fusion(bad)
     eng.close()
-    for storage in ("f16_dev", "f16_dev_r32", "f16_neq", "f64"):
+    for storage in ("f16_neq", "f64"):
         e = _engine(p, u, storage=storage)
         assert e.fusion() == 1
         with pytest.raises(lbm.LbmError):
             e.set_fusion(2)
+        e.close()
+    for storage in ("f16_dev", "f16_dev_r32"):
+        e = _engine(p, u, storage=storage)
+        assert e.fusion() == 2
+        e.set_fusion(3)
+        with pytest.raises(lbm.LbmError):
+            e.set_fusion(4)
         e.close()
