@@ -582,6 +582,8 @@ ONLY = {
     "moments_2d": lambda a: moments_variant(2, a.n, a.variant_steps, copy_probe_gbs()),
     "moments_3d": lambda a: moments_variant(3, 256, a.variant_steps, copy_probe_gbs()),
     "sweep": lambda a: sweep_variant(),
+    "batch_f32": lambda a: batch_variant("f32", 1000, copy_probe_gbs()),
+    "batch_f16_dev_r32": lambda a: batch_variant("f16_dev_r32", 1000, copy_probe_gbs()),
 }
 
 if __name__ == "__main__":

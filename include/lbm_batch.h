@@ -50,7 +50,9 @@ size_t lbm_batch_workspace_bytes(int32_t dim, int32_t storage, int32_t nruns,
  *   u0[r]    host FP64 [dim][cells_r] velocity of run r (required)
  *   rho0     NULL, or an array whose entries are NULL (rho_ref) or FP64 [cells_r]
  * Returns LBM_EINVAL / LBM_EUNSTABLE for the first invalid run (its index in
- * *bad_run if bad_run != NULL).  Synchronises once. */
+ * *bad_run if bad_run != NULL); a 2D run of more than 2^30 cells is invalid in
+ * a batch (the multi-step tiles address a plane with 32-bit byte offsets).
+ * Synchronises once. */
 lbm_status lbm_batch_init(lbm_batch** out, int32_t dim, int32_t storage, int32_t nruns,
                           const lbm_run_spec* runs, const double* const* u0,
                           const double* const* rho0, void* workspace, size_t ws_bytes,
@@ -59,10 +61,11 @@ lbm_status lbm_batch_init(lbm_batch** out, int32_t dim, int32_t storage, int32_t
 /* Choose the tile shape of every size class (runs grouped by nx rounded up to
  * a power of two), then the number of blocks of the persistent launch (4, 8,
  * 16 or 32 per compute unit, or one per tile), and in 2D the number of blocks
- * of the two-step launch (1, 2, 4 or 8 per compute unit, or one per tile), the
- * five-step tile shape of every size class (each shape timed on the class's
- * runs alone) and the blocks per compute unit of the five-step launches, by
- * timing each candidate on the batch's own buffers; the state is not changed.
+ * of the two-step launch (1, 2, 4 or 8 per compute unit, or one per tile) and
+ * the five-step tile shape of every size class (each shape timed on the
+ * class's runs alone, as a graph launch), by timing each candidate on the
+ * batch's own buffers; the state is not changed.  The five-step launches keep
+ * one block per tile (lbm_batch_set_fused_grid changes that).
  * If cache_path is non-NULL (else the environment
  * variable LBM_AUTOTUNE_CACHE, if set) previously tuned shapes for this
  * device, dimension and storage are read from that text file and new ones are
@@ -86,9 +89,11 @@ int32_t lbm_batch_tile_width(const lbm_batch* b, int32_t run);
  * means one block per tile); chosen by lbm_batch_autotune. */
 int32_t lbm_batch_grid(const lbm_batch* b);
 
-/* Blocks of the current multi-step launch: the five-step kernel's when the
- * fusion is 5, else the two-step kernel's (0 if the batch has none, i.e. in
- * 3D).  Chosen by lbm_batch_autotune. */
+/* Blocks of the current multi-step launch: the five-step kernel's (summed
+ * over its tile shapes) when the fusion is 5, else the two-step kernel's (0 if
+ * the batch has none, i.e. in 3D).  The two-step grid is chosen by
+ * lbm_batch_autotune; the five-step grid is one block per tile unless
+ * lbm_batch_set_fused_grid set a persistent one. */
 int32_t lbm_batch_fused_grid(const lbm_batch* b);
 
 /* Cell tile (tx x ty) of run r in the five-step launches (2D population
@@ -100,6 +105,14 @@ lbm_status lbm_batch_fused_tile(const lbm_batch* b, int32_t run, int32_t* tx, in
 /* Use fused tile shape `shape` (0, 1 or 2, in the order above) for every run
  * (results do not depend on it).  Rebuilds the step graphs.  Synchronises. */
 lbm_status lbm_batch_set_fused_shape(lbm_batch* b, int32_t shape);
+
+/* Blocks per compute unit of each five-step launch (1..64; each block then
+ * walks several tiles), or 0 for one block per tile (the default); results do
+ * not depend on it.  A persistent grid is slower here: the launch's per-shape
+ * graph nodes run concurrently and share the compute units.  2D population
+ * storages only (LBM_EINVAL otherwise).  Rebuilds the step graphs.
+ * Synchronises. */
+lbm_status lbm_batch_set_fused_grid(lbm_batch* b, int32_t blocks_per_cu);
 
 /* Steps per launch: 1 (one-step kernel), 2 (two-step kernel) or 5 (five-step
  * kernel, the default); 2 and 5 in 2D only; LBM_EINVAL otherwise.  Every

@@ -43,6 +43,7 @@ SIGNATURES = {
     "lbm_batch_fused_grid": (C.c_int32, [C.c_void_p]),
     "lbm_batch_fused_tile": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "lbm_batch_set_fused_shape": (C.c_int, [C.c_void_p, C.c_int32]),
+    "lbm_batch_set_fused_grid": (C.c_int, [C.c_void_p, C.c_int32]),
     "lbm_batch_set_fusion": (C.c_int, [C.c_void_p, C.c_int32]),
     "lbm_batch_fusion": (C.c_int32, [C.c_void_p]),
     "lbm_batch_destroy": (None, [C.c_void_p]),
@@ -143,6 +144,10 @@ def lbm_batch_set_fused_shape(h: int, shape: int) -> None:
     _ok(blib().lbm_batch_set_fused_shape(C.c_void_p(h), int(shape)), "lbm_batch_set_fused_shape")
 
 
+def lbm_batch_set_fused_grid(h: int, blocks_per_cu: int) -> None:
+    _ok(blib().lbm_batch_set_fused_grid(C.c_void_p(h), int(blocks_per_cu)), "lbm_batch_set_fused_grid")
+
+
 def lbm_batch_set_fusion(h: int, steps_per_launch: int) -> None:
     _ok(blib().lbm_batch_set_fusion(C.c_void_p(h), steps_per_launch), "lbm_batch_set_fusion")
 
@@ -222,6 +227,9 @@ class Batch:
 
     def set_fused_shape(self, shape: int) -> None:
         lbm_batch_set_fused_shape(self.handle, shape)
+
+    def set_fused_grid(self, blocks_per_cu: int) -> None:
+        lbm_batch_set_fused_grid(self.handle, blocks_per_cu)
 
     def close(self) -> None:
         if self.handle:

@@ -561,13 +561,12 @@ def last_decreasing_level(levels, err) -> int:
 def equal_error_speedup(levels, err, time_ms, e_target, t_target):
     """Speedup of a run with error e_target and wall time t_target over the
     plain FP32 scheme at equal error.  N* is the resolution at which the plain
-    scheme's error equals e_target, by log-log interpolation of err(N) over
-    the levels where it still decreases (FP32 rounding, which grows with the
-    N^2 steps of a run, ends the second-order decrease at fine levels); beyond
-    the last decreasing level it is extrapolated along the last segment.
-    T_plain(N*) is interpolated (extrapolated) log-log the same way;
-    speedup = T_plain(N*) / t_target.  A target error above the coarsest
-    level's has no equal-error point (NaN)."""
+    scheme's error equals e_target, by log-log interpolation of err(N) between
+    two levels over which it still decreases (FP32 rounding, which grows with
+    the N^2 steps of a run, ends the second-order decrease at fine levels);
+    T_plain(N*) is interpolated log-log the same way; speedup = T_plain(N*) /
+    t_target.  No extrapolation: a target error above the coarsest level's or
+    below the finest decreasing level's has no equal-error point (NaN)."""
     lv = sorted(int(n) for n in levels)
     e = [float(err[str(n)]) for n in lv]
     t = [float(time_ms[str(n)]) for n in lv]
@@ -578,16 +577,17 @@ def equal_error_speedup(levels, err, time_ms, e_target, t_target):
     if not e_target < e[0]:
         return {"N_star": float("nan"), "speedup": float("nan"),
                 "note": "error above the plain scheme's at the coarsest level: no equal-error point"}
-    if len(lv) < 2:
-        return {"N_star": float("nan"), "speedup": float("nan"), "note": "one level only"}
+    if not e_target >= e[-1]:
+        return {"N_star": float("nan"), "speedup": float("nan"),
+                "note": f"error below the plain scheme's at every level up to {lv[-1]} (the finest level "
+                        "where its error still decreases): no equal-error point without extrapolation"}
     ln, le, lt = np.log(lv), np.log(e), np.log(t)
     lc = math.log(e_target)
-    i = next((j for j in range(len(lv) - 1) if le[j + 1] <= lc), len(lv) - 2)
+    i = next(j for j in range(len(lv) - 1) if le[j + 1] <= lc)
     f = (lc - le[i]) / (le[i + 1] - le[i])
     nstar = math.exp(ln[i] + f * (ln[i + 1] - ln[i]))
     tstar = math.exp(lt[i] + f * (lt[i + 1] - lt[i]))
-    note = "interpolated" if f <= 1.0 else "extrapolated beyond the finest decreasing level"
-    return {"N_star": nstar, "speedup": tstar / t_target, "note": note}
+    return {"N_star": nstar, "speedup": tstar / t_target, "note": "interpolated"}
 
 
 # trained correction network shipped with the package (written by main())

@@ -151,10 +151,11 @@ constexpr int kShapes = 3;
 template <typename TR, typename TM, int S>
 struct BatchKShape {
   static constexpr bool kRegs = sizeof(TR) == 4 && sizeof(TM) == 4;
-  // 4-byte planes, rest populations in registers: 32x32 on 512 threads (the
-  // single-run engine's tile, two blocks per compute unit), 32x16 on 256
-  // (three blocks per compute unit), 16x16 on 256 (small runs: more tiles);
-  // 16-bit planes: 64x16 on 512, 32x32 on 512, 32x16 on 256.
+  // 4-byte planes, rest populations in registers: 32x32 on 512 threads (two
+  // blocks per compute unit; on 768 threads, the single-run engine's choice,
+  // the 512-run batch ran 105 against 169 GLUPS), 32x16 on 256 (three blocks
+  // per compute unit), 16x16 on 256 (small runs: more tiles); 16-bit planes:
+  // 64x16 on 512, 32x32 on 512, 32x16 on 256.
   static constexpr int TX = kRegs ? (S == 2 ? 16 : 32) : (S == 0 ? 64 : 32);
   static constexpr int TY = kRegs ? (S == 0 ? 32 : 16) : (S == 1 ? 32 : 16);
   static constexpr int NT = kRegs ? (S == 0 ? 512 : 256) : (S == 2 ? 256 : 512);
@@ -440,18 +441,6 @@ unsigned gridK_for(const lbm_batch* b, int64_t n) {
   return static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>(n, std::min<int64_t>(cap, 0x7fffffff))));
 }
 
-hipError_t launch_stepK(lbm_batch* b, int parity, hipStream_t s) {
-  for (int sh = 0; sh < kShapes; ++sh) {
-    if (b->countK[sh] == 0) continue;
-    const BatchTile* t = b->d_tilesK + b->startK[sh];
-    hipLaunchKernelGGL(b->kernelK[sh].fn, dim3(gridK_for(b, b->countK[sh])), dim3(b->kernelK[sh].threads), 0, s,
-                       b->d_runs, t, b->countK[sh], b->ws, parity);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
-}
-
 void destroy_graphs(lbm_batch* b) {
   auto drop = [](hipGraphExec_t& e) {
     if (e) hipGraphExecDestroy(e);
@@ -562,10 +551,11 @@ hipError_t rebuild(lbm_batch* b) {
 
 // The multi-step tile list of the runs selected by `use` (all if empty): the
 // tiles of each shape in one contiguous range, each range in XCD-major order
-// (list slot s is taken by a block on XCD s % 8, with one block per tile or a
-// persistent grid that is a multiple of 8, so the slots of XCD j get the j-th
-// eighth of the range in raster order and neighbouring tiles share their
-// border reads through one L2).
+// (xcd_major: list slot s is taken by a block on XCD s % 8, with one block per
+// tile or a persistent grid that is a multiple of 8, so neighbouring tiles
+// share their border reads through one L2; a range whose length is not a
+// multiple of 8 in raster order ran 5.07 against 4.12 ms per five-step launch
+// of the 512-run FP32 batch).
 hipError_t upload_tilesK(lbm_batch* b, const std::vector<char>& use = {}) {
   std::vector<BatchTile> all;
   for (int sh = 0; sh < kShapes; ++sh) {
@@ -580,11 +570,7 @@ hipError_t upload_tilesK(lbm_batch* b, const std::vector<char>& use = {}) {
     const size_t n = t.size();
     b->startK[sh] = static_cast<int64_t>(all.size());
     b->countK[sh] = static_cast<int64_t>(n);
-    if (n % 8 == 0) {
-      for (size_t q = 0; q < n; ++q) all.push_back(t[(q % 8) * (n / 8) + q / 8]);
-    } else {
-      all.insert(all.end(), t.begin(), t.end());
-    }
+    for (size_t q = 0; q < n; ++q) all.push_back(t[xcd_major(static_cast<int64_t>(q), static_cast<int64_t>(n))]);
   }
   b->ntilesK = static_cast<int64_t>(all.size());
   if (all.empty()) return hipSuccess;
@@ -647,6 +633,8 @@ lbm_status lbm_batch_init(lbm_batch** out, int32_t dim, int32_t storage, int32_t
     double mu = 0, aq = 0;
     lbm_status st = lbm_check_params(&p, &mu, &aq, nullptr);
     if (st == LBM_OK && (!u0[r] || runs[r].n[2] > 32767)) st = LBM_EINVAL;  // tile z is 16-bit
+    // the multi-step tiles address a plane with 32-bit byte offsets
+    if (st == LBM_OK && dim == 2 && !fused_offsets_fit(runs[r].n[0] * runs[r].n[1], 4)) st = LBM_EINVAL;
     if (st != LBM_OK) {
       if (bad_run) *bad_run = r;
       return st;
@@ -724,7 +712,11 @@ lbm_status lbm_batch_init(lbm_batch** out, int32_t dim, int32_t storage, int32_t
     b->cus = cus;
     b->grid = 8 * cus;  // 8 resident 256-thread blocks per CU at the kernel's register use
     b->grid2 = 2 * cus;  // two resident 512-thread fused blocks per CU (LDS tile of up to 40 KB)
-    b->gridK = 4;  // blocks per compute unit of each multi-step launch
+    // one block per tile in each multi-step launch: the launch's per-shape
+    // graph nodes run concurrently, and a persistent grid sized for the whole
+    // chip then waits for the compute units the other node holds (2 blocks per
+    // CU: 96 against 170 GLUPS for the 512-run FP32 batch)
+    b->gridK = 0;
     if (b->kernel2) e = upload_tiles2(b);
     if (e == hipSuccess && b->kernelK[0].fn) e = upload_tilesK(b);
     if (e == hipSuccess) e = rebuild(b);
@@ -750,7 +742,7 @@ lbm_status lbm_batch_autotune(lbm_batch* b, const char* cache_path) {
       int d, st, cl, bx;
       while (fscanf(f, "%127s %d %d %d %d", arch, &d, &st, &cl, &bx) == 5)
         if (key == arch && d == b->dim && st == b->storage && (cl < 0 || bx == 64 || bx == 128 || bx == 256))
-          cached[cl] = bx;  // cl >= 0: one-step tile width; -1, -2, -3: grids; -(1000 + cl): fused shape
+          cached[cl] = bx;  // cl >= 0: one-step tile width; -1, -2: grids; -(1000 + cl): fused shape
       fclose(f);
     }
   }
@@ -849,13 +841,23 @@ lbm_status lbm_batch_autotune(lbm_batch* b, const char* cache_path) {
   }
   // fused tile shape of every size class (cache key -(1000 + class)): each
   // candidate timed on the class's runs alone, one block per tile
+  // each candidate is timed as the steps run: replays of a one-launch graph
+  // whose per-shape nodes may overlap (timing plain launches in stream order
+  // ranked persistent grids first that lose when the nodes overlap); every
+  // replay reads the current buffer and writes the other: the state is kept
   auto time_K = [&](float* ms) {
-    for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch_stepK(b, b->parity, b->stream);
+    hipGraphExec_t g = nullptr;
+    if (e == hipSuccess) e = make_graphK(b, b->parity, 1, &g);
+    for (int w = 0; w < 2 && e == hipSuccess; ++w) e = hipGraphLaunch(g, b->stream);
     if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
-    for (int it = 0; it < 5 && e == hipSuccess; ++it) e = launch_stepK(b, b->parity, b->stream);
+    for (int it = 0; it < 6 && e == hipSuccess; ++it) e = hipGraphLaunch(g, b->stream);
     if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+    if (g) {
+      hipStreamSynchronize(b->stream);
+      hipGraphExecDestroy(g);
+    }
   };
   if (e == hipSuccess && b->kernelK[0].fn) {
     const int grid_keep = b->gridK;
@@ -885,27 +887,6 @@ lbm_status lbm_batch_autotune(lbm_batch* b, const char* cache_path) {
     }
     b->gridK = grid_keep;
     if (e == hipSuccess) e = upload_tilesK(b);
-  }
-  // blocks per compute unit of each multi-step launch (class -3; 0: one block per tile)
-  if (e == hipSuccess && b->kernelK[0].fn && cached.count(-3)) {
-    b->gridK = std::max(0, cached[-3]);
-  } else if (e == hipSuccess && b->kernelK[0].fn) {
-    const int cands[] = {1, 2, 4, 8, 0};
-    float best = 1e30f;
-    int best_pc = 4;
-    for (int pc : cands) {
-      if (e != hipSuccess) break;
-      b->gridK = pc;
-      // a launch reads the current buffer and writes the other: the state is kept
-      float ms = 0;
-      time_K(&ms);
-      if (e == hipSuccess && ms < best) {
-        best = ms;
-        best_pc = pc;
-      }
-    }
-    b->gridK = best_pc;
-    fresh.emplace_back(-3, best_pc);
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
@@ -1038,6 +1019,12 @@ lbm_status lbm_batch_set_fused_shape(lbm_batch* b, int32_t shape) {
   hipError_t e = upload_tilesK(b);
   if (e == hipSuccess) e = rebuild(b);
   return dev(e);
+}
+
+lbm_status lbm_batch_set_fused_grid(lbm_batch* b, int32_t blocks_per_cu) {
+  if (!b || !b->kernelK[0].fn || blocks_per_cu < 0 || blocks_per_cu > 64) return LBM_EINVAL;
+  b->gridK = blocks_per_cu;
+  return dev(rebuild(b));
 }
 
 lbm_status lbm_batch_set_fusion(lbm_batch* b, int32_t steps_per_launch) {

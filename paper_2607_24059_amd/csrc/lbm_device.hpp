@@ -213,6 +213,16 @@ __device__ __forceinline__ double recip_r(double x) { return 1.0 / x; }
 // Periodic index of v on a grid of n cells, for v within a tile border of the
 // grid: two compares while v lies in [-n, 2n), the remainder otherwise (tiny
 // grids, where a border wraps several times).
+// XCD-major order of n tiles: with a one-dimensional grid, block (slot) q
+// runs on XCD q mod 8, so XCD j takes the slots j, j + 8, ...; giving it the
+// j-th of eight contiguous runs of tiles (the first n mod 8 runs one longer)
+// makes the tiles that run together on one XCD neighbours, and their shared
+// borders are read through its L2.  A bijection of [0, n) for every n.
+__host__ __device__ __forceinline__ int64_t xcd_major(int64_t q, int64_t n) {
+  const int64_t j = q % 8, per = n / 8, extra = n % 8;
+  return j * per + (j < extra ? j : extra) + q / 8;
+}
+
 __device__ __forceinline__ int wrap_coord(int v, int n) {
   if (v >= -n && v < 2 * n) return v < 0 ? v + n : (v >= n ? v - n : v);
   return ((v % n) + n) % n;

@@ -84,13 +84,11 @@ __device__ __forceinline__ void lds_stages(TR (&s_rest)[3][EX * EY], TM (&s_move
 __device__ __forceinline__ void hbm_phase_begin() { __builtin_amdgcn_s_setprio(1); }
 __device__ __forceinline__ void hbm_phase_end() { __builtin_amdgcn_s_setprio(0); }
 
-// XCD: with a one-dimensional grid, consecutive blocks go to the eight XCDs in
-// turn; XCD-major numbering gives each XCD a contiguous band of tiles, so the
-// borders that neighbouring tiles share are read through the same L2.
+// origin of the tile that block b takes, in XCD-major order (xcd_major)
 __device__ __forceinline__ void xcd_tile_origin(int b, int nx, int ny, int TX, int TY, int* x0, int* y0) {
   const int tiles_x = (nx + TX - 1) / TX;
   const int nt = tiles_x * ((ny + TY - 1) / TY);
-  const int t = (nt % 8 == 0) ? (b % 8) * (nt / 8) + b / 8 : b;
+  const int t = static_cast<int>(xcd_major(b, nt));
   *x0 = (t % tiles_x) * TX;
   *y0 = (t / tiles_x) * TY;
 }

@@ -312,7 +312,7 @@ __global__ __launch_bounds__(NT) void k_step2_3d(const TR* __restrict__ sr, cons
   const int tx_n = (nx + TX - 1) / TX, ty_n = (ny + TY - 1) / TY;
   const int nt = tx_n * ty_n * ((nz + ZS - 1) / ZS);
   const int b = blockIdx.x;
-  const int tt = (nt % 8 == 0) ? (b % 8) * (nt / 8) + b / 8 : b;
+  const int tt = static_cast<int>(xcd_major(b, nt));
   const int x0 = (tt % tx_n) * TX, y0 = ((tt / tx_n) % ty_n) * TY, z0 = (tt / (tx_n * ty_n)) * ZS;
   int x = x0 - 1 + ex, y = y0 - 1 + ey;
   x = wrap_coord(x, nx);  // the border may wrap (several times on tiny grids)
@@ -430,7 +430,7 @@ __global__ __launch_bounds__(64 * (TY + 5)) void k_step3_3d(const TR* __restrict
   const int tx_n = (nx + TX - 1) / TX, ty_n = (ny + TY - 1) / TY;
   const int nt = tx_n * ty_n * ((nz + ZS - 1) / ZS);
   const int b = blockIdx.x;
-  const int tt = (nt % 8 == 0) ? (b % 8) * (nt / 8) + b / 8 : b;
+  const int tt = static_cast<int>(xcd_major(b, nt));
   const int x0 = (tt % tx_n) * TX, y0 = ((tt / tx_n) % ty_n) * TY, z0 = (tt / (tx_n * ty_n)) * ZS;
   int x = x0 - H + ex, y = y0 - H + ey;
   x = wrap_coord(x, nx);  // the border may wrap (several times on tiny grids)
@@ -576,7 +576,7 @@ __global__ __launch_bounds__(TX * TY) void k_step_mom_3d(const float* __restrict
   const int tx_n = (nx + TX - 1) / TX, ty_n = (ny + TY - 1) / TY;
   const int nt = tx_n * ty_n * ((nz + ZS - 1) / ZS);
   const int b = blockIdx.x;
-  const int tt = (nt % 8 == 0) ? (b % 8) * (nt / 8) + b / 8 : b;
+  const int tt = static_cast<int>(xcd_major(b, nt));
   const int x0 = (tt % tx_n) * TX, y0 = ((tt / tx_n) % ty_n) * TY, z0 = (tt / (tx_n * ty_n)) * ZS;
   const int zend = min(z0 + ZS, nz);
   const int ox = t % TX, oy = t / TX;
@@ -841,9 +841,9 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag(const TR* __restrict__ r,
   double a[kDiagSlots];
   identity(a);
   for (int sched = blockIdx.x; sched < nt; sched += gridDim.x) {
-    // XCD-major tile order: schedule index s of XCD s mod 8 maps into the
-    // (s mod 8)-th eighth of the tiles in raster order
-    const int t = (nt % 8 == 0) ? (sched % 8) * (nt / 8) + sched / 8 : sched;
+    // XCD-major tile order (a grid that is a multiple of 8 keeps each
+    // block's schedule indices on its XCD)
+    const int t = static_cast<int>(xcd_major(sched, nt));
     const int x0 = (t % tiles_x) * T::TX, y0 = ((t / tiles_x) % tiles_y) * T::TY;
     const int z0 = (D == 3) ? (t / (tiles_x * tiles_y)) * T::TZ : 0;
     __syncthreads();  // the previous tile's LDS values are no longer read

@@ -18,13 +18,18 @@ def test_interpolated_between_levels():
     assert r["speedup"] == pytest.approx(0.9 * math.sqrt(4.6 / 0.9), rel=1e-12)
 
 
-def test_extrapolated_past_the_rounding_floor():
-    """Below the 512 error the 1024 level (larger error) is ignored and the
-    256 -> 512 segment extended."""
+def test_no_extrapolation_past_the_rounding_floor():
+    """Below the 512 error (the 1024 level, rounding-limited, has a larger
+    one) there is no equal-error point: the curve is not extended."""
     r = cl.equal_error_speedup(LEVELS, ERR, TIME, 5e-6, 2.0)
-    assert r["note"].startswith("extrapolated")
-    assert r["N_star"] == pytest.approx(256 * 2 ** 1.5, rel=1e-12)
-    assert r["speedup"] == pytest.approx(0.9 * (4.6 / 0.9) ** 1.5 / 2.0, rel=1e-12)
+    assert math.isnan(r["N_star"]) and math.isnan(r["speedup"])
+    assert "without extrapolation" in r["note"]
+    # a target below a nearly flat last segment is refused the same way
+    flat = {"256": 4e-5, "512": 1.06e-5, "1024": 1.03e-5}
+    assert math.isnan(cl.equal_error_speedup(LEVELS, flat, TIME, 7.3e-6, 3.0)["N_star"])
+    # interpolation on the last segment is kept
+    r = cl.equal_error_speedup(LEVELS, flat, TIME, 1.05e-5, 3.0)
+    assert r["note"] == "interpolated" and 512 < r["N_star"] < 1024
 
 
 def test_no_equal_error_point():

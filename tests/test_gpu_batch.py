@@ -96,6 +96,29 @@ def test_every_fused_tile_shape_is_bitwise(storage, shape):
     b.close()
 
 
+@pytest.mark.parametrize("per_cu", [0, 1, 3])
+def test_every_fused_grid_is_bitwise(per_cu):
+    """The five-step launches give the single-run states bit for bit with one
+    block per tile (0) and with persistent grids of 1 and 3 blocks per compute
+    unit (each block then walks several tiles); 27 = 5 x 5 + 2 steps."""
+    runs, u0s = _mixed_runs(2)
+    b = B.Batch.create(2, "f32", runs, u0s)
+    b.set_fused_grid(per_cu)
+    print(f"[batch] f32 fused grid {per_cu} per CU: {b.fused_grid()} blocks", flush=True)
+    tiles_k = sum(-(-int(r.n[0]) // b.fused_tile(i)[0]) * -(-int(r.n[1]) // b.fused_tile(i)[1])
+                  for i, r in enumerate(runs))
+    assert b.fused_grid() <= tiles_k if per_cu else b.fused_grid() == tiles_k
+    b.step(27)
+    for r, (run, u0) in enumerate(zip(runs, u0s)):
+        rho, q = b.moments(r)
+        rho1, q1 = _single(2, "f32", run, u0, 27)
+        assert np.array_equal(rho, rho1) and np.array_equal(q, q1), r
+    for bad in (-1, 65):
+        with pytest.raises(lbm.LbmError):
+            b.set_fused_grid(bad)
+    b.close()
+
+
 def test_batch_bitwise_equals_single_runs_3d():
     runs, u0s = _mixed_runs(3)
     b = B.Batch.create(3, "f32", runs, u0s)
@@ -103,6 +126,8 @@ def test_batch_bitwise_equals_single_runs_3d():
     for bad in (2, 5, 3, 0):
         with pytest.raises(lbm.LbmError):
             b.set_fusion(bad)
+    with pytest.raises(lbm.LbmError):
+        b.set_fused_grid(0)
     b.step(37)
     for r, (run, u0) in enumerate(zip(runs, u0s)):
         rho, q = b.moments(r)
