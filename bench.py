@@ -350,6 +350,106 @@ def equal_error_section(n_seeds: int) -> dict:
             "plain": ev["plain"], "closure": ev["closure"], "speedup": ev["speedup_equal_error"]})
 
 
+def _restrict_3d(a: np.ndarray, r: int) -> np.ndarray:
+    """Block averages over r^3 cells of the last three axes (host arrays)."""
+    if r == 1:
+        return a
+    m = a.shape[-1] // r
+    return a.reshape(a.shape[:-3] + (m, r, m, r, m, r)).mean(axis=(-5, -3, -1))
+
+
+def _solenoidal_3d(u: np.ndarray) -> np.ndarray:
+    """Divergence-free part of a periodic field u[3][z][y][x] (spectral
+    Helmholtz projection; the same operator on both sides of a comparison)."""
+    n = u.shape[-1]
+    k = np.fft.fftfreq(n, 1.0 / n)
+    kv = (k[None, None, :], k[None, :, None], k[:, None, None])   # kx, ky, kz
+    k2 = kv[0] ** 2 + kv[1] ** 2 + kv[2] ** 2
+    k2[0, 0, 0] = 1.0
+    uh = [np.fft.fftn(c) for c in u]
+    div = sum(kk * c for kk, c in zip(kv, uh))
+    return np.stack([np.fft.ifftn(c - kk * div / k2).real for kk, c in zip(kv, uh)])
+
+
+def _rel(a: np.ndarray, b: np.ndarray) -> float:
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def precision_3d_variant(levels=(64, 128, 256), fine_n: int = 512, horizon: int = 64, seed: int = 1000,
+                         storages=("f32", "f64", "f16_neq", "f16_dev_r32", "f16_dev")) -> dict:
+    """Storage precision at equal error in 3D: a k^-3 divergence-free field
+    (Mach 0.05 on the coarsest grid, nu = 5e-4, dt = dx^2/8) run for `horizon`
+    steps of the coarsest grid (levels[0]^3, the comparison grid) at each level
+    in each storage, every run started from the block average of the fine
+    initial field; reference = the FP64 run on fine_n^3, block-averaged to the
+    comparison grid.  Errors are relative L2 of u and of its divergence-free
+    part; times are HIP events around each run's steps.  Equal-error speedups
+    against plain FP32 interpolate its error and time between levels."""
+    import torch
+    import inputs
+    from paper_2607_24059_amd import lbm
+    from paper_2607_24059_amd.closure import equal_error_speedup
+    nc, mu, nu = levels[0], 8.0, 5e-4
+    for n in levels:
+        if fine_n % n or n % nc:
+            raise ValueError(f"level {n} must divide {fine_n} and be a multiple of {nc}")
+    u0f = inputs.random_field_3d(fine_n, seed, umax=0.05 / (2 * math.pi / nc))
+    starts = {n: _restrict_3d(u0f, fine_n // n) for n in levels}
+
+    def run(n, storage, u0):
+        dx = 2 * math.pi / n
+        eng = lbm.Engine.create(lbm.make_params(3, (n, n, n), dx, dx * dx / mu, nu, storage=storage), u0)
+        steps = horizon * (n // nc) ** 2
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(eng.stream)
+        eng.step(steps)
+        e1.record(eng.stream)
+        torch.cuda.synchronize()
+        rho, q = eng.moments()
+        fuse = eng.fusion()
+        eng.close()
+        r = n // nc
+        u = _restrict_3d(q, r) / _restrict_3d(rho, r)[None]
+        return u, e0.elapsed_time(e1), steps, fuse
+
+    log(f"[precision 3d] FP64 reference {fine_n}^3, {horizon * (fine_n // nc) ** 2} steps")
+    ref, t_ref, _, _ = run(fine_n, "f64", u0f)
+    del u0f
+    ref_sol = _solenoidal_3d(ref)
+    err = {st: {"u": {}, "u_sol": {}} for st in storages}
+    tim = {st: {} for st in storages}
+    fuse_of = {}
+    for st in storages:
+        for n in levels:
+            u, ms, steps, fuse = run(n, st, starts[n])
+            err[st]["u"][str(n)] = _rel(u, ref)
+            err[st]["u_sol"][str(n)] = _rel(_solenoidal_3d(u), ref_sol)
+            tim[st][str(n)] = ms
+            fuse_of[st] = fuse
+            log(f"[precision 3d] {st} {n}^3: u {err[st]['u'][str(n)]:.3e} u_sol {err[st]['u_sol'][str(n)]:.3e} "
+                f"{ms:.1f} ms ({n ** 3 * steps / (ms * 1e-3) / 1e9:.1f} GLUPS)")
+    speed = {}
+    for st in storages:
+        if st == "f32":
+            continue
+        speed[st] = {}
+        for metric in ("u_sol", "u"):
+            speed[st][metric] = {}
+            for n in levels:
+                k = str(n)
+                sp = equal_error_speedup(levels, err["f32"][metric], tim["f32"], err[st][metric][k], tim[st][k])
+                sp["speedup_same_resolution"] = tim["f32"][k] / tim[st][k]
+                sp["error_ratio_same_resolution"] = err[st][metric][k] / err["f32"][metric][k]
+                speed[st][metric][k] = {a: (None if isinstance(b, float) and math.isnan(b) else b)
+                                        for a, b in sp.items()}
+    return {"workload": f"3D k^-3 field, nu={nu}, Mach 0.05 on {nc}^3, dt = dx^2/{mu:g}, {horizon} steps of "
+                        f"the {nc}^3 grid, reference FP64 {fine_n}^3 block-averaged, seed {seed}",
+            "reference_ms": t_ref, "steps_per_launch": fuse_of, "errors": err, "time_ms": tim,
+            "speedup_vs_f32": speed}
+
+
 def moments_variant(dim: int, n: int, steps: int, probe: float) -> dict:
     """The relaxation scheme (omega_rho = omega_q = 1) on the same k^-3 field,
     in moment-only storage: (1 + dim) FP32 planes, 24 B (2D) / 32 B (3D) per
@@ -583,6 +683,7 @@ ONLY = {
     "moments_3d": lambda a: moments_variant(3, 256, a.variant_steps, copy_probe_gbs()),
     "sweep": lambda a: sweep_variant(),
     "batch_f32": lambda a: batch_variant("f32", 1000, copy_probe_gbs()),
+    "precision_3d": lambda a: precision_3d_variant(),
     "batch_f16_dev_r32": lambda a: batch_variant("f16_dev_r32", 1000, copy_probe_gbs()),
 }
 

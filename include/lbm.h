@@ -144,20 +144,24 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const 
                     void* workspace, size_t ws_bytes, void* hip_stream);
 
 /* Advance nsteps >= 0 time steps (relaxation then transport, Section 2).
- * Each launch fuses relaxation and transport.  In 2D one launch advances
- * several steps (lbm_set_fusion): each tile and a border as wide as the
+ * Each launch fuses relaxation and transport.  One launch may advance
+ * several steps (lbm_set_fusion): in 2D each tile and a border as wide as the
  * steps still to come are advanced on chip, the border shrinking by one cell
- * per step, and only the tile's final state is written back.  A remainder
- * shorter than the fusion depth runs as two-step and single-step launches.
- * The result is bit-identical for any fusion setting.  Asynchronous. */
+ * per step; in 3D a column tile marches along z with one plane per step in
+ * flight.  Only the final state is written back.  A remainder shorter than
+ * the fusion depth runs as two-step and single-step launches.  The result is
+ * bit-identical for any fusion setting.  Asynchronous. */
 lbm_status lbm_step(lbm_ctx* ctx, int64_t nsteps);
 
 /* Time steps per launch, 1 .. 6.  In 2D, 2 .. 6 in any storage but LBM_F64
  * (3 .. 6 only while a plane holds at most 2^32 bytes, i.e. 2^30 FP32 cells);
- * in 3D, 2 and 3 for LBM_F32 and LBM_F32_RAW (kernels that march along z);
- * channel boundaries allow 1 only.  LBM_EINVAL otherwise.  Default from 2^20
- * cells on: 4 for LBM_F32_MOMENTS in 2D, 5 for the other 2D storages, 3 for
- * the 3D FP32 storages; else 2 where available, 1 otherwise. */
+ * in 3D, 2 and 3 for the population storages LBM_F32, LBM_F32_RAW and the
+ * four 16-bit deviation storages (kernels that march along z); channel
+ * boundaries allow 1 only.  LBM_EINVAL otherwise.  Default in 2D: from 2^20
+ * cells on 4 for LBM_F32_MOMENTS and 5 for the other storages, below that 2
+ * where available, else 1.  Default in 3D: the largest of 3 and 2 whose launch
+ * has at least 128 blocks (one per 64 x 6 or 64 x 8 column tile and 32-plane
+ * segment; 128^3 runs three steps per launch, 64^3 one), else 1. */
 lbm_status lbm_set_fusion(lbm_ctx* ctx, int32_t steps_per_launch);
 
 /* The current number of time steps per launch (0 for a NULL context). */

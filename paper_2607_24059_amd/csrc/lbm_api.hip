@@ -178,6 +178,29 @@ static bool multi_step_fits(const lbm_ctx* c) {
 // 132.9 at 4), the moment-only storage at 4.
 static int default_depth(int storage) { return storage == LBM_F32_MOMENTS ? 4 : 5; }
 
+// Fewest blocks a 3D z-marching launch needs to be the default: those kernels
+// take one block per column tile and z segment, so small grids leave most of
+// the 256 compute units idle (64^3 FP32: 5.0 GLUPS at two and three steps per
+// launch in 16 and 22 blocks; 128^3 at three steps, 176 blocks: 40 GLUPS).
+constexpr int64_t kMinFusedBlocks3d = 128;
+
+// Steps per launch when a context is created.  2D: the multi-step kernels from
+// 1024^2 cells on; smaller grids are launch-bound and keep the two-step
+// kernel's small tiles.  3D: the deepest z-marching kernel whose launch has
+// kMinFusedBlocks3d blocks, else one step per launch.
+static int default_fusion(const lbm_ctx* c) {
+  const lbm::Ops* o = c->ops;
+  if (c->p.dim == 3) {
+    for (int d = std::min(3, o->max_fuse); d >= 2; --d) {
+      const bool has = d >= 3 ? multi_step_fits(c) : o->step2 != nullptr;
+      if (has && o->launch_blocks(c->g, d) >= kMinFusedBlocks3d) return d;
+    }
+    return 1;
+  }
+  if (multi_step_fits(c) && c->g.cells >= (int64_t(1) << 20)) return std::min(default_depth(c->p.storage), o->max_fuse);
+  return o->step2 ? 2 : 1;
+}
+
 extern "C" {
 
 lbm_status lbm_check_params(const lbm_params* p, double* mu, double* alpha_q, uint32_t* flags) {
@@ -232,11 +255,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const 
   c->steps = 0;
   c->static_scratch = nullptr;
   default_block(g, &c->bx, &c->by);
-  // deeper fusion from 1024^2 cells on; smaller grids are launch-bound and
-  // keep the two-step kernel's small tiles
-  c->fuse = multi_step_fits(c) && g.cells >= (int64_t(1) << 20) ? std::min(default_depth(p->storage), c->ops->max_fuse)
-            : c->ops->step2                                        ? 2
-                                                                   : 1;
+  c->fuse = default_fusion(c);
 
   // stage u0 (and rho0) as FP64 in the idle buffer, then build the equilibrium
   double* su = reinterpret_cast<double*>(staging(c));

@@ -453,25 +453,46 @@ __device__ __forceinline__ void step_cell_neq(const float* __restrict__ sr, cons
 // alone and a step is the stencil
 //   W_i(t+1, x) = f^eq_{i,rest}(W(t, x)) + sum_moving f^eq_{i,l}(W(t, x - c_l))
 // (the relaxation scheme of Section 2; in deviation form, since the reference
-// equilibria of one set sum to the same constant in every cell).  The
-// arithmetic is that of the equilibrium routine, one moving entry at a time.
+// equilibria of one set sum to the same constant in every cell).
 // ----------------------------------------------------------------------------
 template <int D, typename WAt>
 __device__ __forceinline__ void step_moments(WAt w_at, const Coef& k, float (&out)[D + 1]) {
-  float W[D + 1];
+  // Every moving entry of set i at an upwind neighbour is base + flux or
+  // base - flux: the bases (a W_i of the neighbour) are summed once over the
+  // 2D neighbours, and the fluxes c F_ij once per axis j as the difference of
+  // the neighbours behind (x - e_j, entry + flux) and ahead (x + e_j, entry
+  // - flux).  F_0j = W_{1+j}; F_ij = (W_i / rho) W_{1+j} (+ W_0 for the
+  // pressure, i - 1 = j), with 1 / rho the hardware reciprocal of the split
+  // storage's equilibria.
+  float sum_w[D + 1], sum_f[D + 1];
 #pragma unroll
-  for (int i = 0; i < D + 1; ++i) {
-    W[i] = w_at(i, -1);
-    out[i] = W[i] - ((i == 0) ? k.d2a_rho : k.d2a_q) * W[i];
+  for (int j = 0; j < D; ++j) {
+    float Fb[D + 1], Fa[D + 1];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int m = 2 * j + side;
+      float Wn[D + 1];
+#pragma unroll
+      for (int i = 0; i < D + 1; ++i) Wn[i] = w_at(i, m);
+      const float inv = recip_neq(Wn[0] + k.ref);
+      float (&F)[D + 1] = side == 0 ? Fb : Fa;
+      F[0] = Wn[1 + j];
+#pragma unroll
+      for (int i = 1; i < D + 1; ++i) {
+        F[i] = (Wn[i] * inv) * Wn[1 + j];
+        if (i - 1 == j) F[i] = F[i] + Wn[0];
+      }
+#pragma unroll
+      for (int i = 0; i < D + 1; ++i) sum_w[i] = (m == 0) ? Wn[i] : sum_w[i] + Wn[i];
+    }
+#pragma unroll
+    for (int i = 0; i < D + 1; ++i) sum_f[i] = (j == 0) ? Fb[i] - Fa[i] : sum_f[i] + (Fb[i] - Fa[i]);
   }
 #pragma unroll
-  for (int m = 0; m < 2 * D; ++m) {
-    float Wn[D + 1];
-#pragma unroll
-    for (int i = 0; i < D + 1; ++i) Wn[i] = w_at(i, m);
-    const float inv = recip_neq(Wn[0] + k.ref);  // hardware reciprocal, as in the split storage
-#pragma unroll
-    for (int i = 0; i < D + 1; ++i) out[i] = out[i] + eq_moving<D, float>(Wn, inv, k, i, m);
+  for (int i = 0; i < D + 1; ++i) {
+    const float w = w_at(i, -1);
+    const float rest = w - ((i == 0) ? k.d2a_rho : k.d2a_q) * w;
+    out[i] = (rest + ((i == 0) ? k.a_rho : k.a_q) * sum_w[i]) + k.c * sum_f[i];
   }
 }
 

@@ -58,6 +58,10 @@ struct Ops {
   // K = 3 .. max_fuse steps in one launch (2D population storages, 3D FP32; nullptr otherwise)
   hipError_t (*stepK)(const Geometry&, const RunCoef&, int K, const void* src, void* dst, hipStream_t s);
   int max_fuse;  // most steps per launch (1 .. kMaxFusion)
+  // blocks of the 3D launch that advances `depth` steps (the z-marching
+  // kernels take one block per column tile and z segment); INT64_MAX where
+  // the grid does not depend on it (2D, and the one-step kernel)
+  int64_t (*launch_blocks)(const Geometry&, int depth);
 };
 
 // Most time steps one launch may advance.

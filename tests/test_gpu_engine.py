@@ -414,7 +414,7 @@ def test_fusion_settings_and_defaults():
     eng.close()
     p3 = scheme.params_for_grid(3, 8, 0.01)
     e3 = _engine(p3, inputs.abc_flow(8, 0.1, 0.1, 0.1))
-    assert e3.fusion() == 2
+    assert e3.fusion() == 1                      # 3D: too few column tiles to fuse
     e3.set_fusion(3)
     with pytest.raises(lbm.LbmError):
         e3.set_fusion(4)
@@ -446,9 +446,20 @@ def test_multi_step_fusion_3d_is_bitwise(storage, shape, steps):
 
 
 def test_two_step_fusion_3d_defaults_and_limits():
+    """3D defaults: the z-marching kernels only where their launch has at
+    least 128 blocks (64^3: 22 and 16 blocks, one step per launch; 128^3: 176
+    blocks at three steps per launch)."""
+    for n, expect in ((64, 1), (128, 3)):
+        pn = scheme.params_for_grid(3, n, 0.01)
+        for storage in ("f32", "f16_dev_r32"):
+            e = _engine(pn, np.zeros((3, n, n, n)), storage=storage)
+            assert e.fusion() == expect, (n, storage)
+            e.close()
     p = scheme.params_for_grid(3, 8, 0.01)
     u = inputs.abc_flow(8, 0.1, 0.1, 0.1)
     eng = _engine(p, u)
+    assert eng.fusion() == 1
+    eng.set_fusion(2)
     assert eng.fusion() == 2
     for bad in (4, 5, 7):
         with pytest.raises(lbm.LbmError):
@@ -462,7 +473,8 @@ def test_two_step_fusion_3d_defaults_and_limits():
         e.close()
     for storage in ("f16_dev", "f16_dev_r32"):
         e = _engine(p, u, storage=storage)
-        assert e.fusion() == 2
+        assert e.fusion() == 1
+        e.set_fusion(2)
         e.set_fusion(3)
         with pytest.raises(lbm.LbmError):
             e.set_fusion(4)
