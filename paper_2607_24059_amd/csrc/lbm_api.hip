@@ -75,6 +75,15 @@ size_t extra_staging_bytes(const Geometry& g) {
 
 lbm_status dev(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EDEVICE; }
 
+// compute units of the current device (256 if the query fails)
+int device_cus() {
+  int d = 0, cus = 0;
+  if (hipGetDevice(&d) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, d) != hipSuccess ||
+      cus <= 0)
+    return 256;
+  return cus;
+}
+
 // Power-of-two scales of the split storage, one per set, from the run's
 // parameters alone (so that any state loaded later, by lbm_load_state or
 // lbm_set_equilibrium_device, is covered): s_i = 2^13 / M_i rounded down to a
@@ -235,6 +244,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const 
   c->alpha_q = aq;
   c->flags = flags;
   c->g = g;
+  if (p->dim == 3) c->g.zseg3 = lbm::zseg3_for(g, device_cus());
   c->ops = lbm::ops_for(p->dim, p->storage);
   c->coef = RunCoef{p->dx, mu, p->alpha_rho, aq, p->omega_rho, p->omega_q, p->rho_ref};
   if (p->storage == LBM_F16_NEQ) neq_scales(p, mu, aq, c->coef.neq_s);

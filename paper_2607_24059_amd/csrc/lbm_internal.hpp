@@ -36,6 +36,7 @@ struct Geometry {
   size_t move_elem;     // bytes per moving-plane element
   size_t rest_bytes;    // bytes of the rest-plane region (256-aligned)
   size_t buf_bytes;     // bytes of one full state buffer (256-aligned)
+  int32_t zseg3 = 32;   // planes per block of the 3D three-step launch (zseg3_for)
 };
 
 // Launchers of one (dimension, storage) instantiation.  Every launcher
@@ -79,6 +80,10 @@ bool storage_elems(int storage, size_t* rest_elem, size_t* move_elem);
 
 // Buffer geometry of one run (plane stride, region sizes) for a storage mode.
 Geometry make_geometry(int dim, int storage, const int64_t n[3]);
+
+// Planes per block of the 3D three-step launch on a device with `cus`
+// compute units (lbm_kernels.hip).
+int32_t zseg3_for(const Geometry& g, int cus);
 
 // Whether a storage mode stores deviations from the reference equilibrium.
 bool storage_is_deviation(int storage);

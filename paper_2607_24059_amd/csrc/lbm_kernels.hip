@@ -8,6 +8,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 #include <type_traits>
 
 #include "lbm_device.hpp"
@@ -397,12 +399,13 @@ __global__ __launch_bounds__(NT) void k_step2_3d(const TR* __restrict__ sr, cons
 // the same collide as the single step, so the result equals three single
 // steps bit for bit.  Waves r < EY own the 64 columns x0 .. x0 + 63 of
 // extended row r (whole 128-byte lines per access); the last wave owns the
-// four border columns x0 - 2, x0 - 1, x0 + 64, x0 + 65 of every row.
+// four border columns x0 - 2, x0 - 1, x0 + 64, x0 + 65 of every row.  A block
+// walks zs planes (chosen per grid by zseg3_for).
 // ----------------------------------------------------------------------------
-template <typename TR, typename TM, int TY, int ZS>
+template <typename TR, typename TM, int TY>
 __global__ __launch_bounds__(64 * (TY + 5)) void k_step3_3d(const TR* __restrict__ sr, const TM* __restrict__ sm,
                                                             TR* __restrict__ dr, TM* __restrict__ dm, int nx, int ny,
-                                                            int nz, int64_t stride, Coef k) {
+                                                            int nz, int zs, int64_t stride, Coef k) {
   constexpr int TX = 64, H = 2, EX = TX + 2 * H, EY = TY + 2 * H, EN1 = EX * EY;
   constexpr int RX2 = TX + 2, RY2 = TY + 2, EN2 = RX2 * RY2;  // stage-2 region
   static_assert(4 * EY <= 64, "border columns of every row fit one wave");
@@ -428,17 +431,17 @@ __global__ __launch_bounds__(64 * (TY + 5)) void k_step3_3d(const TR* __restrict
   const int e1 = ey * EX + ex;
   const int e2 = in2 ? (ey - 1) * RX2 + (ex - 1) : 0;
   const int tx_n = (nx + TX - 1) / TX, ty_n = (ny + TY - 1) / TY;
-  const int nt = tx_n * ty_n * ((nz + ZS - 1) / ZS);
+  const int nt = tx_n * ty_n * ((nz + zs - 1) / zs);
   const int b = blockIdx.x;
   const int tt = static_cast<int>(xcd_major(b, nt));
-  const int x0 = (tt % tx_n) * TX, y0 = ((tt / tx_n) % ty_n) * TY, z0 = (tt / (tx_n * ty_n)) * ZS;
+  const int x0 = (tt % tx_n) * TX, y0 = ((tt / tx_n) % ty_n) * TY, z0 = (tt / (tx_n * ty_n)) * zs;
   int x = x0 - H + ex, y = y0 - H + ey;
   x = wrap_coord(x, nx);  // the border may wrap (several times on tiny grids)
   y = wrap_coord(y, ny);
   const bool out = in3 && x0 + ex - H < nx && y0 + ey - H < ny;
   const int64_t plane = static_cast<int64_t>(nx) * ny;
   const int64_t cxy = static_cast<int64_t>(y) * nx + x;
-  const int zend = min(z0 + ZS, nz);
+  const int zend = min(z0 + zs, nz);
   // stage histories: rest and +z of the previous plane, +z of the one before
   float r1p[4], z1p[4], z1pp[4], r2p[4], z2p[4], z2pp[4];
 #pragma unroll
@@ -948,6 +951,37 @@ __global__ __launch_bounds__(256) void k_copy(const float4* __restrict__ src, fl
 // ----------------------------------------------------------------------------
 // launchers
 // ----------------------------------------------------------------------------
+// 3D three-step launch: 64 x k3KY column tiles on 64 (k3KY + 5) threads.
+constexpr int k3KY = 6;
+
+}  // namespace
+
+// Planes per block of the 3D three-step launch.  One block fills a compute
+// unit (its LDS, or its registers in the 16-bit storages), so the launch runs
+// in rounds of `cus` blocks and a partial last round leaves the rest of the
+// chip idle; a block also recomputes four planes of its first stage and two
+// of its second at the ends of its segment.  The segment length minimises
+// rounds x the work of one block (256^3: 37 planes, 1204 blocks in 5 rounds,
+// against 32 planes, 1376 blocks in 6 rounds).
+int32_t zseg3_for(const Geometry& g, int cus) {
+  const int64_t txy = static_cast<int64_t>((g.nx + 63) / 64) * ((g.ny + k3KY - 1) / k3KY);
+  const int64_t e1 = 68 * (k3KY + 4), e2 = 66 * (k3KY + 2), e3 = 64 * k3KY;  // cells per plane of each stage
+  int32_t best = 32;
+  double best_cost = -1.0;
+  for (int32_t zs = 8; zs <= std::max<int32_t>(8, g.nz); ++zs) {
+    const int64_t blocks = txy * ((g.nz + zs - 1) / zs);
+    const int64_t rounds = (blocks + cus - 1) / std::max(cus, 1);
+    const double cost = static_cast<double>(rounds) * static_cast<double>((zs + 4) * e1 + (zs + 2) * e2 + zs * e3);
+    if (best_cost < 0.0 || cost < best_cost) {
+      best_cost = cost;
+      best = zs;
+    }
+  }
+  return best;
+}
+
+namespace {
+
 template <int D, typename TR, typename TM, bool DEV>
 struct Impl {
   static hipError_t init(const Geometry& g, const RunCoef& r, const double* u0, const double* rho0,
@@ -1059,8 +1093,6 @@ struct Impl {
   // most steps per launch: 6 in 2D, 3 for the 3D FP32 storages, else the
   // two-step kernel's 2 or one
   static constexpr int kMaxFuse = kHasStepK ? (D == 2 ? kMaxFusion : 3) : kHasStep2 ? 2 : 1;
-  // 3D, three steps: 64 x 6 columns on 704 threads, 32-plane segments
-  static constexpr int kT3KY = 6, kT3KZ = 32;
   static constexpr int kStepKThreads = 512;
 
   static constexpr bool kRestInRegisters = sizeof(TR) == 4 && sizeof(TM) == 4;
@@ -1126,11 +1158,9 @@ struct Impl {
       auto a = planes_of<TR, TM>(const_cast<void*>(src), g.rest_bytes);
       auto b = planes_of<TR, TM>(dst, g.rest_bytes);
       const Coef k = make_coef<float>(r, D, DEV);
-      const int64_t tiles = static_cast<int64_t>((g.nx + 63) / 64) * ((g.ny + kT3KY - 1) / kT3KY) *
-                            ((g.nz + kT3KZ - 1) / kT3KZ);
-      hipLaunchKernelGGL((k_step3_3d<TR, TM, kT3KY, kT3KZ>), dim3(static_cast<uint32_t>(tiles)),
-                         dim3(64 * (kT3KY + 5)), 0, s, a.rest, a.move, b.rest, b.move, g.nx, g.ny, g.nz, g.stride,
-                         k);
+      const int64_t tiles = launch_blocks(g, 3);
+      hipLaunchKernelGGL((k_step3_3d<TR, TM, k3KY>), dim3(static_cast<uint32_t>(tiles)), dim3(64 * (k3KY + 5)), 0, s,
+                         a.rest, a.move, b.rest, b.move, g.nx, g.ny, g.nz, g.zseg3, g.stride, k);
       return hipGetLastError();
     } else {
       switch (K) {
@@ -1190,7 +1220,7 @@ struct Impl {
   static int64_t launch_blocks(const Geometry& g, int depth) {
     if constexpr (D == 3) {
       if (depth >= 3 && kHasStepK)
-        return static_cast<int64_t>((g.nx + 63) / 64) * ((g.ny + kT3KY - 1) / kT3KY) * ((g.nz + kT3KZ - 1) / kT3KZ);
+        return static_cast<int64_t>((g.nx + 63) / 64) * ((g.ny + k3KY - 1) / k3KY) * ((g.nz + g.zseg3 - 1) / g.zseg3);
       if (depth == 2 && kHasStep2)
         return static_cast<int64_t>((g.nx + kT3X - 1) / kT3X) * ((g.ny + kT3Y - 1) / kT3Y) *
                ((g.nz + kT3Z - 1) / kT3Z);
