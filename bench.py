@@ -330,7 +330,8 @@ def equal_error_section(n_seeds: int) -> dict:
     reference, on the closure workload: k^-3 fields (held-out seeds 1000...),
     nu = 5e-4, coarse 256^2, reference = the plain scheme at 2048^2 in FP64
     storage restricted to 256^2, 256 coarse steps.  Plain levels 256^2, 512^2,
-    1024^2, 2048^2 in FP32, FP64, split FP16 and FP16 + FP32-rest storage; the
+    1024^2, 2048^2 in FP32, FP64, split FP16, FP16 + FP32-rest and all-FP16
+    deviation storage; the
     corrected 256^2 run uses the committed trained network.  Errors: relative
     L2 of u and of its divergence-free part, each with its own equal-error
     speedups.  Times: HIP events around each run's steps."""
@@ -341,7 +342,7 @@ def equal_error_section(n_seeds: int) -> dict:
     cfg.test_seeds = list(range(1000, 1000 + n_seeds))
     net = cnn.Net(params=params)
     ev = closure.evaluate(cfg, net, meta["scales"], log=log, levels=(256, 512, 1024, 2048),
-                          plain_storages=("f32", "f64", "f16_neq", "f16_dev_r32"))
+                          plain_storages=("f32", "f64", "f16_neq", "f16_dev_r32", "f16_dev"))
     return _finite({"workload": f"k^-3 field, nu={cfg.nu}, coarse {cfg.coarse_n}^2, reference FP64 "
                         f"{cfg.fine_n}^2 restricted, {cfg.horizon} coarse steps, "
                         f"seeds {cfg.test_seeds[0]}..{cfg.test_seeds[-1]}",
