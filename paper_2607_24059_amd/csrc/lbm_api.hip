@@ -172,13 +172,14 @@ void default_block(const Geometry& g, int* bx, int* by) {
 
 }  // namespace
 
-// Whether a context may run the K >= 3 kernels: the 2D tiles address a plane
-// with 32-bit byte offsets (fused_offsets_fit), so planes of more than 2^32
-// bytes take the two-step kernel.
+// Whether a context may run the K >= 3 kernels: the 2D tiles and the 3D
+// three-step kernel address a plane (an x-y plane in 3D) with 32-bit byte
+// offsets (fused_offsets_fit), so planes of more than 2^32 bytes take the
+// two-step kernel.
 static bool multi_step_fits(const lbm_ctx* c) {
-  return c->ops->stepK && (c->p.dim != 2 || lbm::fused_offsets_fit(c->g.cells, c->g.move_elem > c->g.rest_elem
-                                                                                    ? c->g.move_elem
-                                                                                    : c->g.rest_elem));
+  const int64_t plane = c->p.dim == 2 ? c->g.cells : static_cast<int64_t>(c->g.nx) * c->g.ny;
+  return c->ops->stepK &&
+         lbm::fused_offsets_fit(plane, c->g.move_elem > c->g.rest_elem ? c->g.move_elem : c->g.rest_elem);
 }
 
 // Default steps per launch of the multi-step kernels, from sweeps at 4096^2 /

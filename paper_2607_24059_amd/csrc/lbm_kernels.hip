@@ -383,6 +383,28 @@ __global__ __launch_bounds__(NT) void k_step2_3d(const TR* __restrict__ sr, cons
   }
 }
 
+// Pull gather of a 3D cell for the z-marching kernels: the rest populations
+// at in-plane index c of plane offset zc, the in-plane moving ones from the
+// upwind indices nb (x - 1, x + 1, y - 1, y + 1, wrapped), +z from the plane
+// below (offset zm) and -z from the plane above (zp).  Plane offsets are
+// common to the block and element indices are 32-bit, so a load is a block
+// base plus a lane offset (planes of at most 2^30 cells); the loaded
+// elements are those of gather_cell.
+template <typename TR, typename TM>
+__device__ __forceinline__ void gather_cell3_o32(const TR* __restrict__ sr, const TM* __restrict__ sm,
+                                                 int64_t stride, int64_t zc, int64_t zm, int64_t zp, uint32_t c,
+                                                 const uint32_t (&nb)[4], float (&g)[4][7]) {
+  constexpr uint32_t BR = sizeof(TR), BM = sizeof(TM);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    g[i][0] = load_f32(at_byte(sr + i * stride + zc, c * BR));
+#pragma unroll
+    for (int m = 0; m < 4; ++m) g[i][1 + m] = load_f32(at_byte(sm + (i * 6 + m) * stride + zc, nb[m] * BM));
+    g[i][5] = load_f32(at_byte(sm + (i * 6 + 4) * stride + zm, c * BM));
+    g[i][6] = load_f32(at_byte(sm + (i * 6 + 5) * stride + zp, c * BM));
+  }
+}
+
 // ----------------------------------------------------------------------------
 // three steps per launch in 3D (4-byte planes), marching along z.  The tile
 // is TX x TY columns; stage 1 runs over the tile plus a two-cell x/y border
@@ -440,7 +462,19 @@ __global__ __launch_bounds__(64 * (TY + 5)) void k_step3_3d(const TR* __restrict
   y = wrap_coord(y, ny);
   const bool out = in3 && x0 + ex - H < nx && y0 + ey - H < ny;
   const int64_t plane = static_cast<int64_t>(nx) * ny;
-  const int64_t cxy = static_cast<int64_t>(y) * nx + x;
+  // the column's in-plane index and its four in-plane upwind indices
+  const uint32_t c32 = static_cast<uint32_t>(y) * static_cast<uint32_t>(nx) + static_cast<uint32_t>(x);
+  const uint32_t row = static_cast<uint32_t>(nx), last = static_cast<uint32_t>(ny - 1) * row;
+  uint32_t nb[4];
+  nb[0] = (x == 0) ? c32 + (row - 1) : c32 - 1;       // +x from x - 1
+  nb[1] = (x == nx - 1) ? c32 - (row - 1) : c32 + 1;  // -x from x + 1
+  nb[2] = (y == 0) ? c32 + last : c32 - row;          // +y from y - 1
+  nb[3] = (y == ny - 1) ? c32 - last : c32 + row;     // -y from y + 1
+  // gather of wrapped plane pz (its neighbours wrap too)
+  auto gather = [&](int pz, float (&gg)[4][7]) {
+    const int zb = (pz == 0) ? nz - 1 : pz - 1, za = (pz == nz - 1) ? 0 : pz + 1;
+    gather_cell3_o32<TR, TM>(sr, sm, stride, pz * plane, zb * plane, za * plane, c32, nb, gg);
+  };
   const int zend = min(z0 + zs, nz);
   // stage histories: rest and +z of the previous plane, +z of the one before
   float r1p[4], z1p[4], z1pp[4], r2p[4], z2p[4], z2pp[4];
@@ -450,10 +484,9 @@ __global__ __launch_bounds__(64 * (TY + 5)) void k_step3_3d(const TR* __restrict
   // work (45.6 against 45.0 GLUPS at 256^3); loads stay in flight across the
   // barrier, which waits on LDS only
   float gn[4][7];
-  if (col) {
-    const int pz = wrap_coord(z0 - 2, nz);
-    gather_cell<3, TR, TM>(sr, sm, x, y, pz, nx, ny, nz, stride, static_cast<int64_t>(pz) * plane + cxy, gn);
-  }
+  int pzn = wrap_coord(z0 - 2, nz);  // wrapped index of the next plane to gather
+  if (col) gather(pzn, gn);
+  pzn = (pzn + 1 == nz) ? 0 : pzn + 1;
   for (int p = z0 - 2; p <= zend + 1; ++p) {
     const int sl = p & 1;
     float g[4][7];
@@ -461,10 +494,8 @@ __global__ __launch_bounds__(64 * (TY + 5)) void k_step3_3d(const TR* __restrict
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int l = 0; l < 7; ++l) g[i][l] = gn[i][l];
-    if (col && p + 1 <= zend + 1) {
-      const int pz = wrap_coord(p + 1, nz);
-      gather_cell<3, TR, TM>(sr, sm, x, y, pz, nx, ny, nz, stride, static_cast<int64_t>(pz) * plane + cxy, gn);
-    }
+    if (col && p + 1 <= zend + 1) gather(pzn, gn);
+    pzn = (pzn + 1 == nz) ? 0 : pzn + 1;
     // stage 1, plane p, from HBM
     float r1[4], zp1[4], zm1[4];
 #pragma unroll
@@ -530,13 +561,13 @@ __global__ __launch_bounds__(64 * (TY + 5)) void k_step3_3d(const TR* __restrict
           h[i][6] = zm2[i];
         }
         collide<3>(h, k);
-        const int64_t c = static_cast<int64_t>(p - 2) * plane + static_cast<int64_t>(y0 + ey - H) * nx +
-                          (x0 + ex - H);
+        const int64_t zc = static_cast<int64_t>(p - 2) * plane;  // an output column does not wrap: c32 is its index
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          store_stream(dr + i * stride + c, h[i][0]);
+          store_stream(at_byte(dr + i * stride + zc, c32 * static_cast<uint32_t>(sizeof(TR))), h[i][0]);
 #pragma unroll
-          for (int m = 0; m < 6; ++m) store_stream(dm + (i * 6 + m) * stride + c, h[i][1 + m]);
+          for (int m = 0; m < 6; ++m)
+            store_stream(at_byte(dm + (i * 6 + m) * stride + zc, c32 * static_cast<uint32_t>(sizeof(TM))), h[i][1 + m]);
         }
       }
 #pragma unroll
