@@ -151,14 +151,14 @@ constexpr int kShapes = 3;
 template <typename TR, typename TM, int S>
 struct BatchKShape {
   static constexpr bool kRegs = sizeof(TR) == 4 && sizeof(TM) == 4;
-  // 4-byte planes, rest populations in registers: 32x32 on 512 threads (two
-  // blocks per compute unit; on 768 threads, the single-run engine's choice,
-  // the 512-run batch ran 105 against 169 GLUPS), 32x16 on 256 (three blocks
-  // per compute unit), 16x16 on 256 (small runs: more tiles); 16-bit planes:
+  // 4-byte planes, rest populations in registers: 32x32 on 768 threads (the
+  // single-run engine's tile, two blocks per compute unit; the 512-run batch
+  // 178.8 against 170.7 GLUPS on 512 threads), 32x16 on 256 (three blocks per
+  // compute unit), 16x16 on 256 (small runs: more tiles); 16-bit planes:
   // 64x16 on 512, 32x32 on 512, 32x16 on 256.
   static constexpr int TX = kRegs ? (S == 2 ? 16 : 32) : (S == 0 ? 64 : 32);
   static constexpr int TY = kRegs ? (S == 0 ? 32 : 16) : (S == 1 ? 32 : 16);
-  static constexpr int NT = kRegs ? (S == 0 ? 512 : 256) : (S == 2 ? 256 : 512);
+  static constexpr int NT = kRegs ? (S == 0 ? 768 : 256) : (S == 2 ? 256 : 512);
 };
 constexpr int kTKXmin = 16, kTKYmin = 16;  // smallest tile width and height (size the tile list)
 
