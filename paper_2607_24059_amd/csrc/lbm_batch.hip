@@ -155,7 +155,9 @@ struct BatchKShape {
   // single-run engine's tile, two blocks per compute unit; the 512-run batch
   // 178.8 against 170.7 GLUPS on 512 threads), 32x16 on 256 (three blocks per
   // compute unit), 16x16 on 256 (small runs: more tiles); 16-bit planes:
-  // 64x16 on 512, 32x32 on 512, 32x16 on 256.
+  // 64x16 on 512 (on 768 threads, the single-run engine's choice with FP32
+  // rest planes, the 512-run FP16 + FP32 rest batch ran 183.0 against 199.6),
+  // 32x32 on 512, 32x16 on 256.
   static constexpr int TX = kRegs ? (S == 2 ? 16 : 32) : (S == 0 ? 64 : 32);
   static constexpr int TY = kRegs ? (S == 0 ? 32 : 16) : (S == 1 ? 32 : 16);
   static constexpr int NT = kRegs ? (S == 0 ? 768 : 256) : (S == 2 ? 256 : 512);

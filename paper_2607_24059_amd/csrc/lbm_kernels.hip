@@ -1142,7 +1142,11 @@ struct Impl {
   // most steps per launch: 6 in 2D, 3 for the 3D FP32 storages, else the
   // two-step kernel's 2 or one
   static constexpr int kMaxFuse = kHasStepK ? (D == 2 ? kMaxFusion : 3) : kHasStep2 ? 2 : 1;
-  static constexpr int kStepKThreads = 512;
+  // threads of the 16-bit multi-step tile (64x16): 768 where the rest planes
+  // are FP32 (FP16 + FP32 rest 194.8 -> 203.3, BF16 + FP32 rest 191.6 ->
+  // 201.8 GLUPS at 4096^2), 512 for the all-16-bit storages (768 ran BF16 at
+  // 201.4 against 212.8, FP16 equal)
+  static constexpr int kStepKThreads = sizeof(TR) == 4 ? 768 : 512;
 
   static constexpr bool kRestInRegisters = sizeof(TR) == 4 && sizeof(TM) == 4;
   // split FP16 storage: 32x24 tiles on 1024 threads (GLUPS at 4096^2 / 2048^2
