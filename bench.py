@@ -140,7 +140,7 @@ def cpu_baseline(n: int = 4096, steps: int = 10, nu: float = 1e-3) -> dict:
 def headline_kernel(fuse: int) -> str:
     """The step kernel instantiation the 4096^2 FP32 engine launches at `fuse`
     steps per launch (tiles as chosen in the library)."""
-    tile = {3: "32,16,256", 4: "64,16,512", 5: "32,32,768", 6: "32,16,256"}
+    tile = {3: "32,16,256", 4: "64,16,512", 5: "32,32,768", 6: "32,28,768"}
     if fuse >= 3:
         return f"k_stepKr_2d<float,float,{tile[fuse]},{fuse},true>"
     return "k_step2_2d<float,float,256,8,1024>" if fuse == 2 else "k_step<2,float,float>"

@@ -182,11 +182,16 @@ static bool multi_step_fits(const lbm_ctx* c) {
          lbm::fused_offsets_fit(plane, c->g.move_elem > c->g.rest_elem ? c->g.move_elem : c->g.rest_elem);
 }
 
-// Default steps per launch of the multi-step kernels, from sweeps at 4096^2 /
-// 2048^2: the population storages peak at 5 (FP32 with the rest in registers
-// on 32x32 tiles: 159.7 / 136.0 GLUPS, against 143.5 / 135.1 at 6 and 139.3 /
-// 132.9 at 4), the moment-only storage at 4.
-static int default_depth(int storage) { return storage == LBM_F32_MOMENTS ? 4 : 5; }
+// Default steps per launch of the multi-step kernels, from sweeps at 4096^2
+// (2048^2): the FP32 storages peak at 6 (rest in registers on 32x28 tiles of
+// 768 threads: 192.6 GLUPS against 176.3 at 5 on 32x32, 191.5 at 7 and 177.8
+// at 8), the 16-bit and split storages at 5 (FP16 + FP32 rest 202.2 against
+// 191.7 at 6, BF16 210.6 against 183.3, split FP16 129.6 against 78.7), the
+// moment-only storage at 4.
+static int default_depth(int storage) {
+  if (storage == LBM_F32_MOMENTS) return 4;
+  return (storage == LBM_F32 || storage == LBM_F32_RAW) ? 6 : 5;
+}
 
 // Fewest blocks a 3D z-marching launch needs to be the default: those kernels
 // take one block per column tile and z segment, so small grids leave most of

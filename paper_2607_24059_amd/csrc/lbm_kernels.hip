@@ -1184,12 +1184,15 @@ struct Impl {
       // blocks share a CU; 135.5 without the XCD order), against 145.3 / 136.4
       // for 32x16 on 256; on 768 threads (24 waves per CU instead of 16,
       // 60 VGPRs) 177.5 against 172.7 after the relaxation change (640: 115);
-      // K = 4: 64x16 on 512, 139.3 / 132.9 against 125.0 / 122.1; K = 3 and
-      // 6: 32x16 on 256 (102.2 and 143.5 at 4096^2; 32x32 at K = 6 needs 85 KB
-      // per block and ran 108.6)
+      // K = 4: 64x16 on 512, 139.3 / 132.9 against 125.0 / 122.1; K = 3:
+      // 32x16 on 256 (102.2 at 4096^2); K = 6 (the FP32 default): 32x28 on 768
+      // threads, 42x40 extended, 77 KB of LDS, two blocks per CU, 192.6 against 176.3 for
+      // K = 5 in the same session (32x24: 182.2, 32x16 on 256: 152.8, 32x28
+      // on 896 or 1024 threads: 119; K = 7 on 32x24: 191.5, K = 8 on 32x20:
+      // 177.8; 32x32 at K = 6 needs 85 KB per block and ran 108.6)
       constexpr int TX = K == 5 ? 32 : K == 4 ? 64 : 32;
-      constexpr int TY = K == 5 ? 32 : 16;
-      constexpr int NT = K == 5 ? 768 : K == 4 ? 512 : 256;
+      constexpr int TY = K == 5 ? 32 : K == 6 ? 28 : 16;
+      constexpr int NT = K == 5 ? 768 : K == 4 ? 512 : K == 6 ? 768 : 256;
       const int64_t tiles = static_cast<int64_t>((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY);
       hipLaunchKernelGGL((k_stepKr_2d<TR, TM, TX, TY, NT, K, true>), dim3(static_cast<uint32_t>(tiles)), dim3(NT), 0,
                          s, a.rest, a.move, b.rest, b.move, g.nx, g.ny, g.stride, k);
