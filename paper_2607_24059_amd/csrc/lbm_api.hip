@@ -182,15 +182,19 @@ static bool multi_step_fits(const lbm_ctx* c) {
          lbm::fused_offsets_fit(plane, c->g.move_elem > c->g.rest_elem ? c->g.move_elem : c->g.rest_elem);
 }
 
-// Default steps per launch of the multi-step kernels, from sweeps at 4096^2
-// (2048^2): the FP32 storages peak at 6 (rest in registers on 32x28 tiles of
-// 768 threads: 192.6 GLUPS against 176.3 at 5 on 32x32, 191.5 at 7 and 177.8
-// at 8), the 16-bit and split storages at 5 (FP16 + FP32 rest 202.2 against
-// 191.7 at 6, BF16 210.6 against 183.3, split FP16 129.6 against 78.7), the
+// Default steps per launch of the multi-step kernels, from sweeps at 4096^2:
+// the FP32 storages peak at 6 (rest in registers on 32x28 tiles of 768
+// threads: 192.6 GLUPS against 176.3 at 5 on 32x32, 191.5 at 7 and 177.8 at
+// 8), the 16-bit storages with FP32 rest planes at 6 too (64x20 tiles: FP16 +
+// FP32 rest 210.0 against 203.4 at 5), the all-16-bit and split storages at 5
+// (BF16 214.5 against 210.7 at 6, split FP16 129.6 against 78.7), the
 // moment-only storage at 4.
 static int default_depth(int storage) {
-  if (storage == LBM_F32_MOMENTS) return 4;
-  return (storage == LBM_F32 || storage == LBM_F32_RAW) ? 6 : 5;
+  switch (storage) {
+    case LBM_F32_MOMENTS: return 4;
+    case LBM_F32: case LBM_F32_RAW: case LBM_F16_DEV_R32: case LBM_BF16_DEV_R32: return 6;
+    default: return 5;
+  }
 }
 
 // Fewest blocks a 3D z-marching launch needs to be the default: those kernels

@@ -1197,7 +1197,11 @@ struct Impl {
       hipLaunchKernelGGL((k_stepKr_2d<TR, TM, TX, TY, NT, K, true>), dim3(static_cast<uint32_t>(tiles)), dim3(NT), 0,
                          s, a.rest, a.move, b.rest, b.move, g.nx, g.ny, g.stride, k);
     } else {
-      constexpr int TX = 64, TY = 16;
+      // 64x16, or 64x20 at six steps with FP32 rest planes (80 KB of LDS, two
+      // blocks per CU: FP16 + FP32 rest 210.0 GLUPS against 203.4 at five
+      // steps on 64x16; 32x28 at six: 190.1; the all-16-bit storages stay at
+      // five, BF16 214.5 against 210.7 at six on 64x20)
+      constexpr int TX = 64, TY = (K == 6 && sizeof(TR) == 4) ? 20 : 16;
       const int64_t tiles = static_cast<int64_t>((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY);
       hipLaunchKernelGGL((k_stepK_2d<TR, TM, TX, TY, kStepKThreads, K, true>), dim3(static_cast<uint32_t>(tiles)),
                          dim3(kStepKThreads), 0, s, a.rest, a.move, b.rest, b.move, g.nx, g.ny, g.stride, k);
