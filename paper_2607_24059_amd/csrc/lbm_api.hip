@@ -199,8 +199,9 @@ static int default_depth(int storage) {
 
 // Fewest blocks a 3D z-marching launch needs to be the default: those kernels
 // take one block per column tile and z segment, so small grids leave most of
-// the 256 compute units idle (64^3 FP32: 5.0 GLUPS at two and three steps per
-// launch in 16 and 22 blocks; 128^3 at three steps, 176 blocks: 40 GLUPS).
+// the 256 compute units idle (64^3 FP32: 5.0 GLUPS with two steps per launch
+// in 16 blocks, against 19.7 with one step per launch; 128^3 at three steps,
+// 220 blocks: 46 GLUPS).
 constexpr int64_t kMinFusedBlocks3d = 128;
 
 // Steps per launch when a context is created.  2D: the multi-step kernels from
