@@ -377,7 +377,7 @@ def _rel(a: np.ndarray, b: np.ndarray) -> float:
 
 
 def precision_3d_variant(levels=(64, 128, 256), fine_n: int = 512, horizon: int = 64, seed: int = 1000,
-                         storages=("f32", "f64", "f16_neq", "f16_dev_r32", "f16_dev")) -> dict:
+                         storages=("f32", "f64", "f16_neq", "f16_dev_r32", "bf16_dev_r32", "f16_dev")) -> dict:
     """Storage precision at equal error in 3D: a k^-3 divergence-free field
     (Mach 0.05 on the coarsest grid, nu = 5e-4, dt = dx^2/8) run for `horizon`
     steps of the coarsest grid (levels[0]^3, the comparison grid) at each level

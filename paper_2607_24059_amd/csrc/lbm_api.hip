@@ -247,6 +247,8 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const 
   if (ws_bytes < need) return LBM_ENOMEM;
   if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0) return LBM_EINVAL;
   const Geometry g = geometry(p);
+  const Ops* ops = lbm::ops_for(p->dim, p->storage);
+  if (!ops) return LBM_EINVAL;
 
   lbm_ctx* c = new (std::nothrow) lbm_ctx;
   if (!c) return LBM_ENOMEM;
@@ -255,8 +257,8 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const 
   c->alpha_q = aq;
   c->flags = flags;
   c->g = g;
-  if (p->dim == 3) c->g.zseg3 = lbm::zseg3_for(g, device_cus());
-  c->ops = lbm::ops_for(p->dim, p->storage);
+  c->ops = ops;
+  if (p->dim == 3 && ops->rows3 > 0) c->g.zseg3 = lbm::zseg3_for(g, c->ops->rows3, device_cus());
   c->coef = RunCoef{p->dx, mu, p->alpha_rho, aq, p->omega_rho, p->omega_q, p->rho_ref};
   if (p->storage == LBM_F16_NEQ) neq_scales(p, mu, aq, c->coef.neq_s);
   c->ws = static_cast<char*>(workspace);

@@ -63,6 +63,7 @@ struct Ops {
   // kernels take one block per column tile and z segment); INT64_MAX where
   // the grid does not depend on it (2D, and the one-step kernel)
   int64_t (*launch_blocks)(const Geometry&, int depth);
+  int rows3;  // rows of the 3D three-step column tile (64 x rows3); 0 where there is none
 };
 
 // Most time steps one launch may advance.
@@ -81,9 +82,9 @@ bool storage_elems(int storage, size_t* rest_elem, size_t* move_elem);
 // Buffer geometry of one run (plane stride, region sizes) for a storage mode.
 Geometry make_geometry(int dim, int storage, const int64_t n[3]);
 
-// Planes per block of the 3D three-step launch on a device with `cus`
-// compute units (lbm_kernels.hip).
-int32_t zseg3_for(const Geometry& g, int cus);
+// Planes per block of the 3D three-step launch with 64 x `rows` column tiles
+// on a device with `cus` compute units (lbm_kernels.hip).
+int32_t zseg3_for(const Geometry& g, int rows, int cus);
 
 // Whether a storage mode stores deviations from the reference equilibrium.
 bool storage_is_deviation(int storage);

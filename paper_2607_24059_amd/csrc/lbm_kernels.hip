@@ -414,9 +414,10 @@ __device__ __forceinline__ void gather_cell3_o32(const TR* __restrict__ sr, cons
 // thread owns one column of the EX x EY region in all three stages: a stage's
 // rest and +-z populations stay in the owner's registers (the +-z neighbours
 // of the next stage are the owner's results of the planes below and above),
-// and its 16 in-plane moving populations go to LDS for the neighbouring
-// columns (stage 1 over EX x EY, stage 2 over its smaller region, each
-// double-buffered by plane parity, so there is one barrier per plane).  Every
+// and its 16 in-plane moving populations go to LDS, each into the slot of the
+// neighbouring column that pulls it in the next stage (so the LDS holds one
+// set per column of the next stage's region, 66 x (TY + 2) and TX x TY,
+// double-buffered by plane parity: one barrier per plane).  Every
 // stage stores its results as the storage type rounds them and relaxes with
 // the same collide as the single step, so the result equals three single
 // steps bit for bit.  Waves r < EY own the 64 columns x0 .. x0 + 63 of
@@ -428,11 +429,14 @@ template <typename TR, typename TM, int TY>
 __global__ __launch_bounds__(64 * (TY + 5)) void k_step3_3d(const TR* __restrict__ sr, const TM* __restrict__ sm,
                                                             TR* __restrict__ dr, TM* __restrict__ dm, int nx, int ny,
                                                             int nz, int zs, int64_t stride, Coef k) {
-  constexpr int TX = 64, H = 2, EX = TX + 2 * H, EY = TY + 2 * H, EN1 = EX * EY;
+  constexpr int TX = 64, H = 2, EX = TX + 2 * H, EY = TY + 2 * H;
   constexpr int RX2 = TX + 2, RY2 = TY + 2, EN2 = RX2 * RY2;  // stage-2 region
   static_assert(4 * EY <= 64, "border columns of every row fit one wave");
-  __shared__ TM s1[2][16][EN1];  // stage-1 in-plane populations, by plane parity
-  __shared__ TM s2[2][16][EN2];  // stage-2 in-plane populations, by plane parity
+  // a stage's moving populations wait in LDS in the slot of the next stage's
+  // column that pulls them, by plane parity: 16 values per column of the
+  // next stage's region, not of the writer's
+  __shared__ TM s1[2][16][EN2];      // stage-1 results, in stage-2 slots
+  __shared__ TM s2[2][16][TX * TY];  // stage-2 results, in stage-3 (tile) slots
   const int t = threadIdx.x;
   int ex, ey;
   bool col;
@@ -450,8 +454,19 @@ __global__ __launch_bounds__(64 * (TY + 5)) void k_step3_3d(const TR* __restrict
   }
   const bool in2 = col && ex >= 1 && ex < EX - 1 && ey >= 1 && ey < EY - 1;
   const bool in3 = col && ex >= H && ex < H + TX && ey >= H && ey < H + TY;
-  const int e1 = ey * EX + ex;
+  // own slots in the stage-2 and stage-3 regions, and the slots that the
+  // four moving populations go to: +x to column (ex + 1, ey), -x to
+  // (ex - 1, ey), +y to (ex, ey + 1), -y to (ex, ey - 1); -1 where that
+  // column is outside the next stage's region
   const int e2 = in2 ? (ey - 1) * RX2 + (ex - 1) : 0;
+  const int e3 = in3 ? (ey - H) * TX + (ex - H) : 0;
+  int w1[4], w2[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int tx = ex + (m == 0 ? 1 : m == 1 ? -1 : 0), ty = ey + (m == 2 ? 1 : m == 3 ? -1 : 0);
+    w1[m] = (col && tx >= 1 && tx < EX - 1 && ty >= 1 && ty < EY - 1) ? (ty - 1) * RX2 + (tx - 1) : -1;
+    w2[m] = (in2 && tx >= H && tx < H + TX && ty >= H && ty < H + TY) ? (ty - H) * TX + (tx - H) : -1;
+  }
   const int tx_n = (nx + TX - 1) / TX, ty_n = (ny + TY - 1) / TY;
   const int nt = tx_n * ty_n * ((nz + zs - 1) / zs);
   const int b = blockIdx.x;
@@ -512,9 +527,12 @@ __global__ __launch_bounds__(64 * (TY + 5)) void k_step3_3d(const TR* __restrict
         r1[i] = load_f32(&a);
         zp1[i] = load_f32(&bp);
         zm1[i] = load_f32(&bm);
-#pragma unroll
-        for (int m = 0; m < 4; ++m) store_f32(&s1[sl][i * 4 + m][e1], g[i][1 + m]);
       }
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+        if (w1[m] >= 0)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) store_f32(&s1[sl][i * 4 + m][w1[m]], g[i][1 + m]);
     }
     // stage 2, plane p - 1, from the stage-1 results
     float zm2[4];
@@ -525,12 +543,12 @@ __global__ __launch_bounds__(64 * (TY + 5)) void k_step3_3d(const TR* __restrict
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         g[i][0] = r1p[i];
-        g[i][1] = load_f32(&s1[sl ^ 1][i * 4 + 0][e1 - 1]);   // +x from x-1
-        g[i][2] = load_f32(&s1[sl ^ 1][i * 4 + 1][e1 + 1]);   // -x from x+1
-        g[i][3] = load_f32(&s1[sl ^ 1][i * 4 + 2][e1 - EX]);  // +y from y-1
-        g[i][4] = load_f32(&s1[sl ^ 1][i * 4 + 3][e1 + EX]);  // -y from y+1
-        g[i][5] = z1pp[i];                                    // +z from z-1
-        g[i][6] = zm1[i];                                     // -z from z+1
+        g[i][1] = load_f32(&s1[sl ^ 1][i * 4 + 0][e2]);  // +x from x-1
+        g[i][2] = load_f32(&s1[sl ^ 1][i * 4 + 1][e2]);  // -x from x+1
+        g[i][3] = load_f32(&s1[sl ^ 1][i * 4 + 2][e2]);  // +y from y-1
+        g[i][4] = load_f32(&s1[sl ^ 1][i * 4 + 3][e2]);  // -y from y+1
+        g[i][5] = z1pp[i];                               // +z from z-1
+        g[i][6] = zm1[i];                                // -z from z+1
       }
       collide<3>(g, k);
       float r2[4], zp2[4];
@@ -544,19 +562,22 @@ __global__ __launch_bounds__(64 * (TY + 5)) void k_step3_3d(const TR* __restrict
         r2[i] = load_f32(&a);
         zp2[i] = load_f32(&bp);
         zm2[i] = load_f32(&bm);
-#pragma unroll
-        for (int m = 0; m < 4; ++m) store_f32(&s2[sl ^ 1][i * 4 + m][e2], g[i][1 + m]);
       }
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+        if (w2[m] >= 0)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) store_f32(&s2[sl ^ 1][i * 4 + m][w2[m]], g[i][1 + m]);
       // stage 3, plane p - 2, from the stage-2 results, to HBM
       if (p >= z0 + 2 && out) {
         float h[4][7];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           h[i][0] = r2p[i];
-          h[i][1] = load_f32(&s2[sl][i * 4 + 0][e2 - 1]);
-          h[i][2] = load_f32(&s2[sl][i * 4 + 1][e2 + 1]);
-          h[i][3] = load_f32(&s2[sl][i * 4 + 2][e2 - RX2]);
-          h[i][4] = load_f32(&s2[sl][i * 4 + 3][e2 + RX2]);
+          h[i][1] = load_f32(&s2[sl][i * 4 + 0][e3]);
+          h[i][2] = load_f32(&s2[sl][i * 4 + 1][e3]);
+          h[i][3] = load_f32(&s2[sl][i * 4 + 2][e3]);
+          h[i][4] = load_f32(&s2[sl][i * 4 + 3][e3]);
           h[i][5] = z2pp[i];
           h[i][6] = zm2[i];
         }
@@ -996,8 +1017,14 @@ __global__ __launch_bounds__(256) void k_copy(const float4* __restrict__ src, fl
 // ----------------------------------------------------------------------------
 // launchers
 // ----------------------------------------------------------------------------
-// 3D three-step launch: 64 x k3KY column tiles on 64 (k3KY + 5) threads.
-constexpr int k3KY = 6;
+// 3D three-step launch: 64 x k3_rows column tiles on 64 (k3_rows + 5)
+// threads, one block per compute unit (FP32: 147 KB of LDS; 16-bit: the
+// registers).  64 x 8 everywhere but FP16 deviations over FP32 rest planes,
+// which need more than the 128 VGPRs that 13 waves leave and keep 64 x 6.
+template <typename TR, typename TM>
+constexpr int k3_rows() {
+  return (std::is_same<TR, float>::value && std::is_same<TM, _Float16>::value) ? 6 : 8;
+}
 
 }  // namespace
 
@@ -1006,11 +1033,12 @@ constexpr int k3KY = 6;
 // in rounds of `cus` blocks and a partial last round leaves the rest of the
 // chip idle; a block also recomputes four planes of its first stage and two
 // of its second at the ends of its segment.  The segment length minimises
-// rounds x the work of one block (256^3: 37 planes, 1204 blocks in 5 rounds,
-// against 32 planes, 1376 blocks in 6 rounds).
-int32_t zseg3_for(const Geometry& g, int cus) {
-  const int64_t txy = static_cast<int64_t>((g.nx + 63) / 64) * ((g.ny + k3KY - 1) / k3KY);
-  const int64_t e1 = 68 * (k3KY + 4), e2 = 66 * (k3KY + 2), e3 = 64 * k3KY;  // cells per plane of each stage
+// rounds x the work of one block (256^3 on 256 units with 64 x 8 tiles:
+// 128 planes, 256 blocks in one round; 64- and 32-plane segments, in two and
+// four rounds, ran 15% and 18% slower).
+int32_t zseg3_for(const Geometry& g, int ky, int cus) {
+  const int64_t txy = static_cast<int64_t>((g.nx + 63) / 64) * ((g.ny + ky - 1) / ky);
+  const int64_t e1 = 68 * (ky + 4), e2 = 66 * (ky + 2), e3 = 64 * ky;  // cells per plane of each stage
   int32_t best = 32;
   double best_cost = -1.0;
   for (int32_t zs = 8; zs <= std::max<int32_t>(8, g.nz); ++zs) {
@@ -1142,6 +1170,7 @@ struct Impl {
   // most steps per launch: 6 in 2D, 3 for the 3D FP32 storages, else the
   // two-step kernel's 2 or one
   static constexpr int kMaxFuse = kHasStepK ? (D == 2 ? kMaxFusion : 3) : kHasStep2 ? 2 : 1;
+  static constexpr int kRows3 = (D == 3 && kHasStepK) ? k3_rows<TR, TM>() : 0;
   // threads of the 16-bit multi-step tile (64x16): 768 where the rest planes
   // are FP32 (FP16 + FP32 rest 194.8 -> 203.3, BF16 + FP32 rest 191.6 ->
   // 201.8 GLUPS at 4096^2), 512 for the all-16-bit storages (768 ran BF16 at
@@ -1219,7 +1248,8 @@ struct Impl {
       auto b = planes_of<TR, TM>(dst, g.rest_bytes);
       const Coef k = make_coef<float>(r, D, DEV);
       const int64_t tiles = launch_blocks(g, 3);
-      hipLaunchKernelGGL((k_step3_3d<TR, TM, k3KY>), dim3(static_cast<uint32_t>(tiles)), dim3(64 * (k3KY + 5)), 0, s,
+      constexpr int KY = k3_rows<TR, TM>();
+      hipLaunchKernelGGL((k_step3_3d<TR, TM, KY>), dim3(static_cast<uint32_t>(tiles)), dim3(64 * (KY + 5)), 0, s,
                          a.rest, a.move, b.rest, b.move, g.nx, g.ny, g.nz, g.zseg3, g.stride, k);
       return hipGetLastError();
     } else {
@@ -1280,7 +1310,8 @@ struct Impl {
   static int64_t launch_blocks(const Geometry& g, int depth) {
     if constexpr (D == 3) {
       if (depth >= 3 && kHasStepK)
-        return static_cast<int64_t>((g.nx + 63) / 64) * ((g.ny + k3KY - 1) / k3KY) * ((g.nz + g.zseg3 - 1) / g.zseg3);
+        return static_cast<int64_t>((g.nx + 63) / 64) * ((g.ny + kRows3 - 1) / kRows3) *
+               ((g.nz + g.zseg3 - 1) / g.zseg3);
       if (depth == 2 && kHasStep2)
         return static_cast<int64_t>((g.nx + kT3X - 1) / kT3X) * ((g.ny + kT3Y - 1) / kT3Y) *
                ((g.nz + kT3Z - 1) / kT3Z);
@@ -1291,7 +1322,7 @@ struct Impl {
   static const Ops* ops() {
     static const Ops o = {&init, &step, kHasStep2 ? &step2 : nullptr, &moments, &diag, &diag_blocks,
                           kHasWalls ? &step_walls : nullptr, kHasStepK ? &stepK : nullptr, kMaxFuse,
-                          &launch_blocks};
+                          &launch_blocks, kRows3};
     return &o;
   }
 };
