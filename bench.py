@@ -455,7 +455,7 @@ def moments_variant(dim: int, n: int, steps: int, probe: float) -> dict:
     """The relaxation scheme (omega_rho = omega_q = 1) on the same k^-3 field,
     in moment-only storage: (1 + dim) FP32 planes, 24 B (2D) / 32 B (3D) per
     lattice update; the library's default fusion (four steps per launch in 2D
-    from 2^20 cells on)."""
+    from 2^20 cells on, two in 3D where that launch has at least 128 blocks)."""
     import torch
     from paper_2607_24059_amd import lbm
     u0, dx, dt, _ = make_workload(n, dim, 1e-3)

@@ -156,13 +156,15 @@ lbm_status lbm_step(lbm_ctx* ctx, int64_t nsteps);
 /* Time steps per launch, 1 .. 6.  In 2D, 2 .. 6 in any storage but LBM_F64
  * (3 .. 6 only while a plane holds at most 2^32 bytes, i.e. 2^30 FP32 cells);
  * in 3D, 2 and 3 for the population storages LBM_F32, LBM_F32_RAW and the
- * four 16-bit deviation storages (kernels that march along z); channel
- * boundaries allow 1 only.  LBM_EINVAL otherwise.  Default in 2D: from 2^20
- * cells on 6 for LBM_F32, LBM_F32_RAW, LBM_F16_DEV_R32 and LBM_BF16_DEV_R32,
- * 4 for LBM_F32_MOMENTS and 5 for the other storages, below that 2 where
- * available, else 1.  Default in 3D: the largest of 3 and 2 whose launch
- * has at least 128 blocks (one per 64 x 6 or 64 x 8 column tile and segment
- * along z; 128^3 runs three steps per launch, 64^3 one), else 1. */
+ * four 16-bit deviation storages, 2 for LBM_F32_MOMENTS while an x-y plane
+ * holds at most 2^30 cells (kernels that march along z); channel boundaries
+ * allow 1 only.  LBM_EINVAL otherwise.  Default in 2D: from 2^20 cells on 6
+ * for LBM_F32, LBM_F32_RAW, LBM_F16_DEV_R32 and LBM_BF16_DEV_R32, 4 for
+ * LBM_F32_MOMENTS and 5 for the other storages, below that 2 where
+ * available, else 1.  Default in 3D: the largest of 3 and 2 whose launch has
+ * at least 128 blocks (one per 64 x 6, 64 x 8 or, for LBM_F32_MOMENTS,
+ * 64 x 11 column tile and segment along z; 128^3 runs three steps per launch
+ * in the population storages and two in LBM_F32_MOMENTS, 64^3 one), else 1. */
 lbm_status lbm_set_fusion(lbm_ctx* ctx, int32_t steps_per_launch);
 
 /* The current number of time steps per launch (0 for a NULL context). */

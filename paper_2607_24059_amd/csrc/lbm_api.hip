@@ -182,6 +182,15 @@ static bool multi_step_fits(const lbm_ctx* c) {
          lbm::fused_offsets_fit(plane, c->g.move_elem > c->g.rest_elem ? c->g.move_elem : c->g.rest_elem);
 }
 
+// Whether a context may run its two-step kernel: the 3D moment-only one, too,
+// addresses an x-y plane with 32-bit byte offsets.
+static bool step2_fits(const lbm_ctx* c) {
+  if (!c->ops->step2) return false;
+  if (c->p.dim == 3 && c->p.storage == LBM_F32_MOMENTS)
+    return lbm::fused_offsets_fit(static_cast<int64_t>(c->g.nx) * c->g.ny, sizeof(float));
+  return true;
+}
+
 // Default steps per launch of the multi-step kernels, from sweeps at 4096^2:
 // the FP32 storages peak at 6 (rest in registers on 32x28 tiles of 768
 // threads: 192.6 GLUPS against 176.3 at 5 on 32x32, 191.5 at 7 and 177.8 at
@@ -212,7 +221,7 @@ static int default_fusion(const lbm_ctx* c) {
   const lbm::Ops* o = c->ops;
   if (c->p.dim == 3) {
     for (int d = std::min(3, o->max_fuse); d >= 2; --d) {
-      const bool has = d >= 3 ? multi_step_fits(c) : o->step2 != nullptr;
+      const bool has = d >= 3 ? multi_step_fits(c) : step2_fits(c);
       if (has && o->launch_blocks(c->g, d) >= kMinFusedBlocks3d) return d;
     }
     return 1;
@@ -258,7 +267,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, const double* u0, const 
   c->flags = flags;
   c->g = g;
   c->ops = ops;
-  if (p->dim == 3 && ops->rows3 > 0) c->g.zseg3 = lbm::zseg3_for(g, c->ops->rows3, device_cus());
+  if (p->dim == 3 && ops->zseg) c->g.zseg = ops->zseg(g, device_cus());
   c->coef = RunCoef{p->dx, mu, p->alpha_rho, aq, p->omega_rho, p->omega_q, p->rho_ref};
   if (p->storage == LBM_F16_NEQ) neq_scales(p, mu, aq, c->coef.neq_s);
   c->ws = static_cast<char*>(workspace);
@@ -323,7 +332,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
 
 lbm_status lbm_set_fusion(lbm_ctx* c, int32_t steps_per_launch) {
   if (!c || steps_per_launch < 1 || steps_per_launch > c->ops->max_fuse) return LBM_EINVAL;
-  if (steps_per_launch >= 2 && (!c->ops->step2 || c->walls)) return LBM_EINVAL;
+  if (steps_per_launch >= 2 && (!step2_fits(c) || c->walls)) return LBM_EINVAL;
   if (steps_per_launch >= 3 && !multi_step_fits(c)) return LBM_EINVAL;
   c->fuse = steps_per_launch;
   return LBM_OK;

@@ -36,7 +36,7 @@ struct Geometry {
   size_t move_elem;     // bytes per moving-plane element
   size_t rest_bytes;    // bytes of the rest-plane region (256-aligned)
   size_t buf_bytes;     // bytes of one full state buffer (256-aligned)
-  int32_t zseg3 = 32;   // planes per block of the 3D three-step launch (zseg3_for)
+  int32_t zseg = 32;    // planes per block of the deepest 3D z-marching launch (Ops::zseg)
 };
 
 // Launchers of one (dimension, storage) instantiation.  Every launcher
@@ -63,7 +63,9 @@ struct Ops {
   // kernels take one block per column tile and z segment); INT64_MAX where
   // the grid does not depend on it (2D, and the one-step kernel)
   int64_t (*launch_blocks)(const Geometry&, int depth);
-  int rows3;  // rows of the 3D three-step column tile (64 x rows3); 0 where there is none
+  // planes per block of the deepest 3D z-marching launch on a device with
+  // `cus` compute units (nullptr where no such launch takes a segment length)
+  int32_t (*zseg)(const Geometry&, int cus);
 };
 
 // Most time steps one launch may advance.
@@ -82,9 +84,10 @@ bool storage_elems(int storage, size_t* rest_elem, size_t* move_elem);
 // Buffer geometry of one run (plane stride, region sizes) for a storage mode.
 Geometry make_geometry(int dim, int storage, const int64_t n[3]);
 
-// Planes per block of the 3D three-step launch with 64 x `rows` column tiles
-// on a device with `cus` compute units (lbm_kernels.hip).
-int32_t zseg3_for(const Geometry& g, int rows, int cus);
+// Planes per block of a 3D z-marching launch that fuses `stages` steps on
+// 64 x `rows` column tiles, `per_cu` blocks per compute unit, on a device
+// with `cus` compute units (lbm_kernels.hip).
+int32_t zseg_for(const Geometry& g, int rows, int stages, int per_cu, int cus);
 
 // Whether a storage mode stores deviations from the reference equilibrium.
 bool storage_is_deviation(int storage);

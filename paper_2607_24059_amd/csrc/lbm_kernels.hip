@@ -423,7 +423,7 @@ __device__ __forceinline__ void gather_cell3_o32(const TR* __restrict__ sr, cons
 // steps bit for bit.  Waves r < EY own the 64 columns x0 .. x0 + 63 of
 // extended row r (whole 128-byte lines per access); the last wave owns the
 // four border columns x0 - 2, x0 - 1, x0 + 64, x0 + 65 of every row.  A block
-// walks zs planes (chosen per grid by zseg3_for).
+// walks zs planes (chosen per grid by zseg_for).
 // ----------------------------------------------------------------------------
 template <typename TR, typename TM, int TY>
 __global__ __launch_bounds__(64 * (TY + 5)) void k_step3_3d(const TR* __restrict__ sr, const TM* __restrict__ sm,
@@ -717,6 +717,122 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(8, 8)))
       h1[i] = hn[i];
     }
     buf ^= 1;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// two steps of the 3D moment-only storage per launch, marching along z.  A
+// block owns a 64 x TY column tile and a segment of zs planes.  Stage 1
+// advances the tile plus a one-cell x/y border (66 x (TY + 2) columns) by one
+// step from the stored W of the tile plus a two-cell border (68 x (TY + 4));
+// stage 2 advances the tile from the stage-1 results, which stay on the chip.
+// At plane p the block evaluates stage 1 at plane p and stage 2 at plane
+// p - 1.  Each thread owns one column of the 68 x (TY + 4) region (waves
+// r < TY + 4 the 64 inner columns of row r, the last wave the four border
+// columns of every row, as in k_step3_3d) and keeps the column's stored W at
+// planes p - 1, p, p + 1 and its stage-1 W at planes p - 2, p - 1, p in
+// registers: the +-z neighbours of both stages.  The in-plane neighbours of a
+// stage come from an LDS plane of that stage's input, double-buffered by
+// plane parity, so a plane costs one barrier.  Both stages evaluate
+// step_moments exactly as the single step does, so the result equals two
+// single steps bit for bit.  Loads and stores use a plane base common to the
+// block plus the column's 32-bit byte offset (planes of at most 2^30 cells).
+// ----------------------------------------------------------------------------
+template <int TY>
+__global__ __launch_bounds__(64 * (TY + 5)) void k_step2_mom_3d(const float* __restrict__ sr, float* __restrict__ dr,
+                                                                int nx, int ny, int nz, int zs, int64_t stride,
+                                                                Coef k) {
+  constexpr int TX = 64, H = 2, EX = TX + 2 * H, EY = TY + 2 * H, E0 = EX * EY;
+  constexpr int RX1 = TX + 2, RY1 = TY + 2, E1 = RX1 * RY1;
+  static_assert(4 * EY <= 64, "border columns of every row fit one wave");
+  __shared__ float s0[2][4][E0];  // stored W of plane p over the 68 x (TY + 4) region
+  __shared__ float s1[2][4][E1];  // stage-1 W of plane p over the 66 x (TY + 2) region
+  const int t = threadIdx.x;
+  int ex, ey;
+  bool col;
+  if (t < 64 * EY) {
+    ey = t / 64;
+    ex = H + t % 64;
+    col = true;
+  } else {
+    const int j = t - 64 * EY;
+    ey = j / 4;
+    const int c = j % 4;
+    ex = c < 2 ? c : TX + c;  // 0, 1, EX - 2, EX - 1
+    col = j < 4 * EY;
+    if (!col) ey = 0;
+  }
+  const bool in1 = col && ex >= 1 && ex < EX - 1 && ey >= 1 && ey < EY - 1;
+  const bool in2 = col && ex >= H && ex < H + TX && ey >= H && ey < H + TY;
+  const int e0 = ey * EX + ex;
+  const int e1 = in1 ? (ey - 1) * RX1 + (ex - 1) : 0;
+  const int tx_n = (nx + TX - 1) / TX, ty_n = (ny + TY - 1) / TY;
+  const int nt = tx_n * ty_n * ((nz + zs - 1) / zs);
+  const int tt = static_cast<int>(xcd_major(blockIdx.x, nt));
+  const int x0 = (tt % tx_n) * TX, y0 = ((tt / tx_n) % ty_n) * TY, z0 = (tt / (tx_n * ty_n)) * zs;
+  const int x = wrap_coord(x0 - H + ex, nx), y = wrap_coord(y0 - H + ey, ny);  // may wrap several times
+  const bool out = in2 && x0 + ex - H < nx && y0 + ey - H < ny;
+  const int64_t plane = static_cast<int64_t>(nx) * ny;
+  const uint32_t o = (static_cast<uint32_t>(y) * static_cast<uint32_t>(nx) + static_cast<uint32_t>(x)) * 4u;
+  const int zend = min(z0 + zs, nz);
+  // the column's stored W at wrapped plane q
+  auto load = [&](int q, float (&w)[4]) {
+    const float* base = sr + static_cast<int64_t>(q) * plane;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i] = *at_byte(base + i * stride, o);
+  };
+  // stored W at planes p - 1, p, p + 1 and p + 2 (in flight); stage-1 W at p - 2, p - 1
+  float a0[4], b0[4], c0[4], n0[4], a1[4], b1[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) a0[i] = b0[i] = c0[i] = n0[i] = a1[i] = b1[i] = 0.0f;
+  int q = wrap_coord(z0 - 2, nz);
+  if (col) load(q, a0);
+  q = (q + 1 == nz) ? 0 : q + 1;
+  if (col) load(q, b0);
+  q = (q + 1 == nz) ? 0 : q + 1;
+  if (col) load(q, c0);
+  q = (q + 1 == nz) ? 0 : q + 1;  // wrapped z0 + 1: the first plane issued ahead
+  for (int p = z0 - 1; p <= zend; ++p) {
+    const int sl = p & 1;
+    // plane p + 2, consumed from the next plane on; in flight across the barrier
+    if (col && p < zend) load(q, n0);
+    q = (q + 1 == nz) ? 0 : q + 1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s0[sl][i][e0] = b0[i];
+    __syncthreads();
+    // stage 1 at plane p
+    float c1[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (in1) {
+      const int off[4] = {-1, 1, -EX, EX};  // upwind neighbour of velocity +x, -x, +y, -y
+      step_moments<3>(
+          [&](int i, int nb) {
+            return nb < 0 ? b0[i] : nb == 4 ? a0[i] : nb == 5 ? c0[i] : s0[sl][i][e0 + off[nb]];
+          },
+          k, c1);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) s1[sl][i][e1] = c1[i];
+    }
+    // stage 2 at plane p - 1, to HBM
+    if (out && p > z0) {
+      const int off[4] = {-1, 1, -RX1, RX1};
+      float w2[4];
+      step_moments<3>(
+          [&](int i, int nb) {
+            return nb < 0 ? b1[i] : nb == 4 ? a1[i] : nb == 5 ? c1[i] : s1[sl ^ 1][i][e1 + off[nb]];
+          },
+          k, w2);
+      const int64_t zc = static_cast<int64_t>(p - 1) * plane;  // an output column does not wrap
+#pragma unroll
+      for (int i = 0; i < 4; ++i) store_stream(at_byte(dr + i * stride + zc, o), w2[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      a0[i] = b0[i];
+      b0[i] = c0[i];
+      c0[i] = n0[i];
+      a1[i] = b1[i];
+      b1[i] = c1[i];
+    }
   }
 }
 
@@ -1028,23 +1144,29 @@ constexpr int k3_rows() {
 
 }  // namespace
 
-// Planes per block of the 3D three-step launch.  One block fills a compute
-// unit (its LDS, or its registers in the 16-bit storages), so the launch runs
-// in rounds of `cus` blocks and a partial last round leaves the rest of the
-// chip idle; a block also recomputes four planes of its first stage and two
-// of its second at the ends of its segment.  The segment length minimises
-// rounds x the work of one block (256^3 on 256 units with 64 x 8 tiles:
-// 128 planes, 256 blocks in one round; 64- and 32-plane segments, in two and
-// four rounds, ran 15% and 18% slower).
-int32_t zseg3_for(const Geometry& g, int ky, int cus) {
+// Planes per block of a 3D z-marching launch of `stages` fused steps on
+// 64 x ky column tiles, `per_cu` blocks per compute unit.  The launch runs in
+// rounds of per_cu x cus blocks and a partial last round leaves the rest of
+// the chip idle; a block also recomputes 2 (stages - s) extra planes of its
+// stage s, over a (64 + 2 (stages - s)) x (ky + 2 (stages - s)) region, at the
+// ends of its segment.  The segment length minimises rounds x the work of one
+// block (256^3 on 256 units, three steps on 64 x 8 tiles: 128 planes, 256
+// blocks in one round; 64- and 32-plane segments, in two and four rounds, ran
+// 15% and 18% slower).
+int32_t zseg_for(const Geometry& g, int ky, int stages, int per_cu, int cus) {
   const int64_t txy = static_cast<int64_t>((g.nx + 63) / 64) * ((g.ny + ky - 1) / ky);
-  const int64_t e1 = 68 * (ky + 4), e2 = 66 * (ky + 2), e3 = 64 * ky;  // cells per plane of each stage
+  const int64_t slots = static_cast<int64_t>(std::max(per_cu, 1)) * std::max(cus, 1);
   int32_t best = 32;
   double best_cost = -1.0;
   for (int32_t zs = 8; zs <= std::max<int32_t>(8, g.nz); ++zs) {
     const int64_t blocks = txy * ((g.nz + zs - 1) / zs);
-    const int64_t rounds = (blocks + cus - 1) / std::max(cus, 1);
-    const double cost = static_cast<double>(rounds) * static_cast<double>((zs + 4) * e1 + (zs + 2) * e2 + zs * e3);
+    const int64_t rounds = (blocks + slots - 1) / slots;
+    double work = 0.0;
+    for (int st = 1; st <= stages; ++st) {
+      const int b = 2 * (stages - st);  // border cells per side of stage st
+      work += static_cast<double>(zs + b) * static_cast<double>((64 + b) * (ky + b));
+    }
+    const double cost = static_cast<double>(rounds) * work;
     if (best_cost < 0.0 || cost < best_cost) {
       best_cost = cost;
       best = zs;
@@ -1068,8 +1190,13 @@ struct Impl {
   }
 
   // 3D moment-only storage: the z-marching kernel, 64 x 16 column tiles on
-  // 1024 threads, 32-plane segments
+  // 1024 threads, 32-plane segments; two steps per launch: 64 x kM2Y column
+  // tiles on 64 (kM2Y + 5) threads, kM2PerCU blocks per compute unit (60 KB
+  // of LDS and 56 VGPRs each).  GLUPS at 256^3 by tile height: 64 x 11 (1024
+  // threads) 177.9, 64 x 10 (960) 172.4, 64 x 8 (832) 141.6, against 143.3
+  // for one step per launch; segment lengths of 16 to 52 planes within 2%.
   static constexpr int kM3X = 64, kM3Y = 16, kM3Z = 32;
+  static constexpr int kM2Y = 11, kM2PerCU = 2;
 
   static hipError_t step(const Geometry& g, const RunCoef& r, const void* src, void* dst, int bx,
                          int by, hipStream_t s) {
@@ -1109,7 +1236,9 @@ struct Impl {
   // 16-bit deviation storages; not FP64 or the split and moment-only ones)
   static constexpr bool k3DPop = D == 3 && !std::is_same<TM, double>::value && !IsNeq<TM>::value &&
                                  !IsMom<TM>::value;
-  static constexpr bool kHasStep2 = (D == 2 && !std::is_same<TM, double>::value) || k3DPop;
+  // 3D moment-only storage: the z-marching two-step kernel
+  static constexpr bool k3DMom = D == 3 && IsMom<TM>::value;
+  static constexpr bool kHasStep2 = (D == 2 && !std::is_same<TM, double>::value) || k3DPop || k3DMom;
   // 64 x 8 columns on 704 threads, 32-plane segments (GLUPS at 256^3: 31.5;
   // 32x16 / 640: 29.2, with 64-plane segments 28.2; 64x12 / 960: 27.5;
   // 96x8 / 1024: 28.0; 32x8 and 16x16 / 384: 25.3, 20.9; 16- and 24-plane
@@ -1131,6 +1260,16 @@ struct Impl {
   static hipError_t step2(const Geometry& g, const RunCoef& r, const void* src, void* dst, hipStream_t s) {
     if constexpr (!kHasStep2) {
       return hipErrorInvalidValue;
+    } else if constexpr (k3DMom) {
+      // 32-bit byte offsets within a plane (lbm_set_fusion refuses larger planes)
+      if (!fused_offsets_fit(static_cast<int64_t>(g.nx) * g.ny, sizeof(float))) return hipErrorInvalidValue;
+      auto a = planes_of<TR, TM>(const_cast<void*>(src), g.rest_bytes);
+      auto b = planes_of<TR, TM>(dst, g.rest_bytes);
+      const Coef k = make_coef<float>(r, D, DEV);
+      hipLaunchKernelGGL((k_step2_mom_3d<kM2Y>), dim3(static_cast<uint32_t>(launch_blocks(g, 2))),
+                         dim3(64 * (kM2Y + 5)), 0, s, a.rest, reinterpret_cast<float*>(b.rest), g.nx, g.ny, g.nz,
+                         g.zseg, g.stride, k);
+      return hipGetLastError();
     } else if constexpr (D == 3) {
       auto a = planes_of<TR, TM>(const_cast<void*>(src), g.rest_bytes);
       auto b = planes_of<TR, TM>(dst, g.rest_bytes);
@@ -1171,6 +1310,12 @@ struct Impl {
   // two-step kernel's 2 or one
   static constexpr int kMaxFuse = kHasStepK ? (D == 2 ? kMaxFusion : 3) : kHasStep2 ? 2 : 1;
   static constexpr int kRows3 = (D == 3 && kHasStepK) ? k3_rows<TR, TM>() : 0;
+
+  // planes per block of the deepest 3D z-marching launch of this storage
+  static int32_t zseg(const Geometry& g, int cus) {
+    if constexpr (k3DMom) return zseg_for(g, kM2Y, 2, kM2PerCU, cus);
+    return zseg_for(g, kRows3 > 0 ? kRows3 : 8, 3, 1, cus);
+  }
   // threads of the 16-bit multi-step tile (64x16): 768 where the rest planes
   // are FP32 (FP16 + FP32 rest 194.8 -> 203.3, BF16 + FP32 rest 191.6 ->
   // 201.8 GLUPS at 4096^2), 512 for the all-16-bit storages (768 ran BF16 at
@@ -1250,7 +1395,7 @@ struct Impl {
       const int64_t tiles = launch_blocks(g, 3);
       constexpr int KY = k3_rows<TR, TM>();
       hipLaunchKernelGGL((k_step3_3d<TR, TM, KY>), dim3(static_cast<uint32_t>(tiles)), dim3(64 * (KY + 5)), 0, s,
-                         a.rest, a.move, b.rest, b.move, g.nx, g.ny, g.nz, g.zseg3, g.stride, k);
+                         a.rest, a.move, b.rest, b.move, g.nx, g.ny, g.nz, g.zseg, g.stride, k);
       return hipGetLastError();
     } else {
       switch (K) {
@@ -1311,7 +1456,9 @@ struct Impl {
     if constexpr (D == 3) {
       if (depth >= 3 && kHasStepK)
         return static_cast<int64_t>((g.nx + 63) / 64) * ((g.ny + kRows3 - 1) / kRows3) *
-               ((g.nz + g.zseg3 - 1) / g.zseg3);
+               ((g.nz + g.zseg - 1) / g.zseg);
+      if (depth == 2 && k3DMom)
+        return static_cast<int64_t>((g.nx + 63) / 64) * ((g.ny + kM2Y - 1) / kM2Y) * ((g.nz + g.zseg - 1) / g.zseg);
       if (depth == 2 && kHasStep2)
         return static_cast<int64_t>((g.nx + kT3X - 1) / kT3X) * ((g.ny + kT3Y - 1) / kT3Y) *
                ((g.nz + kT3Z - 1) / kT3Z);
@@ -1322,7 +1469,7 @@ struct Impl {
   static const Ops* ops() {
     static const Ops o = {&init, &step, kHasStep2 ? &step2 : nullptr, &moments, &diag, &diag_blocks,
                           kHasWalls ? &step_walls : nullptr, kHasStepK ? &stepK : nullptr, kMaxFuse,
-                          &launch_blocks, kRows3};
+                          &launch_blocks, (k3DPop || k3DMom) ? &zseg : nullptr};
     return &o;
   }
 };

@@ -4,9 +4,9 @@ every set, advanced as a stencil on the moments alone.
 Parity: against the FP64 oracle of the full scheme (15 / 28 populations) run
 with omega_rho = omega_q = 1, where every post-relaxation population is its
 cell's equilibrium, so both compute the same W(t) up to rounding (relative L2
-of u <= 1e-5 after 1000 steps in 2D); the two-step kernel is bit-identical to
-two single steps; and the population storage (LBM_F32) at omega = 1 agrees to
-FP32 rounding.
+of u <= 1e-5 after 1000 steps in 2D); the multi-step kernels (2D: 2 to 6 steps per launch, 3D: two) are
+bit-identical to single steps; and the population storage (LBM_F32) at
+omega = 1 agrees to FP32 rounding.
 """
 
 import math
@@ -101,6 +101,57 @@ def test_moments_3d_ragged_and_z_segments(shape, steps):
     print(f"[moments] rel-L2(u) = {err:.3e}, max cell {cell:.3e}", flush=True)
     assert err <= 1e-5 and cell <= 1e-4
     assert np.max(np.abs(rho - r_ref)) <= 1e-6
+
+
+@pytest.mark.parametrize("shape,steps", [((40, 20, 33), 9), ((70, 9, 66), 8), ((10, 12, 14), 11), ((1, 1, 1), 5),
+                                         ((3, 70, 5), 6), ((65, 17, 129), 7), ((33, 7, 130), 4), ((17, 13, 64), 10)])
+def test_moments_3d_two_step_is_bitwise(shape, steps):
+    """3D moment-only storage, two steps per launch (the z-marching kernel on
+    64 x 11 column tiles, segments of at least 8 planes): the single-step state
+    bit for bit on grids ragged in every direction, with several segments
+    along z, tiny grids whose border wraps several times, and odd step counts
+    (the last step runs alone)."""
+    nz, ny, nx = shape
+    dx = 2 * math.pi / max(shape)
+    p = scheme.Params(dim=3, dx=dx, dt=dx * dx / 8, nu=0.02, omega_rho=1.0, omega_q=1.0)
+    u = inputs.random_field_box(shape, dx, seed=23, umax=0.05 / dx)
+    print(f"[moments] 3D two-step shape={shape} steps={steps}", flush=True)
+    blobs = []
+    for fuse in (1, 2):
+        eng = _engine(p, u)
+        eng.set_fusion(fuse)
+        assert eng.fusion() == fuse
+        eng.step(steps)
+        blobs.append(eng.save_state())
+        eng.close()
+    assert np.array_equal(blobs[0], blobs[1])
+
+
+def test_moments_3d_default_two_steps_large_grid():
+    """A 3D grid whose two-step launch has enough blocks (130 x 200 x 96:
+    3 x 19 column tiles, 12-plane segments, 456 blocks) runs two steps per
+    launch by default, bit for bit the single-step state after 7 steps; three
+    steps per launch are refused, and small grids keep one step per launch."""
+    shape = (96, 200, 130)
+    dx = 2 * math.pi / 200
+    p = scheme.Params(dim=3, dx=dx, dt=dx * dx / 8, nu=1e-3, omega_rho=1.0, omega_q=1.0)
+    u = inputs.random_field_box(shape, dx, seed=24, umax=0.05 / dx)
+    blobs = []
+    for fuse in (1, None):
+        eng = _engine(p, u)
+        if fuse is None:
+            assert eng.fusion() == 2
+            with pytest.raises(lbm.LbmError):
+                eng.set_fusion(3)
+        else:
+            eng.set_fusion(fuse)
+        eng.step(7)
+        blobs.append(eng.save_state())
+        eng.close()
+    assert np.array_equal(blobs[0], blobs[1])
+    small = _engine(p, inputs.random_field_box((24, 24, 24), dx, seed=25, umax=0.05 / dx))
+    assert small.fusion() == 1
+    small.close()
 
 
 def test_moments_default_fusion_large_grid_bitwise():
