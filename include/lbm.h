@@ -162,8 +162,8 @@ lbm_status lbm_step(lbm_ctx* ctx, int64_t nsteps);
  * for LBM_F32, LBM_F32_RAW, LBM_F16_DEV_R32 and LBM_BF16_DEV_R32, 4 for
  * LBM_F32_MOMENTS and 5 for the other storages, below that 2 where
  * available, else 1.  Default in 3D: the largest of 3 and 2 whose launch has
- * at least 128 blocks (one per 64 x 6, 64 x 8 or, for LBM_F32_MOMENTS,
- * 64 x 11 column tile and segment along z; 128^3 runs three steps per launch
+ * at least 128 blocks (one per 64 x 8 or, for LBM_F32_MOMENTS, 64 x 11
+ * column tile and segment along z; 128^3 runs three steps per launch
  * in the population storages and two in LBM_F32_MOMENTS, 64^3 one), else 1. */
 lbm_status lbm_set_fusion(lbm_ctx* ctx, int32_t steps_per_launch);
 

@@ -36,16 +36,33 @@ struct bf16 {
   uint16_t bits;
 };
 
+// FP16 bits of v (round to nearest even) and the float of FP16 bits: the
+// hardware conversions written out, so that the compiler keeps each value in
+// a 32-bit register of its own.  Left to itself it packs FP16 values into
+// register halves and folds a conversion into the FMA before it (rounding the
+// exact product-sum to FP16 once instead of the FP32 result); in the 3D
+// three-step kernels that spilled 24-26 bytes per lane at 64 x 8 tiles (GLUPS
+// at 256^3: FP16 + FP32 rest 57.4 -> 84.0, FP16 63.1 -> 83.7; 2D FP16 at
+// 4096^2: 185 -> 212).
+__device__ __forceinline__ uint16_t f16_bits(float v) {
+  uint32_t b;
+  __asm__("v_cvt_f16_f32_e32 %0, %1" : "=v"(b) : "v"(v));
+  return static_cast<uint16_t>(b);
+}
+__device__ __forceinline__ float f16_value(uint16_t h) {
+  float f;
+  __asm__("v_cvt_f32_f16_e32 %0, %1" : "=v"(f) : "v"(static_cast<uint32_t>(h)));
+  return f;
+}
+
 __device__ __forceinline__ float load_f32(const float* p) { return *p; }
-__device__ __forceinline__ float load_f32(const _Float16* p) { return static_cast<float>(*p); }
+__device__ __forceinline__ float load_f32(const _Float16* p) { return f16_value(*reinterpret_cast<const uint16_t*>(p)); }
 __device__ __forceinline__ float load_f32(const bf16* p) {
   return __uint_as_float(static_cast<uint32_t>(p->bits) << 16);
 }
 
 __device__ __forceinline__ void store_f32(float* p, float v) { *p = v; }
-__device__ __forceinline__ void store_f32(_Float16* p, float v) {
-  *p = static_cast<_Float16>(v);  // round to nearest even
-}
+__device__ __forceinline__ void store_f32(_Float16* p, float v) { *reinterpret_cast<uint16_t*>(p) = f16_bits(v); }
 // BF16 bits of v, rounded to nearest even by the hardware conversion (one
 // instruction on gfx950, against six for the same rounding in integer code)
 __device__ __forceinline__ uint16_t bf16_bits(float v) {
@@ -121,7 +138,7 @@ __device__ __forceinline__ double fma_r(double a, double b, double c) { return _
 // shifted loads of adjacent tiles still need.
 __device__ __forceinline__ void store_stream(float* p, float v) { __builtin_nontemporal_store(v, p); }
 __device__ __forceinline__ void store_stream(_Float16* p, float v) {
-  __builtin_nontemporal_store(static_cast<_Float16>(v), p);
+  __builtin_nontemporal_store(f16_bits(v), reinterpret_cast<uint16_t*>(p));
 }
 __device__ __forceinline__ void store_stream(bf16* p, float v) {
   __builtin_nontemporal_store(bf16_bits(v), reinterpret_cast<uint16_t*>(p));

@@ -1133,14 +1133,10 @@ __global__ __launch_bounds__(256) void k_copy(const float4* __restrict__ src, fl
 // ----------------------------------------------------------------------------
 // launchers
 // ----------------------------------------------------------------------------
-// 3D three-step launch: 64 x k3_rows column tiles on 64 (k3_rows + 5)
-// threads, one block per compute unit (FP32: 147 KB of LDS; 16-bit: the
-// registers).  64 x 8 everywhere but FP16 deviations over FP32 rest planes,
-// which need more than the 128 VGPRs that 13 waves leave and keep 64 x 6.
-template <typename TR, typename TM>
-constexpr int k3_rows() {
-  return (std::is_same<TR, float>::value && std::is_same<TM, _Float16>::value) ? 6 : 8;
-}
+// 3D three-step launch: 64 x k3Rows column tiles on 64 (k3Rows + 5) threads,
+// one block per compute unit (FP32: 147 KB of LDS; 16-bit: the registers,
+// 127-128 VGPRs of the 128 that 13 waves leave).
+constexpr int k3Rows = 8;
 
 }  // namespace
 
@@ -1309,7 +1305,7 @@ struct Impl {
   // most steps per launch: 6 in 2D, 3 for the 3D FP32 storages, else the
   // two-step kernel's 2 or one
   static constexpr int kMaxFuse = kHasStepK ? (D == 2 ? kMaxFusion : 3) : kHasStep2 ? 2 : 1;
-  static constexpr int kRows3 = (D == 3 && kHasStepK) ? k3_rows<TR, TM>() : 0;
+  static constexpr int kRows3 = (D == 3 && kHasStepK) ? k3Rows : 0;
 
   // planes per block of the deepest 3D z-marching launch of this storage
   static int32_t zseg(const Geometry& g, int cus) {
@@ -1393,7 +1389,7 @@ struct Impl {
       auto b = planes_of<TR, TM>(dst, g.rest_bytes);
       const Coef k = make_coef<float>(r, D, DEV);
       const int64_t tiles = launch_blocks(g, 3);
-      constexpr int KY = k3_rows<TR, TM>();
+      constexpr int KY = k3Rows;
       hipLaunchKernelGGL((k_step3_3d<TR, TM, KY>), dim3(static_cast<uint32_t>(tiles)), dim3(64 * (KY + 5)), 0, s,
                          a.rest, a.move, b.rest, b.move, g.nx, g.ny, g.nz, g.zseg, g.stride, k);
       return hipGetLastError();

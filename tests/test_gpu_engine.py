@@ -430,8 +430,8 @@ def test_fusion_settings_and_defaults():
                                          ((3, 70, 5), 9), ((64, 64, 64), 3), ((70, 9, 66), 4), ((33, 7, 130), 8)])
 def test_multi_step_fusion_3d_is_bitwise(storage, shape, steps):
     """3D population storages: the z-marching two-step kernel (64 x 8
-    columns, 32-plane segments) and three-step kernel (64 x 8 columns, 64 x 6
-    for FP16 over FP32 rest planes; segments of 8 planes on these grids) give
+    columns, 32-plane segments) and three-step kernel (64 x 8 columns,
+    segments of 8 planes on these grids) give
     the single-step state bit for bit, ragged in every direction, over several
     segments along z, and with remainders that run as shorter launches."""
     nz, ny, nx = shape
@@ -451,8 +451,8 @@ def test_multi_step_fusion_3d_is_bitwise(storage, shape, steps):
 
 def test_two_step_fusion_3d_defaults_and_limits():
     """3D defaults: the z-marching kernels only where their launch has at
-    least 128 blocks (64^3: at most 88 blocks, one step per launch; 128^3: 256
-    blocks in FP32 and 220 for FP16 over FP32 rest, three steps per launch)."""
+    least 128 blocks (64^3: 64 blocks, one step per launch; 128^3: 256 blocks,
+    three steps per launch)."""
     for n, expect in ((64, 1), (128, 3)):
         pn = scheme.params_for_grid(3, n, 0.01)
         for storage in ("f32", "f16_dev_r32"):
