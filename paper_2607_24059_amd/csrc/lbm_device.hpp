@@ -472,8 +472,10 @@ __device__ __forceinline__ void step_cell_neq(const float* __restrict__ sr, cons
 // (the relaxation scheme of Section 2; in deviation form, since the reference
 // equilibria of one set sum to the same constant in every cell).
 // ----------------------------------------------------------------------------
-template <int D, typename WAt>
-__device__ __forceinline__ void step_moments(WAt w_at, const Coef& k, float (&out)[D + 1]) {
+// With inv_at(m) the 1 / rho of upwind neighbour m, as recip_neq(W_0 + ref)
+// gives it (callers that keep it per cell pass it in; the value is the same).
+template <int D, typename WAt, typename InvAt>
+__device__ __forceinline__ void step_moments_inv(WAt w_at, InvAt inv_at, const Coef& k, float (&out)[D + 1]) {
   // Every moving entry of set i at an upwind neighbour is base + flux or
   // base - flux: the bases (a W_i of the neighbour) are summed once over the
   // 2D neighbours, and the fluxes c F_ij once per axis j as the difference of
@@ -491,7 +493,7 @@ __device__ __forceinline__ void step_moments(WAt w_at, const Coef& k, float (&ou
       float Wn[D + 1];
 #pragma unroll
       for (int i = 0; i < D + 1; ++i) Wn[i] = w_at(i, m);
-      const float inv = recip_neq(Wn[0] + k.ref);
+      const float inv = inv_at(m);
       float (&F)[D + 1] = side == 0 ? Fb : Fa;
       F[0] = Wn[1 + j];
 #pragma unroll
@@ -511,6 +513,11 @@ __device__ __forceinline__ void step_moments(WAt w_at, const Coef& k, float (&ou
     const float rest = w - ((i == 0) ? k.d2a_rho : k.d2a_q) * w;
     out[i] = (rest + ((i == 0) ? k.a_rho : k.a_q) * sum_w[i]) + k.c * sum_f[i];
   }
+}
+
+template <int D, typename WAt>
+__device__ __forceinline__ void step_moments(WAt w_at, const Coef& k, float (&out)[D + 1]) {
+  step_moments_inv<D>(w_at, [&](int m) { return recip_neq(w_at(0, m) + k.ref); }, k, out);
 }
 
 template <int D>

@@ -733,9 +733,12 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(8, 8)))
 // planes p - 1, p, p + 1 and its stage-1 W at planes p - 2, p - 1, p in
 // registers: the +-z neighbours of both stages.  The in-plane neighbours of a
 // stage come from an LDS plane of that stage's input, double-buffered by
-// plane parity, so a plane costs one barrier.  Both stages evaluate
-// step_moments exactly as the single step does, so the result equals two
-// single steps bit for bit.  Loads and stores use a plane base common to the
+// plane parity, so a plane costs one barrier.  Each cell's 1 / rho is
+// computed once per plane by its owner and kept beside its W (in LDS and in
+// the column's registers) instead of once by each of its six neighbours
+// (GLUPS at 256^3: 174.1 -> 184.8, 128^3: 116 -> 133).  Both stages evaluate
+// the single step's stencil (step_moments_inv, with that same reciprocal), so
+// the result equals two single steps bit for bit.  Loads and stores use a plane base common to the
 // block plus the column's 32-bit byte offset (planes of at most 2^30 cells).
 // ----------------------------------------------------------------------------
 template <int TY>
@@ -745,8 +748,8 @@ __global__ __launch_bounds__(64 * (TY + 5)) void k_step2_mom_3d(const float* __r
   constexpr int TX = 64, H = 2, EX = TX + 2 * H, EY = TY + 2 * H, E0 = EX * EY;
   constexpr int RX1 = TX + 2, RY1 = TY + 2, E1 = RX1 * RY1;
   static_assert(4 * EY <= 64, "border columns of every row fit one wave");
-  __shared__ float s0[2][4][E0];  // stored W of plane p over the 68 x (TY + 4) region
-  __shared__ float s1[2][4][E1];  // stage-1 W of plane p over the 66 x (TY + 2) region
+  __shared__ float s0[2][5][E0];  // stored W of plane p and its 1 / rho, over the 68 x (TY + 4) region
+  __shared__ float s1[2][5][E1];  // stage-1 W of plane p and its 1 / rho, over the 66 x (TY + 2) region
   const int t = threadIdx.x;
   int ex, ey;
   bool col;
@@ -785,6 +788,9 @@ __global__ __launch_bounds__(64 * (TY + 5)) void k_step2_mom_3d(const float* __r
   float a0[4], b0[4], c0[4], n0[4], a1[4], b1[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) a0[i] = b0[i] = c0[i] = n0[i] = a1[i] = b1[i] = 0.0f;
+  // 1 / rho of the column at those planes, computed once per cell and plane
+  auto rinv = [&](const float (&w)[4]) { return recip_neq(w[0] + k.ref); };
+  float ia0 = 0.0f, ib0 = 0.0f, ic0 = 0.0f, ia1 = 0.0f, ib1 = 0.0f;
   int q = wrap_coord(z0 - 2, nz);
   if (col) load(q, a0);
   q = (q + 1 == nz) ? 0 : q + 1;
@@ -792,6 +798,8 @@ __global__ __launch_bounds__(64 * (TY + 5)) void k_step2_mom_3d(const float* __r
   q = (q + 1 == nz) ? 0 : q + 1;
   if (col) load(q, c0);
   q = (q + 1 == nz) ? 0 : q + 1;  // wrapped z0 + 1: the first plane issued ahead
+  ia0 = rinv(a0);
+  ib0 = rinv(b0);
   for (int p = z0 - 1; p <= zend; ++p) {
     const int sl = p & 1;
     // plane p + 2, consumed from the next plane on; in flight across the barrier
@@ -799,28 +807,33 @@ __global__ __launch_bounds__(64 * (TY + 5)) void k_step2_mom_3d(const float* __r
     q = (q + 1 == nz) ? 0 : q + 1;
 #pragma unroll
     for (int i = 0; i < 4; ++i) s0[sl][i][e0] = b0[i];
+    s0[sl][4][e0] = ib0;
+    ic0 = rinv(c0);
     __syncthreads();
     // stage 1 at plane p
     float c1[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    float ic1 = 0.0f;
     if (in1) {
       const int off[4] = {-1, 1, -EX, EX};  // upwind neighbour of velocity +x, -x, +y, -y
-      step_moments<3>(
+      step_moments_inv<3>(
           [&](int i, int nb) {
             return nb < 0 ? b0[i] : nb == 4 ? a0[i] : nb == 5 ? c0[i] : s0[sl][i][e0 + off[nb]];
           },
-          k, c1);
+          [&](int nb) { return nb == 4 ? ia0 : nb == 5 ? ic0 : s0[sl][4][e0 + off[nb]]; }, k, c1);
+      ic1 = rinv(c1);
 #pragma unroll
       for (int i = 0; i < 4; ++i) s1[sl][i][e1] = c1[i];
+      s1[sl][4][e1] = ic1;
     }
     // stage 2 at plane p - 1, to HBM
     if (out && p > z0) {
       const int off[4] = {-1, 1, -RX1, RX1};
       float w2[4];
-      step_moments<3>(
+      step_moments_inv<3>(
           [&](int i, int nb) {
             return nb < 0 ? b1[i] : nb == 4 ? a1[i] : nb == 5 ? c1[i] : s1[sl ^ 1][i][e1 + off[nb]];
           },
-          k, w2);
+          [&](int nb) { return nb == 4 ? ia1 : nb == 5 ? ic1 : s1[sl ^ 1][4][e1 + off[nb]]; }, k, w2);
       const int64_t zc = static_cast<int64_t>(p - 1) * plane;  // an output column does not wrap
 #pragma unroll
       for (int i = 0; i < 4; ++i) store_stream(at_byte(dr + i * stride + zc, o), w2[i]);
@@ -833,6 +846,10 @@ __global__ __launch_bounds__(64 * (TY + 5)) void k_step2_mom_3d(const float* __r
       a1[i] = b1[i];
       b1[i] = c1[i];
     }
+    ia0 = ib0;
+    ib0 = ic0;
+    ia1 = ib1;
+    ib1 = ic1;
   }
 }
 
@@ -1187,8 +1204,8 @@ struct Impl {
 
   // 3D moment-only storage: the z-marching kernel, 64 x 16 column tiles on
   // 1024 threads, 32-plane segments; two steps per launch: 64 x kM2Y column
-  // tiles on 64 (kM2Y + 5) threads, kM2PerCU blocks per compute unit (60 KB
-  // of LDS and 56 VGPRs each).  GLUPS at 256^3 by tile height: 64 x 11 (1024
+  // tiles on 64 (kM2Y + 5) threads, kM2PerCU blocks per compute unit (75 KB
+  // of LDS and 60 VGPRs each).  GLUPS at 256^3 by tile height: 64 x 11 (1024
   // threads) 177.9, 64 x 10 (960) 172.4, 64 x 8 (832) 141.6, against 143.3
   // for one step per launch; segment lengths of 16 to 52 planes within 2%.
   static constexpr int kM3X = 64, kM3Y = 16, kM3Z = 32;
