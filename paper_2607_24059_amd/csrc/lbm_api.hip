@@ -206,23 +206,16 @@ static int default_depth(int storage) {
   }
 }
 
-// Fewest blocks a 3D z-marching launch needs to be the default: those kernels
-// take one block per column tile and z segment, so small grids leave most of
-// the 256 compute units idle (64^3 FP32: 5.0 GLUPS with two steps per launch
-// in 16 blocks, against 19.7 with one step per launch; 128^3 at three steps,
-// 220 blocks: 46 GLUPS).
-constexpr int64_t kMinFusedBlocks3d = 128;
-
 // Steps per launch when a context is created.  2D: the multi-step kernels from
 // 1024^2 cells on; smaller grids are launch-bound and keep the two-step
 // kernel's small tiles.  3D: the deepest z-marching kernel whose launch has
-// kMinFusedBlocks3d blocks, else one step per launch.
+// lbm::kMinZmarchBlocks3d blocks, else one step per launch.
 static int default_fusion(const lbm_ctx* c) {
   const lbm::Ops* o = c->ops;
   if (c->p.dim == 3) {
     for (int d = std::min(3, o->max_fuse); d >= 2; --d) {
       const bool has = d >= 3 ? multi_step_fits(c) : step2_fits(c);
-      if (has && o->launch_blocks(c->g, d) >= kMinFusedBlocks3d) return d;
+      if (has && o->launch_blocks(c->g, d) >= lbm::kMinZmarchBlocks3d) return d;
     }
     return 1;
   }

@@ -71,6 +71,15 @@ struct Ops {
 // Most time steps one launch may advance.
 constexpr int kMaxFusion = 6;
 
+// Fewest blocks with which a 3D z-marching launch is used where a
+// cell-parallel launch can do the same work: those kernels take one block per
+// column tile and z segment, so small grids leave most of the 256 compute
+// units idle (64^3 FP32: 5.0 GLUPS with two steps per launch in 16 blocks,
+// against 19.7 with the cell-parallel single step; moment-only single step
+// at 64^3 / 128^3 / 192^3, z-marching in 8 / 64 / 216 blocks against
+// cell-parallel: 5.3 / 36.1 / 101.8 against 61.3 / 87.6 / 96.4 GLUPS).
+constexpr int64_t kMinZmarchBlocks3d = 128;
+
 // Most blocks of the diagnostics launch (Ops::diag_blocks), hence most FP64
 // partials its final pass reads.
 constexpr int kDiagMaxBlocks = 2048;

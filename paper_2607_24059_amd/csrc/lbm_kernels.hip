@@ -1217,11 +1217,12 @@ struct Impl {
     auto b = planes_of<TR, TM>(dst, g.rest_bytes);
     const auto k = make_coef<typename ComputeOf<TM>::type>(r, D, DEV);
     if constexpr (D == 3 && IsMom<TM>::value) {
-      // the z-marching kernel addresses a plane with 32-bit byte offsets;
-      // larger planes take the cell-parallel kernel (the same stencil)
-      if (fused_offsets_fit(static_cast<int64_t>(g.nx) * g.ny, sizeof(float))) {
-        const int64_t tiles = static_cast<int64_t>((g.nx + kM3X - 1) / kM3X) * ((g.ny + kM3Y - 1) / kM3Y) *
-                              ((g.nz + kM3Z - 1) / kM3Z);
+      // the z-marching kernel where its launch fills the chip and its 32-bit
+      // byte offsets cover a plane; else the cell-parallel kernel (the same
+      // stencil, the same bits)
+      const int64_t tiles = static_cast<int64_t>((g.nx + kM3X - 1) / kM3X) * ((g.ny + kM3Y - 1) / kM3Y) *
+                            ((g.nz + kM3Z - 1) / kM3Z);
+      if (tiles >= kMinZmarchBlocks3d && fused_offsets_fit(static_cast<int64_t>(g.nx) * g.ny, sizeof(float))) {
         hipLaunchKernelGGL((k_step_mom_3d<kM3X, kM3Y, kM3Z>), dim3(static_cast<uint32_t>(tiles)), dim3(kM3X * kM3Y),
                            0, s, a.rest, reinterpret_cast<float*>(b.rest), g.nx, g.ny, g.nz, g.stride, k);
         return hipGetLastError();

@@ -81,10 +81,11 @@ def test_moments_fusion_is_bitwise(shape, steps):
 @pytest.mark.parametrize("shape,steps", [((40, 20, 33), 60), ((70, 9, 66), 40), ((10, 12, 14), 80), ((1, 1, 1), 5),
                                          ((3, 70, 5), 30), ((65, 17, 129), 12)])
 def test_moments_3d_ragged_and_z_segments(shape, steps):
-    """3D moment-only storage (the z-marching kernel: 64 x 16 column tiles,
-    32-plane segments) against the full-population oracle at omega = 1 on
-    grids ragged in every direction, with several segments along z, tiny
-    grids whose halo wraps several times, and a y extent below the tile."""
+    """3D moment-only storage at its default fusion (one step per launch on
+    these grids, by the cell-parallel kernel: the z-marching launches would
+    have fewer than 128 blocks) against the full-population oracle at
+    omega = 1 on grids ragged in every direction, tiny grids and a y extent
+    below the tile."""
     nz, ny, nx = shape
     dx = 2 * math.pi / max(shape)
     p = scheme.Params(dim=3, dx=dx, dt=dx * dx / 8, nu=0.02, omega_rho=1.0, omega_q=1.0)
@@ -152,6 +153,35 @@ def test_moments_3d_default_two_steps_large_grid():
     small = _engine(p, inputs.random_field_box((24, 24, 24), dx, seed=25, umax=0.05 / dx))
     assert small.fusion() == 1
     small.close()
+
+
+def test_moments_3d_z_marching_single_step_oracle():
+    """The z-marching single step runs where its launch has at least 128
+    blocks (smaller grids take the cell-parallel kernel): 130 x 260 x 100 is
+    3 x 17 column tiles by 4 segments, ragged in every direction.  Against
+    the full-population oracle at omega = 1 after 4 steps, and bit for bit
+    the two-step kernel's state."""
+    shape = (100, 260, 130)
+    dx = 2 * math.pi / 260
+    p = scheme.Params(dim=3, dx=dx, dt=dx * dx / 8, nu=0.02, omega_rho=1.0, omega_q=1.0)
+    u0 = inputs.random_field_box(shape, dx, seed=26, umax=0.05 / dx)
+    states = []
+    for fuse in (1, 2):
+        print(f"[moments] 3D {shape} fusion {fuse}", flush=True)
+        eng = _engine(p, u0)
+        eng.set_fusion(fuse)
+        eng.step(4)
+        states.append(eng.save_state())
+        if fuse == 1:
+            rho, q = eng.moments()
+        eng.close()
+    assert np.array_equal(states[0], states[1])
+    r_ref, q_ref, _ = scheme.simulate(u0, p, 4)
+    err = _rel(q / rho, q_ref / r_ref)
+    cell = float(np.max(np.abs(q / rho - q_ref / r_ref)) / np.max(np.abs(q_ref / r_ref)))
+    print(f"[moments] rel-L2(u) = {err:.3e}, max cell {cell:.3e}", flush=True)
+    assert err <= 1e-5 and cell <= 1e-4
+    assert np.max(np.abs(rho - r_ref)) <= 1e-6
 
 
 def test_moments_default_fusion_large_grid_bitwise():
