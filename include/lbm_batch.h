@@ -12,9 +12,11 @@
  * several steps per launch (lbm_batch_set_fusion): one walks 64 x 8-cell tiles
  * and advances two steps (each tile and its one-cell border by one step into
  * LDS, the tile by the second); the default one walks the single-run engine's
- * multi-step tiles and advances five (the tile and a four-cell border by one
- * step into LDS, three more steps inside LDS on shrinking regions, the tile by
- * the fifth).  The per-cell update is the same device code as lbm_step, so a
+ * multi-step tiles and advances K steps (the tile and a (K-1)-cell border by
+ * one step into LDS, K-2 more steps inside LDS on shrinking regions, the tile
+ * by the last): K = 6 in LBM_F32 and LBM_F32_RAW when at least half of the
+ * batch's cells belong to runs of 2^20 cells or more (as the single-run
+ * engine), else 5.  The per-cell update is the same device code as lbm_step, so a
  * run advanced in a batch is bit-identical to the same run advanced alone,
  * with any setting.  The split FP16 (LBM_F16_NEQ) and FP64
  * storages are not available in a batch.
@@ -62,10 +64,10 @@ lbm_status lbm_batch_init(lbm_batch** out, int32_t dim, int32_t storage, int32_t
  * a power of two), then the number of blocks of the persistent launch (4, 8,
  * 16 or 32 per compute unit, or one per tile), and in 2D the number of blocks
  * of the two-step launch (1, 2, 4 or 8 per compute unit, or one per tile) and
- * the five-step tile shape of every size class (each shape timed on the
- * class's runs alone, as a graph launch), by timing each candidate on the
- * batch's own buffers; the state is not changed.  The five-step launches keep
- * one block per tile (lbm_batch_set_fused_grid changes that).
+ * the K-step tile shape of every size class (each shape timed on the class's
+ * runs alone, as a graph launch), by timing each candidate on the batch's own
+ * buffers; the state is not changed.  The K-step launches keep one block per
+ * tile (lbm_batch_set_fused_grid changes that).
  * If cache_path is non-NULL (else the environment
  * variable LBM_AUTOTUNE_CACHE, if set) previously tuned shapes for this
  * device, dimension and storage are read from that text file and new ones are
@@ -89,24 +91,25 @@ int32_t lbm_batch_tile_width(const lbm_batch* b, int32_t run);
  * means one block per tile); chosen by lbm_batch_autotune. */
 int32_t lbm_batch_grid(const lbm_batch* b);
 
-/* Blocks of the current multi-step launch: the five-step kernel's (summed
- * over its tile shapes) when the fusion is 5, else the two-step kernel's (0 if
- * the batch has none, i.e. in 3D).  The two-step grid is chosen by
- * lbm_batch_autotune; the five-step grid is one block per tile unless
+/* Blocks of the current multi-step launch: the K-step kernel's (summed over
+ * its tile shapes) when the fusion is K, else the two-step kernel's (0 if the
+ * batch has none, i.e. in 3D).  The two-step grid is chosen by
+ * lbm_batch_autotune; the K-step grid is one block per tile unless
  * lbm_batch_set_fused_grid set a persistent one. */
 int32_t lbm_batch_fused_grid(const lbm_batch* b);
 
-/* Cell tile (tx x ty) of run r in the five-step launches (2D population
+/* Cell tile (tx x ty) of run r in the K-step launches (2D population
  * storages; LBM_EINVAL otherwise).  Three shapes exist per storage (4-byte
- * planes: 32x32, 32x16, 16x16; 16-bit planes: 64x16, 32x32, 32x16);
- * lbm_batch_autotune picks one per size class, the first one otherwise. */
+ * planes: 32x32 at K = 5 or 32x28 at K = 6, 32x16, 16x16; 16-bit planes:
+ * 64x16, 32x32, 32x16); lbm_batch_autotune picks one per size class, the
+ * first one otherwise. */
 lbm_status lbm_batch_fused_tile(const lbm_batch* b, int32_t run, int32_t* tx, int32_t* ty);
 
 /* Use fused tile shape `shape` (0, 1 or 2, in the order above) for every run
  * (results do not depend on it).  Rebuilds the step graphs.  Synchronises. */
 lbm_status lbm_batch_set_fused_shape(lbm_batch* b, int32_t shape);
 
-/* Blocks per compute unit of each five-step launch (1..64; each block then
+/* Blocks per compute unit of each K-step launch (1..64; each block then
  * walks several tiles), or 0 for one block per tile (the default); results do
  * not depend on it.  A persistent grid is slower here: the launch's per-shape
  * graph nodes run concurrently and share the compute units.  2D population
@@ -114,10 +117,10 @@ lbm_status lbm_batch_set_fused_shape(lbm_batch* b, int32_t shape);
  * Synchronises. */
 lbm_status lbm_batch_set_fused_grid(lbm_batch* b, int32_t blocks_per_cu);
 
-/* Steps per launch: 1 (one-step kernel), 2 (two-step kernel) or 5 (five-step
- * kernel, the default); 2 and 5 in 2D only; LBM_EINVAL otherwise.  Every
- * setting gives the same states.  A remainder shorter than the setting runs
- * as shorter launches. */
+/* Steps per launch: 1 (one-step kernel), 2 (two-step kernel) or the batch's K
+ * (the K-step kernel, the default: 5 or 6, fixed when the batch is created);
+ * 2 and K in 2D only; LBM_EINVAL otherwise.  Every setting gives the same
+ * states.  A remainder shorter than the setting runs as shorter launches. */
 lbm_status lbm_batch_set_fusion(lbm_batch* b, int32_t steps_per_launch);
 
 /* The current number of steps per launch (0 for NULL). */

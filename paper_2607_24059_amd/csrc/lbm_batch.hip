@@ -139,16 +139,16 @@ __global__ __launch_bounds__(kT2N) void k_batch_step2(const BatchRun* __restrict
   }
 }
 
-// kBatchK steps per launch (2D): the single-run engine's multi-step tiles
+// K steps per launch (2D): the single-run engine's multi-step tiles
 // (lbm_fused.hpp) walked by a persistent grid, each tile wrapping periodically
 // in its own run, so again bit-identical to single steps.  Three tile shapes
 // per storage; lbm_batch_autotune picks one per size class (the tiles of each
 // shape are one launch of that shape's kernel, and the launches of one fused
-// step are independent graph nodes).
-constexpr int kBatchK = 5;
+// step are independent graph nodes).  K is 5, or 6 for the 4-byte storages
+// where most cells belong to large runs (batch_depth).
 constexpr int kShapes = 3;
 
-template <typename TR, typename TM, int S>
+template <typename TR, typename TM, int S, int K>
 struct BatchKShape {
   static constexpr bool kRegs = sizeof(TR) == 4 && sizeof(TM) == 4;
   // 4-byte planes, rest populations in registers: 32x32 on 768 threads (the
@@ -157,30 +157,32 @@ struct BatchKShape {
   // compute unit), 16x16 on 256 (small runs: more tiles); 16-bit planes:
   // 64x16 on 512 (on 768 threads, the single-run engine's choice with FP32
   // rest planes, the 512-run FP16 + FP32 rest batch ran 183.0 against 199.6),
-  // 32x32 on 512, 32x16 on 256.
+  // 32x32 on 512, 32x16 on 256.  At six steps the first 4-byte shape is the
+  // single-run engine's 32x28 (its 42x38 extended tile keeps two blocks per
+  // compute unit).
   static constexpr int TX = kRegs ? (S == 2 ? 16 : 32) : (S == 0 ? 64 : 32);
-  static constexpr int TY = kRegs ? (S == 0 ? 32 : 16) : (S == 1 ? 32 : 16);
+  static constexpr int TY = kRegs ? (S == 0 ? (K == 6 ? 28 : 32) : 16) : (S == 1 ? 32 : 16);
   static constexpr int NT = kRegs ? (S == 0 ? 768 : 256) : (S == 2 ? 256 : 512);
 };
 constexpr int kTKXmin = 16, kTKYmin = 16;  // smallest tile width and height (size the tile list)
 
-template <typename TR, typename TM, int S>
-__global__ __launch_bounds__((BatchKShape<TR, TM, S>::NT)) void k_batch_stepK(const BatchRun* __restrict__ runs,
+template <typename TR, typename TM, int S, int K>
+__global__ __launch_bounds__((BatchKShape<TR, TM, S, K>::NT)) void k_batch_stepK(const BatchRun* __restrict__ runs,
                                                                             const BatchTile* __restrict__ tiles,
                                                                             int64_t ntiles, char* __restrict__ base,
                                                                             int parity) {
-  using SH = BatchKShape<TR, TM, S>;
+  using SH = BatchKShape<TR, TM, S, K>;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const BatchTile tl = tiles[t];
     const BatchRun& r = runs[tl.run];
     const auto a = planes_of<TR, TM>(base + r.off[parity], static_cast<size_t>(r.rest_bytes));
     const auto b = planes_of<TR, TM>(base + r.off[parity ^ 1], static_cast<size_t>(r.rest_bytes));
     if constexpr (SH::kRegs) {
-      using T = TileKr<TR, TM, SH::TX, SH::TY, SH::NT, kBatchK>;
+      using T = TileKr<TR, TM, SH::TX, SH::TY, SH::NT, K>;
       __shared__ TM s_move[12][T::EN];
       T::run(a.rest, a.move, b.rest, b.move, tl.x0, tl.y0, r.nx, r.ny, r.stride, r.k, s_move);
     } else {
-      using T = TileK<TR, TM, SH::TX, SH::TY, SH::NT, kBatchK>;
+      using T = TileK<TR, TM, SH::TX, SH::TY, SH::NT, K>;
       __shared__ TR s_rest[3][T::EN];
       __shared__ TM s_move[12][T::EN];
       T::run(a.rest, a.move, b.rest, b.move, tl.x0, tl.y0, r.nx, r.ny, r.stride, r.k, s_rest, s_move);
@@ -193,32 +195,53 @@ using BatchKernel = void (*)(const BatchRun*, const BatchTile*, int64_t, char*, 
 
 struct BatchKKernel {
   BatchKernel fn = nullptr;
-  int tx = 0, ty = 0, threads = 0;
+  int tx = 0, ty = 0, threads = 0, depth = 0;
 };
 
-template <typename TR, typename TM, int S>
+template <typename TR, typename TM, int S, int K>
 BatchKKernel batch_k_shape() {
-  using SH = BatchKShape<TR, TM, S>;
-  return BatchKKernel{&k_batch_stepK<TR, TM, S>, SH::TX, SH::TY, SH::NT};
+  using SH = BatchKShape<TR, TM, S, K>;
+  return BatchKKernel{&k_batch_stepK<TR, TM, S, K>, SH::TX, SH::TY, SH::NT, K};
 }
 
-template <typename TR, typename TM>
+template <typename TR, typename TM, int K>
 void batch_k_of(BatchKKernel (&out)[kShapes]) {
-  out[0] = batch_k_shape<TR, TM, 0>();
-  out[1] = batch_k_shape<TR, TM, 1>();
-  out[2] = batch_k_shape<TR, TM, 2>();
+  out[0] = batch_k_shape<TR, TM, 0, K>();
+  out[1] = batch_k_shape<TR, TM, 1, K>();
+  out[2] = batch_k_shape<TR, TM, 2, K>();
 }
 
-// the multi-step kernels of a storage (all null where there are none)
-void batch_kernelK(int dim, int storage, BatchKKernel (&out)[kShapes]) {
+// Steps per launch of a batch's multi-step kernel.  As in the single-run
+// engine, six for the 4-byte storages where at least half of the cells belong
+// to runs of 2^20 cells or more, else five: small runs (the 575 runs of 75^2
+// of the parameter sweeps) keep the narrower border, and the 16-bit storages
+// lost with six on the 512-run workload (FP16 + FP32 rest 189.4 against
+// 199.2, BF16 195.0 against 205.7 GLUPS).
+int batch_depth(int dim, int storage, int nruns, const lbm_run_spec* runs) {
+  if (dim != 2 || (storage != LBM_F32 && storage != LBM_F32_RAW)) return 5;
+  int64_t big = 0, all = 0;
+  for (int r = 0; r < nruns; ++r) {
+    const int64_t c = runs[r].n[0] * runs[r].n[1];
+    all += c;
+    if (c >= (int64_t(1) << 20)) big += c;
+  }
+  return 2 * big >= all && all > 0 ? 6 : 5;
+}
+
+// the multi-step kernels of a storage at `depth` steps per launch (all null
+// where there are none)
+void batch_kernelK(int dim, int storage, int depth, BatchKKernel (&out)[kShapes]) {
   for (auto& k : out) k = BatchKKernel{};
   if (dim != 2) return;
   switch (storage) {
-    case LBM_F32: case LBM_F32_RAW: batch_k_of<float, float>(out); return;
-    case LBM_F16_DEV: batch_k_of<_Float16, _Float16>(out); return;
-    case LBM_BF16_DEV: batch_k_of<bf16, bf16>(out); return;
-    case LBM_F16_DEV_R32: batch_k_of<float, _Float16>(out); return;
-    case LBM_BF16_DEV_R32: batch_k_of<float, bf16>(out); return;
+    case LBM_F32: case LBM_F32_RAW:
+      if (depth == 6) batch_k_of<float, float, 6>(out);
+      else batch_k_of<float, float, 5>(out);
+      return;
+    case LBM_F16_DEV: batch_k_of<_Float16, _Float16, 5>(out); return;
+    case LBM_BF16_DEV: batch_k_of<bf16, bf16, 5>(out); return;
+    case LBM_F16_DEV_R32: batch_k_of<float, _Float16, 5>(out); return;
+    case LBM_BF16_DEV_R32: batch_k_of<float, bf16, 5>(out); return;
   }
 }
 
@@ -308,9 +331,10 @@ struct lbm_batch {
   BatchTile* d_tiles2 = nullptr;  // fused (two-step) tiles, 2D only
   int64_t ntiles2 = 0;
   int grid2 = 0;                  // persistent grid of the fused kernel
-  int fuse = 1;                   // steps per launch: 1, 2 (two-step kernel) or kBatchK
+  int fuse = 1;                   // steps per launch: 1, 2 (two-step kernel) or kdepth
+  int kdepth = 0;                 // steps per launch of the multi-step kernel (0: none)
   BatchKernel kernel2 = nullptr;
-  BatchKKernel kernelK[kShapes];  // kBatchK steps per launch (2D population storages), per tile shape
+  BatchKKernel kernelK[kShapes];  // kdepth steps per launch (2D population storages), per tile shape
   std::map<int, int> shape_of_class;  // fused tile shape per size class
   BatchTile* d_tilesK = nullptr;
   int64_t ntilesK = 0;
@@ -667,8 +691,9 @@ lbm_status lbm_batch_init(lbm_batch** out, int32_t dim, int32_t storage, int32_t
   b->stream = static_cast<hipStream_t>(hip_stream);
   b->kernel = batch_kernel(dim, storage);
   b->kernel2 = batch_kernel2(dim, storage);
-  batch_kernelK(dim, storage, b->kernelK);
-  b->fuse = b->kernelK[0].fn ? kBatchK : b->kernel2 ? 2 : 1;
+  batch_kernelK(dim, storage, batch_depth(dim, storage, nruns, runs), b->kernelK);
+  b->kdepth = b->kernelK[0].fn ? b->kernelK[0].depth : 0;
+  b->fuse = b->kdepth ? b->kdepth : b->kernel2 ? 2 : 1;
   const Ops* ops = ops_for(dim, storage);
   const bool devn = storage_is_deviation(storage);
 
@@ -907,17 +932,17 @@ lbm_status lbm_batch_autotune(lbm_batch* b, const char* cache_path) {
 lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
   if (!b || nsteps < 0) return LBM_EINVAL;
   hipError_t e = hipSuccess;
-  if (b->fuse == kBatchK) {
+  if (b->kdepth && b->fuse == b->kdepth) {
     // multi-step launches, then two-step and single-step ones for the remainder
     while (nsteps > 0 && e == hipSuccess) {
       int adv = 1, flip = 1;
-      if (nsteps >= kBatchK * kFusedGraphLaunches) {
+      if (nsteps >= b->kdepth * kFusedGraphLaunches) {
         e = hipGraphLaunch(b->exec_mainK[b->parity], b->stream);  // even launch count: parity kept
-        adv = kBatchK * kFusedGraphLaunches;
+        adv = b->kdepth * kFusedGraphLaunches;
         flip = 0;
-      } else if (nsteps >= kBatchK) {
+      } else if (nsteps >= b->kdepth) {
         e = hipGraphLaunch(b->exec_oneK[b->parity], b->stream);
-        adv = kBatchK;
+        adv = b->kdepth;
       } else if (nsteps >= 2) {
         e = hipGraphLaunch(b->exec_two[b->parity], b->stream);
         adv = 2;
@@ -998,7 +1023,7 @@ int32_t lbm_batch_grid(const lbm_batch* b) { return b ? b->grid : -1; }
 
 int32_t lbm_batch_fused_grid(const lbm_batch* b) {
   if (!b) return -1;
-  if (b->fuse == kBatchK) {
+  if (b->kdepth && b->fuse == b->kdepth) {
     int64_t blocks = 0;
     for (int sh = 0; sh < kShapes; ++sh)
       if (b->countK[sh]) blocks += gridK_for(b, b->countK[sh]);
@@ -1032,8 +1057,8 @@ lbm_status lbm_batch_set_fused_grid(lbm_batch* b, int32_t blocks_per_cu) {
 lbm_status lbm_batch_set_fusion(lbm_batch* b, int32_t steps_per_launch) {
   if (!b) return LBM_EINVAL;
   if (steps_per_launch == 2 && !b->kernel2) return LBM_EINVAL;
-  if (steps_per_launch == kBatchK && !b->kernelK[0].fn) return LBM_EINVAL;
-  if (steps_per_launch != 1 && steps_per_launch != 2 && steps_per_launch != kBatchK) return LBM_EINVAL;
+  if (steps_per_launch != 1 && steps_per_launch != 2 && (steps_per_launch != b->kdepth || !b->kdepth))
+    return LBM_EINVAL;
   b->fuse = steps_per_launch;
   return LBM_OK;
 }

@@ -51,9 +51,10 @@ def _single(dim, storage, run, u0, steps):
 @pytest.mark.parametrize("storage,steps", [("f32", 73), ("f16_dev_r32", 120), ("bf16_dev", 51), ("f16_dev", 8),
                                            ("bf16_dev_r32", 17), ("f32_raw", 126)])
 def test_batch_bitwise_equals_single_runs_2d(storage, steps, fuse):
-    """Every kernel (five steps per launch, the 2D default, two or one) gives
-    each run's single-run state bit for bit; the step counts end on shorter
-    launches (73 = 14 x 5 + 2 + 1) or use the graphs of 24 launches (120, 126)."""
+    """Every kernel (five steps per launch, the 2D default for batches of
+    small runs, two or one) gives each run's single-run state bit for bit; the
+    step counts end on shorter launches (73 = 14 x 5 + 2 + 1) or use the
+    graphs of 24 launches (120, 126)."""
     runs, u0s = _mixed_runs(2)
     print(f"[batch] 2D {storage} {len(runs)} runs {steps} steps fuse={fuse}", flush=True)
     b = B.Batch.create(2, storage, runs, u0s)
@@ -116,6 +117,35 @@ def test_every_fused_grid_is_bitwise(per_cu):
     for bad in (-1, 65):
         with pytest.raises(lbm.LbmError):
             b.set_fused_grid(bad)
+    b.close()
+
+
+@pytest.mark.parametrize("storage,depth", [("f32", 6), ("f32_raw", 6), ("f16_dev_r32", 5)])
+def test_batch_depth_follows_run_sizes(storage, depth):
+    """A batch whose cells are mostly in runs of at least 2^20 cells (one
+    1024^2 run beside small ones) runs six steps per launch in the 4-byte
+    storages (32x28 tiles for the large run), five in the 16-bit ones; bit for
+    bit the single runs after 151 = 24 x 6 + 6 + 1 steps, and only 1, 2 and
+    that depth are accepted."""
+    shapes = [(1024, 1024), (64, 64), (75, 75), (130, 3)]
+    runs, u0s = [], []
+    for i, (ny, nx) in enumerate(shapes):
+        dx = 2 * math.pi / max(nx, ny)
+        runs.append(B.make_run((nx, ny), dx, dx * dx / 8, 0.01 * (1 + i)))
+        u0s.append(inputs.random_field_box((ny, nx), dx, seed=40 + i, umax=0.05 / dx))
+    print(f"[batch] depth {storage}", flush=True)
+    b = B.Batch.create(2, storage, runs, u0s)
+    assert b.fusion() == depth
+    assert b.fused_tile(0) == ((32, 28) if depth == 6 else (64, 16))
+    for bad in (3, 4, 11 - depth, 7):
+        with pytest.raises(lbm.LbmError):
+            b.set_fusion(bad)
+    b.set_fusion(depth)
+    b.step(151)
+    for r, (run, u0) in enumerate(zip(runs, u0s)):
+        rho, q = b.moments(r)
+        rho1, q1 = _single(2, storage, run, u0, 151)
+        assert np.array_equal(rho, rho1) and np.array_equal(q, q1), r
     b.close()
 
 
@@ -208,8 +238,9 @@ def test_invalid_run_reported():
 
 
 def test_full_batch_workload_sampled():
-    """The 512-run workload (sizes 64^2..1024^2, nu log-uniform): a few steps,
-    then sampled runs against the single-run engine, bitwise."""
+    """The 512-run workload (sizes 64^2..1024^2, nu log-uniform; most cells in
+    the 1024^2 runs, so six steps per launch in FP32): a few steps, then
+    sampled runs against the single-run engine, bitwise."""
     specs = inputs.batch_run_specs(512)
     runs, u0s = [], []
     for s in specs:
@@ -218,6 +249,7 @@ def test_full_batch_workload_sampled():
         runs.append(B.make_run((n, n), dx, dx * dx / 8, s["nu"]))
         u0s.append(inputs.random_field_2d(n, s["seed"], umax=0.05 / dx))
     b = B.Batch.create(2, "f32", runs, u0s)
+    assert b.fusion() == 6
     b.autotune(None)
     b.step(23)
     for r in (0, 1, 255, 511) + tuple(i for i, s in enumerate(specs) if s["n"] == 1024)[:1]:
