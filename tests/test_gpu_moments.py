@@ -184,6 +184,37 @@ def test_moments_3d_z_marching_single_step_oracle():
     assert np.max(np.abs(rho - r_ref)) <= 1e-6
 
 
+def _patch_reference(u0_full, p, centre, steps):
+    """Oracle value at `centre` after `steps` steps, from a periodic patch of
+    side 2*steps + 2 around it (information moves one cell per step)."""
+    half = steps + 1
+    idx = [np.arange(c - half, c + half) % s for c, s in zip(centre, u0_full.shape[1:])]
+    patch = u0_full[(slice(None),) + np.ix_(*idx)]
+    rho, q, _ = scheme.simulate(np.ascontiguousarray(patch), p, steps)
+    mid = (half,) * p.dim
+    return rho[mid], q[(slice(None),) + mid]
+
+
+def test_moments_3d_256_default_sampled():
+    """256^3 at the default fusion (two steps per launch: the z-marching
+    two-step kernel, 64 x 11 column tiles, one block per tile and segment):
+    sampled cells against the full-population oracle at omega = 1 on
+    domain-of-dependence patches."""
+    n, steps = 256, 16
+    p = _params(3, n, 1e-3)
+    u0 = inputs.random_field_3d(n, 0, umax=0.05 / p.dx)
+    eng = _engine(p, u0)
+    assert eng.fusion() == 2
+    eng.step(steps)
+    rho, q = eng.moments()
+    eng.close()
+    rng = np.random.default_rng(2)
+    for centre in [(0, 0, 0), (255, 3, 128), (17, 200, 63)] + [tuple(rng.integers(0, n, 3)) for _ in range(2)]:
+        r_ref, q_ref = _patch_reference(u0, p, centre, steps)
+        assert abs(rho[centre] - r_ref) <= 1e-6, centre
+        assert np.max(np.abs(q[(slice(None),) + centre] - q_ref)) <= 1e-5 * 0.05 / p.dx, centre
+
+
 def test_moments_default_fusion_large_grid_bitwise():
     """From 2^20 cells the moment-only storage runs four steps per launch by
     default: a 1100 x 1000 grid (ragged against the 64 x 32 tiles), 19 steps."""
