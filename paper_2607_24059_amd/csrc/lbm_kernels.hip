@@ -1374,9 +1374,10 @@ struct Impl {
       // 60 VGPRs) 177.5 against 172.7 after the relaxation change (640: 115);
       // K = 4: 64x16 on 512, 139.3 / 132.9 against 125.0 / 122.1; K = 3:
       // 32x16 on 256 (102.2 at 4096^2); K = 6 (the FP32 default): 32x28 on 768
-      // threads, 42x40 extended, 77 KB of LDS, two blocks per CU, 192.6 against 176.3 for
-      // K = 5 in the same session (32x24: 182.2, 32x16 on 256: 152.8, 32x28
-      // on 896 or 1024 threads: 119; K = 7 on 32x24: 191.5, K = 8 on 32x20:
+      // threads, 42x38 extended, 77 KB of LDS, two blocks per CU, 192.6 against 176.3 for
+      // K = 5 in the same session (32x24: 182.2, 32x16 on 256: 152.8, 32x16
+      // and 32x20 on 512 (three and two blocks per CU): 166, 32x28 on 832,
+      // 896 or 1024 threads: 118-120; K = 7 on 32x24: 191.5, K = 8 on 32x20:
       // 177.8; 32x32 at K = 6 needs 85 KB per block and ran 108.6)
       constexpr int TX = K == 5 ? 32 : K == 4 ? 64 : 32;
       constexpr int TY = K == 5 ? 32 : K == 6 ? 28 : 16;
